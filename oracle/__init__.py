@@ -1,0 +1,21 @@
+"""CPU oracle for DSBlockCG -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It is a plain, slow FP64 statement of what the hot path
+computes, written from the paper and sharing no code with the HIP library:
+
+  * ``wilson_oracle.c``  the Wilson-Dirac operator D, D^H, A = D^H D, the
+    neighbour table and the link derivative (C, loops over sites);
+  * ``dsbcg.py``         the deflated shifted block CG method in block form
+    (numpy), following Sec. 3 of the paper.
+
+Every function is pinned by CPU tests against facts fixed outside the oracle
+(closed forms, textbook special cases, dense solves).
+"""
+from .wilson import (apply_D, apply_A, apply_D_sites, apply_A_sites, neighbors, gamma,
+                     link_grad, max_threads, load)
+from .dsbcg import (dsbcg, deflated_qr, true_relres, NotHPD, Result)
+
+__all__ = ["apply_D", "apply_A", "apply_D_sites", "apply_A_sites", "neighbors", "gamma",
+           "link_grad", "max_threads", "load", "dsbcg", "deflated_qr", "true_relres",
+           "NotHPD", "Result"]
