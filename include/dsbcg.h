@@ -1,0 +1,158 @@
+/*
+ * dsbcg.h -- C ABI of the MI355X (gfx950) library for the deflated shifted
+ * block CG method (DSBlockCG) of Birk & Frommer, "A CG Method for Multiple
+ * Right Hand Sides and Multiple Shifts in Lattice QCD Calculations".
+ *
+ * Problem (Sec. 1, eqs. (1.1) and (1.2)): for m right-hand sides
+ * B = [b_1 | ... | b_m] and s real shifts sigma_j, solve
+ *
+ *        (sigma_j I + A) X_j = B,   j = 1..s,
+ *
+ * with A = D^H D and D the Wilson-Dirac operator on a periodic 4-d lattice
+ * (the paper names "the Wilson fermion matrix"; its conventions are fixed
+ * here):
+ *
+ *   (D psi)(x) = psi(x) - kappa sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu)
+ *                                      + (1 + g_mu) U_mu(x-mu)^H psi(x-mu) ]
+ *
+ * hermitian gamma matrices in the chiral (DeGrand-Rossi) basis, periodic
+ * boundaries, site index x + Lx*(y + Ly*(z + Lz*t)), U_mu(x) on the link
+ * x -> x+mu.
+ *
+ * Memory layouts (C order):
+ *   U   complex128 [V][4][3][3]     U[x][mu][a][b] = (U_mu(x))_{ab}
+ *   B   complex128 [V][4][3][m]     right-hand side innermost
+ *   X   complex128 [s][V][4][3][m]  one block per shift
+ * complex128 = two IEEE doubles (re, im), 16-byte aligned.
+ *
+ * All array pointers are DEVICE pointers (memory of the current HIP device)
+ * unless a comment says "host".  The caller owns every array it passes; the
+ * handle owns its neighbour geometry and a workspace that grows on demand and
+ * is freed by dsbcg_destroy.  Inputs are never modified.  Calls on one handle
+ * must not overlap; distinct handles are independent.
+ *
+ * Every call returns a dsbcg_status; on failure dsbcg_last_error() returns a
+ * message for the calling thread.
+ */
+#ifndef DSBCG_H
+#define DSBCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dsbcg_ctx *dsbcg_handle;
+typedef void *dsbcg_stream; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+    DSBCG_OK = 0,
+    DSBCG_ERR_ARG = 1,           /* bad sizes, NULL pointer, m or s out of range, tol <= 0,
+                                    non-finite sigma or kappa */
+    DSBCG_ERR_NOT_HPD = 2,       /* a shifted block Delta_{j,i} lost positive definiteness:
+                                    sigma_j I + A is not hpd (or B, U hold NaN/Inf) */
+    DSBCG_ERR_NOT_CONVERGED = 3, /* max_iters reached; X holds the current iterates */
+    DSBCG_ERR_HIP = 4,           /* HIP runtime error */
+    DSBCG_ERR_OOM = 5            /* device allocation failed */
+} dsbcg_status;
+
+typedef enum {
+    DSBCG_FP64 = 0,          /* every vector operation in FP64 */
+    DSBCG_FP32_RELIABLE = 1  /* FP32 stencil and block updates, FP64 small algebra,
+                                FP64 solution accumulation and true-residual updates */
+} dsbcg_precision;
+
+/* Largest supported number of right-hand sides and of shifts. */
+#define DSBCG_MAX_RHS 16
+#define DSBCG_MAX_SHIFTS 16
+
+typedef struct {
+    int32_t precision;    /* dsbcg_precision */
+    int32_t max_iters;    /* block-step limit of the main phase (default 10000) */
+    int32_t fixed_iters;  /* > 0: run exactly this many block steps, no convergence stop */
+    int32_t ru_interval;  /* FP32 form: reliable update every this many steps (default 50) */
+    double ru_delta;      /* FP32 form: also update when the largest estimated residual fell
+                             by this factor since the last update (default 1e-3) */
+    double tau_B;         /* initial deflation of B: drop column l when its remainder is
+                             <= tau_B * ||b_l|| (default 0.1 * tol) */
+    double tau_W;         /* in-iteration deflation: drop a new basis column whose remainder is
+                             <= tau_W * ||T||_est (default 1e-12 FP64, 1e-6 FP32) */
+    int32_t refine;       /* 1: after the main phase, re-solve systems whose true residual
+                             misses tol (default 1) */
+    int32_t freeze;       /* 1: stop updating a system once its estimate reaches tol (default 1) */
+} dsbcg_opts;
+
+typedef struct {
+    int32_t block_iters;      /* block steps of the main phase */
+    int32_t rank0;            /* width of the first Lanczos block after deflating B */
+    int32_t deflations;       /* columns dropped during the iteration */
+    int32_t reliable_updates; /* FP32 form: number of reliable updates */
+    int32_t refine_iters;     /* block steps spent in refinement solves */
+    int32_t final_width;      /* width of the last Lanczos block */
+    int64_t mvms;             /* applications of A to one vector (sum of block widths,
+                                 refinement and true-residual products included) */
+    double *est_relres;       /* host [s*m] (index j*m + l) or NULL: last estimated
+                                 relative residuals */
+    double *true_relres;      /* host [s*m] or NULL: FP64 true relative residuals
+                                 ||b_l - (sigma_j + A) x_{l,j}|| / ||b_l|| at return */
+} dsbcg_stats;
+
+/* Fill opts with the defaults listed above. */
+void dsbcg_default_opts(dsbcg_opts *opts);
+
+/* Create a handle for a lattice L = {Lx, Ly, Lz, Lt} (host array; each
+ * extent >= 2, volume < 2^31 / 12).  Binds the handle to the current device. */
+int dsbcg_create(const int32_t *L, dsbcg_handle *out);
+
+/* Release the handle and its workspace (NULL is ignored). */
+void dsbcg_destroy(dsbcg_handle h);
+
+/* Export the neighbour table the kernels use: host_out[V][8] receives the
+ * sites x+x^, x-x^, x+y^, x-y^, x+z^, x-z^, x+t^, x-t^ (host array, caller
+ * allocated).  Synchronous. */
+int dsbcg_neighbors(dsbcg_handle h, int32_t *host_out);
+
+/* Y = A X = D^H (D X) for m columns (1 <= m <= DSBCG_MAX_RHS).
+ * U, X, Y: device, layouts above (X, Y are [V][4][3][m]); Y must not alias X.
+ * precision DSBCG_FP64 computes in FP64; DSBCG_FP32_RELIABLE rounds U and X
+ * to FP32, applies the FP32 stencil and writes the FP32 result widened to
+ * FP64.  Asynchronous on `stream`. */
+int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y,
+                  int32_t m, int32_t precision, dsbcg_stream stream);
+
+/* Y = D X (dagger = 0) or D^H X (dagger = 1), FP64, same layouts as
+ * dsbcg_apply_A.  Asynchronous on `stream`. */
+int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y,
+                  int32_t m, int32_t dagger, dsbcg_stream stream);
+
+/* Solve (sigma_j I + A) X_j = B for j = 0..s-1 with DSBlockCG (Sec. 3).
+ * U, B: device inputs; sigma: HOST array of s real shifts with sigma_j I + A
+ * hpd; X: device output [s][V][4][3][m], fully written.  tol: target relative
+ * residual ||b_l - (sigma_j + A) x_{l,j}|| <= tol ||b_l|| for every (l, j)
+ * (Sec. 4).  opts may be NULL (defaults); stats may be NULL.
+ * Returns with `stream` synchronised (the iteration takes host decisions
+ * after every block step).  Zero columns of B give zero columns of X. */
+int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
+                const double *sigma, int32_t s, double tol, const dsbcg_opts *opts,
+                void *X, dsbcg_stats *stats, dsbcg_stream stream);
+
+/* Link derivative of f(U) = sum_k Re <Phi_k, D[U] Psi_k> summed over the
+ * nvec = s*m columns of Phi and Psi ([V][4][3][nvec], device), in the
+ * convention dU = df/dRe U + i df/dIm U:
+ *
+ *   dU_mu(x) = -kappa sum_{spin, k} [ ((1 - g_mu) Phi(x)) Psi(x+mu)^H
+ *                                   + Psi(x) ((1 + g_mu) Phi(x+mu))^H ]
+ *
+ * dU: device [V][4][3][3], overwritten.  FP64.  Asynchronous on `stream`. */
+int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *Psi,
+                    int32_t nvec, void *dU, dsbcg_stream stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *dsbcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSBCG_H */

@@ -1,0 +1,450 @@
+// Small FP64 algebra of DSBlockCG, on the device.
+//
+// Block form of the paper's root-free Cholesky recurrences (Sec. 3): for
+// T_sigma = sigma I + T, block tridiagonal with diagonal blocks alpha_i and
+// sub-diagonal blocks beta_{i+1},
+//   Delta_{j,1} = alpha_1 + sigma_j I
+//   N_{j,i}     = Delta_{j,i-1}^{-1} beta_i^H
+//   Delta_{j,i} = alpha_i + sigma_j I - beta_i N_{j,i}
+//   M_{j,i}     = Delta_{j,i}^{-1} Z_{j,i}
+//   Z_{j,i+1}   = -beta_{i+1} M_{j,i}  (the residual coefficients: R_j = V_{i+1} Z_{j,i+1})
+// with Z_{j,1} = rho from B = V_1 rho.  The block Lanczos basis is made
+// orthonormal by a deflated Cholesky QR applied twice.
+//
+// These matrices are at most 16 x 16; each kernel runs one or a few
+// workgroups.
+
+#include "small.hpp"
+
+namespace dsbcg {
+
+__device__ inline zd zmul(zd a, zd b) { return a * b; }
+__device__ inline zd zdivr(zd a, double r) { return mk<double>(a.x / r, a.y / r); }
+
+// Forward substitution L y = y (L lower, n x n, leading dim 16) on one column
+// held by this thread; stride gives the column's element spacing.
+__device__ inline void lower_solve(const zd *L, zd *y, int n, int stride) {
+    for (int r = 0; r < n; ++r) {
+        zd v = y[r * stride];
+        for (int c = 0; c < r; ++c) {
+            const zd l = L[r * 16 + c];
+            const zd w = y[c * stride];
+            v = v - l * w;
+        }
+        y[r * stride] = zdivr(v, L[r * 16 + r].x);
+    }
+}
+
+// Back substitution L^H y = y.
+__device__ inline void lower_h_solve(const zd *L, zd *y, int n, int stride) {
+    for (int r = n - 1; r >= 0; --r) {
+        zd v = y[r * stride];
+        for (int c = r + 1; c < n; ++c) {
+            const zd l = conj(L[c * 16 + r]);
+            v = v - l * y[c * stride];
+        }
+        y[r * stride] = zdivr(v, L[r * 16 + r].x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-shift coefficients: one 64-lane workgroup per active shift.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void shift_coeffs_kernel(SmallState *st, StepReport *rep,
+                                                          const zd *__restrict__ alpha_raw,
+                                                          int first,
+                                                          const int32_t *__restrict__ list) {
+    __shared__ zd A[256], Bt[256], Lp[256], Nn[256], D[256], Zs[256];
+    const int j = list[blockIdx.x];
+    const int t = threadIdx.x;
+    const int b = st->b, bp = st->bp, m = st->m;
+    const double sg = st->sigma[j];
+
+    (void)alpha_raw;
+    for (int e = t; e < b * b; e += 64) {
+        const int r = e / b, c = e - r * b;
+        A[r * 16 + c] = st->alpha[r * 16 + c];
+    }
+    if (!first) {
+        for (int e = t; e < b * bp; e += 64) {
+            const int r = e / bp, c = e - r * bp;
+            Bt[r * 16 + c] = st->beta[r * 16 + c];
+        }
+        for (int e = t; e < bp * bp; e += 64) {
+            const int r = e / bp, c = e - r * bp;
+            Lp[r * 16 + c] = st->L[j][r * 16 + c];
+        }
+    }
+    __syncthreads();
+
+    if (first) {
+        for (int e = t; e < b * b; e += 64) {
+            const int r = e / b, c = e - r * b;
+            zd v = A[r * 16 + c];
+            if (r == c) v.x += sg;
+            D[r * 16 + c] = v;
+        }
+    } else {
+        // N = Delta_{i-1}^{-1} beta^H: column q of beta^H per lane
+        if (t < b) {
+            for (int p = 0; p < bp; ++p) Nn[p * 16 + t] = conj(Bt[t * 16 + p]);
+            lower_solve(Lp, Nn + t, bp, 16);
+            lower_h_solve(Lp, Nn + t, bp, 16);
+        }
+        __syncthreads();
+        // Delta = alpha + sigma I - beta N
+        for (int e = t; e < b * b; e += 64) {
+            const int r = e / b, c = e - r * b;
+            zd v = A[r * 16 + c];
+            if (r == c) v.x += sg;
+            for (int p = 0; p < bp; ++p) v = v - Bt[r * 16 + p] * Nn[p * 16 + c];
+            Zs[r * 16 + c] = v;  // scratch
+        }
+        __syncthreads();
+        for (int e = t; e < b * b; e += 64) {
+            const int r = e / b, c = e - r * b;
+            const zd v = Zs[r * 16 + c], w = conj(Zs[c * 16 + r]);
+            D[r * 16 + c] = mk<double>(0.5 * (v.x + w.x), 0.5 * (v.y + w.y));
+        }
+    }
+    __syncthreads();
+
+    // Cholesky D = L L^H in place (lower triangle), right-looking.
+    bool ok = true;
+    for (int k = 0; k < b; ++k) {
+        const double d = D[k * 16 + k].x;
+        if (!(d > 0.0)) ok = false;
+        const double rd = ok ? sqrt(d) : 1.0;
+        __syncthreads();
+        if (t == 0) D[k * 16 + k] = mk<double>(rd, 0.0);
+        if (t > k && t < b) D[t * 16 + k] = zdivr(D[t * 16 + k], rd);
+        __syncthreads();
+        for (int e = t; e < b * b; e += 64) {
+            const int r = e / b, c = e - r * b;
+            if (c > k && r >= c) D[r * 16 + c] = D[r * 16 + c] - D[r * 16 + k] * conj(D[c * 16 + k]);
+        }
+        __syncthreads();
+    }
+    if (!ok) {
+        if (t == 0) atomicOr(&rep->flags, kFlagNotHPD);
+        return;
+    }
+    // keep the factor and N for the next step / the block update
+    for (int e = t; e < b * b; e += 64) {
+        const int r = e / b, c = e - r * b;
+        st->L[j][r * 16 + c] = (c <= r) ? D[r * 16 + c] : mk<double>(0, 0);
+    }
+    if (!first) {
+        for (int e = t; e < bp * b; e += 64) {
+            const int r = e / b, c = e - r * b;
+            st->N[j][r * 16 + c] = Nn[r * 16 + c];
+            st->N32[j][r * 16 + c] = cvt<float>(Nn[r * 16 + c]);
+        }
+    }
+    // M = Delta^{-1} Z: one column per lane
+    for (int e = t; e < b * m; e += 64) {
+        const int r = e / m, c = e - r * m;
+        Zs[r * 16 + c] = st->Z[j][r * 16 + c];
+    }
+    __syncthreads();
+    if (t < m) {
+        lower_solve(D, Zs + t, b, 16);
+        lower_h_solve(D, Zs + t, b, 16);
+    }
+    __syncthreads();
+    for (int e = t; e < b * m; e += 64) {
+        const int r = e / m, c = e - r * m;
+        st->M[j][r * 16 + c] = Zs[r * 16 + c];
+        st->M32[j][r * 16 + c] = cvt<float>(Zs[r * 16 + c]);
+    }
+}
+
+hipError_t small_shift_coeffs(SmallState *st, StepReport *rep, const zd *alpha_raw, int first,
+                              const int32_t *shift_list, int nact, hipStream_t stream) {
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shift_coeffs_kernel, dim3(nact), dim3(64), 0, stream, st, rep, alpha_raw,
+                       first, shift_list);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// alpha_i = herm(raw Gram); coef[1] = -alpha_i for the block combination.
+// ---------------------------------------------------------------------------
+__global__ void prep_alpha_kernel(SmallState *st, const zd *__restrict__ raw) {
+    const int b = st->b;
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        const int r = e / 16, c = e - r * 16;
+        zd h = mk<double>(0, 0);
+        if (r < b && c < b) {
+            const zd v = raw[r * 16 + c], w = conj(raw[c * 16 + r]);
+            h = mk<double>(0.5 * (v.x + w.x), 0.5 * (v.y + w.y));
+        }
+        st->alpha[e] = h;
+        st->coef[1][e] = -h;
+    }
+}
+
+hipError_t small_prep_alpha(SmallState *st, const zd *alpha_raw, hipStream_t stream) {
+    hipLaunchKernelGGL(prep_alpha_kernel, dim3(1), dim3(256), 0, stream, st, alpha_raw);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// First CholQR pass with deflation (single thread: b <= 16).
+// Column k of W is kept when the Schur remainder d_k of W^H W exceeds
+// (tau_W ||T||_est)^2; R1 gets one row per kept column.
+// ---------------------------------------------------------------------------
+__global__ void chol_deflate_kernel(SmallState *st, StepReport *rep,
+                                    const zd *__restrict__ alpha_raw, const zd *__restrict__ G,
+                                    double tau_W) {
+    if (threadIdx.x != 0) return;
+    const int b = st->b, bp = st->bp;
+    // ||T||_est from alpha_i and beta_i
+    (void)alpha_raw;
+    double na = 0.0;
+    for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) na += norm2(st->alpha[r * 16 + c]);
+    double nb = 0.0;
+    if (bp > 0)
+        for (int r = 0; r < b; ++r)
+            for (int c = 0; c < bp; ++c) nb += norm2(st->beta[r * 16 + c]);
+    double test = st->test;
+    test = fmax(test, sqrt(na));
+    test = fmax(test, sqrt(nb));
+    st->test = test;
+    const double thr = tau_W * test;
+
+    zd R[256];
+    int piv[16];
+    int nk = 0;
+    for (int k = 0; k < b; ++k) {
+        double d = G[k * 16 + k].x;
+        for (int r = 0; r < nk; ++r) {
+            zd v = G[piv[r] * 16 + k];
+            for (int q = 0; q < r; ++q) v = v - conj(R[q * 16 + piv[r]]) * R[q * 16 + k];
+            v = zdivr(v, R[r * 16 + piv[r]].x);
+            R[r * 16 + k] = v;
+            d -= norm2(v);
+        }
+        if (d > thr * thr) {
+            for (int c = 0; c < b; ++c) R[nk * 16 + c] = mk<double>(0, 0);
+            for (int q = 0; q < nk; ++q) { /* rows above keep their entries */ }
+            R[nk * 16 + k] = mk<double>(sqrt(d), 0.0);
+            piv[nk] = k;
+            ++nk;
+        } else {
+            // dropped column: its entries in the kept rows stay as computed
+        }
+    }
+    // R has nk rows; zero the entries left of each pivot
+    for (int r = 0; r < nk; ++r)
+        for (int c = 0; c < piv[r]; ++c) R[r * 16 + c] = mk<double>(0, 0);
+    for (int r = 0; r < nk; ++r)
+        for (int c = 0; c < b; ++c) st->R1[r * 16 + c] = R[r * 16 + c];
+    // C1 = E_K R_KK^{-1}: R_KK (nk x nk) is R restricted to the pivot columns
+    for (int e = 0; e < 256; ++e) st->C1[e] = mk<double>(0, 0);
+    for (int q = 0; q < nk; ++q) {
+        // column q of R_KK^{-1}: solve R_KK x = e_q (upper triangular)
+        zd x[16];
+        for (int r = nk - 1; r >= 0; --r) {
+            zd v = (r == q) ? mk<double>(1, 0) : mk<double>(0, 0);
+            for (int c = r + 1; c < nk; ++c) v = v - R[r * 16 + piv[c]] * x[c];
+            x[r] = zdivr(v, R[r * 16 + piv[r]].x);
+        }
+        for (int r = 0; r < nk; ++r) st->C1[piv[r] * 16 + q] = x[r];
+    }
+    rep->bnew = nk;
+    for (int r = 0; r < 16; ++r) rep->kept[r] = (r < nk) ? piv[r] : -1;
+}
+
+hipError_t small_chol_deflate(SmallState *st, StepReport *rep, const zd *alpha_raw, const zd *G,
+                              double tau_W, hipStream_t stream) {
+    hipLaunchKernelGGL(chol_deflate_kernel, dim3(1), dim3(64), 0, stream, st, rep, alpha_raw, G,
+                       tau_W);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Second CholQR pass, beta_{i+1}, residual coefficients and freezing.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport *rep,
+                                                     const zd *__restrict__ G2, double tol,
+                                                     int freeze, const int32_t *__restrict__ list,
+                                                     int nact) {
+    __shared__ zd R2[256], BN[256];
+    __shared__ int fail;
+    const int t = threadIdx.x;
+    const int b = st->b, m = st->m;
+    const int nk = rep->bnew;
+    if (t == 0) {
+        fail = 0;
+        // G2 = R2^H R2, R2 upper triangular (nk x nk)
+        for (int e = 0; e < 256; ++e) R2[e] = mk<double>(0, 0);
+        for (int k = 0; k < nk; ++k) {
+            double d = G2[k * 16 + k].x;
+            for (int q = 0; q < k; ++q) d -= norm2(R2[q * 16 + k]);
+            if (!(d > 0.0)) {
+                fail = 1;
+                d = 1.0;
+            }
+            const double rd = sqrt(d);
+            R2[k * 16 + k] = mk<double>(rd, 0.0);
+            for (int c = k + 1; c < nk; ++c) {
+                zd v = G2[k * 16 + c];
+                for (int q = 0; q < k; ++q) v = v - conj(R2[q * 16 + k]) * R2[q * 16 + c];
+                R2[k * 16 + c] = zdivr(v, rd);
+            }
+        }
+        if (fail) atomicOr(&rep->flags, kFlagQR2);
+        // Rinv = C1 R2^{-1}: rows of C1 solved against upper-triangular R2
+        for (int r = 0; r < b; ++r) {
+            zd x[16];
+            for (int c = 0; c < nk; ++c) {
+                zd v = st->C1[r * 16 + c];
+                for (int q = 0; q < c; ++q) v = v - x[q] * R2[q * 16 + c];
+                x[c] = zdivr(v, R2[c * 16 + c].x);
+            }
+            for (int c = 0; c < 16; ++c) st->Rinv[r * 16 + c] = (c < nk) ? x[c] : mk<double>(0, 0);
+        }
+        // beta_{i+1} = R2 R1 (nk x b)
+        for (int r = 0; r < 16; ++r)
+            for (int c = 0; c < 16; ++c) {
+                zd v = mk<double>(0, 0);
+                if (r < nk && c < b)
+                    for (int q = r; q < nk; ++q) v = v + R2[r * 16 + q] * st->R1[q * 16 + c];
+                BN[r * 16 + c] = v;
+            }
+    }
+    __syncthreads();
+    // per shift: C_j = -beta_{i+1} M_j = Z_{j,i+1}; estimates; freezing
+    for (int js = t; js < nact; js += 256) {
+        const int j = list[js];
+        uint32_t mask = rep->colmask[j];
+        for (int l = 0; l < m; ++l) {
+            double nrm = 0.0;
+            for (int r = 0; r < nk; ++r) {
+                zd v = mk<double>(0, 0);
+                for (int q = 0; q < b; ++q) v = v - BN[r * 16 + q] * st->M[j][q * 16 + l];
+                st->Z[j][r * 16 + l] = v;
+                nrm += norm2(v);
+            }
+            const double bn = st->bnorm[l];
+            const double e = (bn > 0.0) ? sqrt(nrm) / bn : 0.0;
+            rep->est[j][l] = e;
+            if (freeze && ((mask >> l) & 1u) && e <= tol) mask &= ~(1u << l);
+        }
+        rep->colmask[j] = mask;
+    }
+    __syncthreads();
+    for (int e = t; e < 256; e += 256) {
+        const int r = e / 16, c = e - r * 16;
+        st->betanext[e] = BN[e];
+        st->beta[e] = BN[e];
+        // -beta_{i+1}^H (b x bnew): coefficient of V_i in the next step
+        st->coef[0][e] = -conj(BN[c * 16 + r]);
+    }
+    if (t == 0) {
+        st->bp = b;
+        st->b = nk;
+    }
+}
+
+hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double tol, int freeze,
+                        const int32_t *shift_list, int nact, hipStream_t stream) {
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, stream, st, rep, G2, tol, freeze,
+                       shift_list, nact);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Initial deflated QR of B (classical Gram-Schmidt twice, column order).
+// ---------------------------------------------------------------------------
+__global__ void bnorms_kernel(SmallState *st, StepReport *rep, const zd *__restrict__ G, int m) {
+    if (threadIdx.x != 0) return;
+    for (int l = 0; l < m; ++l) {
+        const double v = G[l * 16 + l].x;
+        if (!isfinite(v)) rep->flags |= kFlagNonFinite;
+        st->bnorm[l] = sqrt(fmax(v, 0.0));
+    }
+    for (int e = 0; e < 256; ++e) st->rho[e] = mk<double>(0, 0);
+}
+
+hipError_t small_bnorms(SmallState *st, StepReport *rep, const zd *G, int m, hipStream_t stream) {
+    hipLaunchKernelGGL(bnorms_kernel, dim3(1), dim3(64), 0, stream, st, rep, G, m);
+    return hipGetLastError();
+}
+
+__global__ void neg_column_kernel(SmallState *st, int slot, const zd *__restrict__ src, int k) {
+    const int t = threadIdx.x;
+    if (t < 16) st->coef[slot][t * 16] = (t < k) ? -src[t * 16] : mk<double>(0, 0);
+}
+
+hipError_t small_neg_column(SmallState *st, int slot, const zd *src, int k, hipStream_t stream) {
+    hipLaunchKernelGGL(neg_column_kernel, dim3(1), dim3(64), 0, stream, st, slot, src, k);
+    return hipGetLastError();
+}
+
+__global__ void cgs_decide_kernel(SmallState *st, StepReport *rep, const zd *__restrict__ c1,
+                                  const zd *__restrict__ c2, const zd *__restrict__ nu2, int k,
+                                  int l, double tau_B) {
+    if (threadIdx.x != 0) return;
+    for (int r = 0; r < k; ++r) {
+        const zd a = c1 ? c1[r * 16] : mk<double>(0, 0);
+        const zd bb = c2 ? c2[r * 16] : mk<double>(0, 0);
+        st->rho[r * 16 + l] = a + bb;
+    }
+    const double nu = sqrt(fmax(nu2[0].x, 0.0));
+    const bool keep = nu > tau_B * st->bnorm[l];
+    if (keep) st->rho[k * 16 + l] = mk<double>(nu, 0.0);
+    st->coef[3][0] = mk<double>(keep ? 1.0 / nu : 0.0, 0.0);
+    rep->scalar[0] = nu;
+    rep->scalar[1] = keep ? 1.0 : 0.0;
+}
+
+hipError_t small_cgs_decide(SmallState *st, StepReport *rep, const zd *c1, const zd *c2,
+                            const zd *nu2, int k, int l, double tau_B, hipStream_t stream) {
+    hipLaunchKernelGGL(cgs_decide_kernel, dim3(1), dim3(64), 0, stream, st, rep, c1, c2, nu2, k, l,
+                       tau_B);
+    return hipGetLastError();
+}
+
+struct ShiftInit {
+    double sigma[kS];
+};
+
+__global__ void init_shifts_kernel(SmallState *st, StepReport *rep, int m1, int m, int s,
+                                   ShiftInit sh, int freeze, double tol) {
+    if (threadIdx.x != 0) return;
+    st->b = m1;
+    st->bp = 0;
+    st->m = m;
+    st->s = s;
+    st->test = 0.0;
+    for (int e = 0; e < 256; ++e) st->beta[e] = mk<double>(0, 0);
+    for (int j = 0; j < s; ++j) {
+        st->sigma[j] = sh.sigma[j];
+        for (int e = 0; e < 256; ++e) st->Z[j][e] = st->rho[e];
+        uint32_t mask = 0;
+        for (int l = 0; l < m; ++l) {
+            double nrm = 0.0;
+            for (int r = 0; r < m1; ++r) nrm += norm2(st->rho[r * 16 + l]);
+            const double bn = st->bnorm[l];
+            const double e = bn > 0.0 ? sqrt(nrm) / bn : 0.0;
+            rep->est[j][l] = e;
+            if (bn > 0.0 && !(freeze && e <= tol)) mask |= 1u << l;
+        }
+        rep->colmask[j] = mask;
+    }
+    rep->bnew = m1;
+}
+
+hipError_t small_init_shifts(SmallState *st, StepReport *rep, int m1, int m, int s,
+                             const double *sigma_host, int freeze, double tol, hipStream_t stream) {
+    ShiftInit sh{};
+    for (int j = 0; j < s && j < kS; ++j) sh.sigma[j] = sigma_host[j];
+    hipLaunchKernelGGL(init_shifts_kernel, dim3(1), dim3(64), 0, stream, st, rep, m1, m, s, sh,
+                       freeze, tol);
+    return hipGetLastError();
+}
+
+}  // namespace dsbcg

@@ -1,0 +1,79 @@
+// Small FP64 algebra of DSBlockCG on the device: the m x m quantities of the
+// block Lanczos process and of the per-shift root-free Cholesky recurrences.
+#pragma once
+
+#include "common.hpp"
+
+namespace dsbcg {
+
+constexpr int kS = 16;  // largest shift count / block width handled by the small kernels
+
+// Matrices are 16 x 16 row-major (leading dimension 16); only the leading
+// rows x cols part is meaningful.
+struct SmallState {
+    zd alpha[256];       // alpha_i  (b x b), hermitised
+    zd beta[256];        // beta_i   (b x bp)
+    zd betanext[256];    // beta_{i+1} (bnew x b)
+    zd R1[256];          // first-pass Cholesky factor of W^H W, kept rows (bnew x b)
+    zd C1[256];          // E_K R_KK^{-1}                       (b x bnew)
+    zd Rinv[256];        // E_K (R2 R_KK)^{-1}                   (b x bnew)
+    zd rho[256];         // R factor of the deflated QR of B     (m1 x m)
+    zd coef[4][256];     // scratch coefficient matrices for the block kernels
+    zd L[kS][256];       // per shift: Cholesky factor of Delta_{j,i} (lower, b x b)
+    zd Z[kS][256];       // per shift: Z_{j,i} (b x m)
+    zd N[kS][256];       // per shift: N_{j,i} (bp x b)
+    zd M[kS][256];       // per shift: M_{j,i} (b x m)
+    zf N32[kS][256];     // FP32 copies of N and M for the FP32 block updates
+    zf M32[kS][256];
+    double sigma[kS];
+    double bnorm[kS];    // ||b_l||
+    double test;         // running estimate of ||T||: max Frobenius norm of alpha_i, beta_i
+    int32_t b, bp, m, s;
+};
+
+// What the host reads after every block step.
+struct StepReport {
+    int32_t bnew;
+    int32_t flags;       // bit 0: Delta not positive definite, bit 1: second QR pass failed,
+                         // bit 2: non-finite input
+    int32_t kept[kS];    // pivot columns kept by the deflated QR
+    uint32_t colmask[kS];// per shift: columns still being updated
+    double est[kS][kS];  // [j][l] estimated relative residual
+    double scalar[4];    // [0]: norm of the last CGS remainder, [1]: kept flag of that column
+};
+
+enum { kFlagNotHPD = 1, kFlagQR2 = 2, kFlagNonFinite = 4 };
+
+// alpha_i = herm(raw Gram V_i^H W) into the state, and coef[1] = -alpha_i.
+hipError_t small_prep_alpha(SmallState *st, const zd *alpha_raw, hipStream_t stream);
+
+// Per-shift coefficients of step i from alpha_i (raw Gram, not yet
+// hermitised): Delta_{j,i}, its Cholesky factor, N_{j,i} and M_{j,i}.
+hipError_t small_shift_coeffs(SmallState *st, StepReport *rep, const zd *alpha_raw, int first,
+                              const int32_t *shift_list, int nact, hipStream_t stream);
+
+// First pass of the deflated CholQR of W: Cholesky of G = W^H W with column
+// dropping (remainder <= tau_W * ||T||_est); also updates ||T||_est from
+// alpha_i and beta_i.
+hipError_t small_chol_deflate(SmallState *st, StepReport *rep, const zd *alpha_raw, const zd *G,
+                              double tau_W, hipStream_t stream);
+
+// Second pass: R2 from G2 = Q1^H Q1, beta_{i+1} = R2 R1, C_j = -beta_{i+1} M_{j,i}
+// (= Z_{j,i+1}), estimated residuals and freezing; rotates b, bp.
+hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double tol, int freeze,
+                        const int32_t *shift_list, int nact, hipStream_t stream);
+
+// Initial deflated QR of B, classical Gram-Schmidt twice per column.
+// small_bnorms: ||b_l|| from the diagonal of B^H B; flags zero / non-finite columns.
+hipError_t small_bnorms(SmallState *st, StepReport *rep, const zd *G, int m, hipStream_t stream);
+// coef[slot] = -(column 0 of src) for the first k rows.
+hipError_t small_neg_column(SmallState *st, int slot, const zd *src, int k, hipStream_t stream);
+// Decide on column l: rho[0..k)[l] = c1 + c2; keep if ||w|| > tau_B ||b_l||.
+// Writes coef[3] = 1/||w|| and the decision into rep->scalar.
+hipError_t small_cgs_decide(SmallState *st, StepReport *rep, const zd *c1, const zd *c2,
+                            const zd *nu2, int k, int l, double tau_B, hipStream_t stream);
+// Initialise the per-shift state from rho: Z_{j,1} = rho, masks and estimates.
+hipError_t small_init_shifts(SmallState *st, StepReport *rep, int m1, int m, int s,
+                             const double *sigma_host, int freeze, double tol, hipStream_t stream);
+
+}  // namespace dsbcg

@@ -1,0 +1,669 @@
+// DSBlockCG driver and C ABI (see include/dsbcg.h).
+//
+// The block step (Sec. 3 of the paper, block form):
+//   W = A V_i                                   Wilson stencil D, then D^H
+//   alpha_i = herm(V_i^H (W - V_{i-1} beta_i^H)) Gram kernel
+//   per shift: Delta, N, M (small FP64 kernel); P_j, X_j updates (one kernel)
+//   W <- W - V_{i-1} beta_i^H - V_i alpha_i, G1 = W^H W
+//   deflated Cholesky QR of W, twice -> V_{i+1}, beta_{i+1}
+//   residual coefficients C_j = Z_{j,i+1}, estimates, freezing
+// The host reads one small report per step (new block width, masks,
+// estimates) and decides whether to continue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dsbcg.h"
+#include "blas.hpp"
+#include "small.hpp"
+#include "stencil.hpp"
+
+using namespace dsbcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            if (e_ == hipErrorOutOfMemory)                                                 \
+                return fail(DSBCG_ERR_OOM, std::string("out of device memory at ") + #expr); \
+            return fail(DSBCG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+        }                                                                                  \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct dsbcg_ctx {
+    Geom g{};
+    int device = 0;
+    bool lds_links = true;
+    // workspace
+    DevBuf U32, T, W, V[3], P[2], X, Bint, Q, wbuf, Rf64a, Rf64b, X32in;
+    DevBuf partials, red, list, st, rep;
+    StepReport *rep_host = nullptr;
+    int32_t *list_host = nullptr;
+    int nwg_max = 2048;
+
+    ~dsbcg_ctx() {
+        DevBuf *all[] = {&U32, &T,    &W,    &V[0], &V[1], &V[2], &P[0],   &P[1],   &X,
+                         &Bint, &Q,   &wbuf, &Rf64a, &Rf64b, &X32in, &partials, &red,
+                         &list, &st,  &rep};
+        for (DevBuf *b : all)
+            if (b->p) (void)hipFree(b->p);
+        if (rep_host) (void)hipHostFree(rep_host);
+        if (list_host) (void)hipHostFree(list_host);
+    }
+};
+
+namespace {
+
+int ensure(DevBuf &b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return DSBCG_OK;
+    if (b.p) {
+        HIPCHK(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(DSBCG_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    b.bytes = bytes;
+    return DSBCG_OK;
+}
+
+#define CHK(expr)                          \
+    do {                                   \
+        int rc_ = (expr);                  \
+        if (rc_ != DSBCG_OK) return rc_;   \
+    } while (0)
+
+int ensure_common(dsbcg_ctx *h) {
+    CHK(ensure(h->partials, (size_t)h->nwg_max * 256 * sizeof(zd)));
+    CHK(ensure(h->red, 8 * 256 * sizeof(zd)));
+    CHK(ensure(h->list, 64 * sizeof(int32_t)));
+    CHK(ensure(h->st, sizeof(SmallState)));
+    CHK(ensure(h->rep, sizeof(StepReport)));
+    if (!h->rep_host) HIPCHK(hipHostMalloc((void **)&h->rep_host, sizeof(StepReport), 0));
+    if (!h->list_host) HIPCHK(hipHostMalloc((void **)&h->list_host, 64 * sizeof(int32_t), 0));
+    return DSBCG_OK;
+}
+
+zd *red_slot(dsbcg_ctx *h, int k) { return (zd *)h->red.p + 256 * k; }
+
+// Tall-skinny combination / Gram launch.  Returns the number of workgroups
+// whose partials must be reduced.
+struct Ts {
+    dsbcg_ctx *h;
+    bool fp64;
+    hipStream_t st;
+    int64_t nrows;
+
+    int run(TsArgs a, int *nwg_out) {
+        const int TR = fp64 ? 32 : 64;
+        int64_t tiles = (nrows + TR - 1) / TR;
+        int nwg = (int)std::min<int64_t>(tiles, h->nwg_max);
+        if (nwg < 1) nwg = 1;
+        int64_t per = (tiles + nwg - 1) / nwg;
+        a.rows_per_wg = per * TR;
+        nwg = (int)((nrows + a.rows_per_wg - 1) / a.rows_per_wg);
+        if (nwg < 1) nwg = 1;
+        a.nrows = nrows;
+        a.partials = (zd *)h->partials.p;
+        HIPCHK(ts_run(fp64, a, nwg, st));
+        if (nwg_out) *nwg_out = nwg;
+        return DSBCG_OK;
+    }
+    // run + reduce of rows p < rows_used into red slot k
+    int run_reduce(TsArgs a, int rows_used, int k) {
+        int nwg = 0;
+        CHK(run(a, &nwg));
+        if (rows_used > 0) HIPCHK(reduce_partials((zd *)h->partials.p, nwg, rows_used * 16, red_slot(h, k), st));
+        return DSBCG_OK;
+    }
+};
+
+TsArgs ts_args() {
+    TsArgs a;
+    memset(&a, 0, sizeof(a));
+    return a;
+}
+
+SmallState *stp(dsbcg_ctx *h) { return (SmallState *)h->st.p; }
+StepReport *repp(dsbcg_ctx *h) { return (StepReport *)h->rep.p; }
+const zd *coef_slot(dsbcg_ctx *h, int k) { return stp(h)->coef[k]; }
+
+int read_report(dsbcg_ctx *h, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(h->rep_host, h->rep.p, sizeof(StepReport), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return DSBCG_OK;
+}
+
+int validate_geom(const int32_t *L) {
+    if (!L) return fail(DSBCG_ERR_ARG, "L is NULL");
+    int64_t V = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (L[d] < 2) return fail(DSBCG_ERR_ARG, "every lattice extent must be >= 2");
+        V *= L[d];
+    }
+    if (V * 12 >= (int64_t)1 << 31) return fail(DSBCG_ERR_ARG, "lattice volume too large");
+    return DSBCG_OK;
+}
+
+// Plane layout of an n x b block: element (x, c, r) at (c*V + x)*b + r.
+inline int64_t plane_site(int b) { return b; }
+inline int64_t plane_comp(const Geom &g, int b) { return (int64_t)g.V * b; }
+
+// Y = A X on b columns, FP64 or FP32 data; X and Y in plane layout with
+// leading dimension b, T scratch of the same shape.
+int apply_A_plane(dsbcg_ctx *h, bool fp64, const void *U, double kappa, const void *X, void *T,
+                  void *Y, int b, hipStream_t st) {
+    HIPCHK(wilson_apply(h->g, fp64, U, kappa, X, plane_site(b), plane_comp(h->g, b), T,
+                        plane_site(b), plane_comp(h->g, b), b, false, h->lds_links, st));
+    HIPCHK(wilson_apply(h->g, fp64, U, kappa, T, plane_site(b), plane_comp(h->g, b), Y,
+                        plane_site(b), plane_comp(h->g, b), b, true, h->lds_links, st));
+    return DSBCG_OK;
+}
+
+struct SolveCtx {
+    dsbcg_ctx *h;
+    hipStream_t st;
+    bool fp64;          // data precision of the iteration
+    size_t esz;         // bytes per complex element of the iteration
+    int64_t V, n;
+    int m, s;
+    const void *Ulinks; // links in the iteration precision
+    double kappa;
+    double tol;
+    dsbcg_opts o;
+};
+
+// Initial deflated QR of B (plane layout FP64, ld m): CGS2 column by column.
+// Leaves V_1 (iteration precision, ld m1) in V[0] and rho in the small state.
+int initial_qr(SolveCtx &c, int *m1_out) {
+    dsbcg_ctx *h = c.h;
+    const int m = c.m;
+    Ts ts{h, true, c.st, c.n};
+    SmallState *S = stp(h);
+    StepReport *rep = repp(h);
+    // ||b_l|| from the diagonal of B^H B
+    {
+        TsArgs a = ts_args();
+        a.K = 1;
+        a.X[0] = h->Bint.p; a.ldx[0] = m; a.bx[0] = m; a.C[0] = nullptr;
+        a.bout = m;
+        a.gram = 1;
+        CHK(ts.run_reduce(a, m, 0));
+        HIPCHK(small_bnorms(S, rep, red_slot(h, 0), m, c.st));
+    }
+    int k = 0;
+    zd *Qp = (zd *)h->Q.p;
+    zd *Bp = (zd *)h->Bint.p;
+    zd *wp = (zd *)h->wbuf.p;
+    for (int l = 0; l < m; ++l) {
+        if (k > 0) {
+            // c1 = Q^H b_l
+            TsArgs a = ts_args();
+            a.K = 1;
+            a.X[0] = Bp + l; a.ldx[0] = m; a.bx[0] = 1; a.C[0] = nullptr;
+            a.bout = 1;
+            a.gram = 2; a.L = Qp; a.ldl = m; a.bl = k;
+            CHK(ts.run_reduce(a, k, 1));
+            HIPCHK(small_neg_column(S, 0, red_slot(h, 1), k, c.st));
+            // w = b_l - Q c1, c2 = Q^H w
+            a = ts_args();
+            a.K = 2;
+            a.X[0] = Bp + l; a.ldx[0] = m; a.bx[0] = 1; a.C[0] = nullptr;
+            a.X[1] = Qp; a.ldx[1] = m; a.bx[1] = k; a.C[1] = coef_slot(h, 0);
+            a.bout = 1;
+            a.out = wp; a.ldo = 1;
+            a.gram = 2; a.L = Qp; a.ldl = m; a.bl = k;
+            CHK(ts.run_reduce(a, k, 2));
+            HIPCHK(small_neg_column(S, 1, red_slot(h, 2), k, c.st));
+            // w = w - Q c2, ||w||^2
+            a = ts_args();
+            a.K = 2;
+            a.X[0] = wp; a.ldx[0] = 1; a.bx[0] = 1; a.C[0] = nullptr;
+            a.X[1] = Qp; a.ldx[1] = m; a.bx[1] = k; a.C[1] = coef_slot(h, 1);
+            a.bout = 1;
+            a.out = wp; a.ldo = 1;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, 1, 3));
+            HIPCHK(small_cgs_decide(S, rep, red_slot(h, 1), red_slot(h, 2), red_slot(h, 3), k, l,
+                                    c.o.tau_B, c.st));
+        } else {
+            TsArgs a = ts_args();
+            a.K = 1;
+            a.X[0] = Bp + l; a.ldx[0] = m; a.bx[0] = 1; a.C[0] = nullptr;
+            a.bout = 1;
+            a.out = wp; a.ldo = 1;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, 1, 3));
+            HIPCHK(small_cgs_decide(S, rep, nullptr, nullptr, red_slot(h, 3), 0, l, c.o.tau_B, c.st));
+        }
+        CHK(read_report(h, c.st));
+        if (h->rep_host->flags & kFlagNonFinite)
+            return fail(DSBCG_ERR_NOT_HPD, "B holds non-finite values");
+        if (h->rep_host->scalar[1] > 0.5) {
+            // Q[:, k] = w / ||w||
+            TsArgs a = ts_args();
+            a.K = 1;
+            a.X[0] = wp; a.ldx[0] = 1; a.bx[0] = 1; a.C[0] = coef_slot(h, 3);
+            a.bout = 1;
+            a.out = Qp + k; a.ldo = m;
+            CHK(ts.run(a, nullptr));
+            ++k;
+        }
+    }
+    // V_1 = Q[:, :k] with leading dimension k, in the iteration precision
+    if (k > 0)
+        HIPCHK(copy_field(true, c.fp64, c.V, k, Qp, m, kPlane, 0, h->V[0].p, k, kPlane, false, 1.0,
+                          c.st));
+    *m1_out = k;
+    return DSBCG_OK;
+}
+
+int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
+    StepReport *rep = repp(h);
+    HIPCHK(hipMemsetAsync(&rep->flags, 0, sizeof(int32_t), st));
+    HIPCHK(find_nonfinite((const double *)U, (int64_t)h->g.V * 72, &rep->flags, st));
+    int32_t flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, &rep->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flag) return fail(DSBCG_ERR_NOT_HPD, "U holds non-finite values");
+    return DSBCG_OK;
+}
+
+// True relative residuals ||b_l - (sigma_j + A) x_{l,j}|| / ||b_l|| in FP64 for
+// every shift; X in API layout.
+int true_residuals(SolveCtx &c, const void *U64, const void *Bapi, const void *Xapi, const double *sigma,
+                   double *out /* host [s*m] */) {
+    dsbcg_ctx *h = c.h;
+    const int m = c.m;
+    const int64_t api_site = 12 * (int64_t)m, api_comp = m;
+    Ts ts{h, true, c.st, c.n};
+    std::vector<double> bn(m);
+    {
+        TsArgs a = ts_args();
+        a.K = 1;
+        a.X[0] = Bapi; a.ldx[0] = m; a.bx[0] = m; a.C[0] = nullptr;
+        a.bout = m;
+        a.gram = 1;
+        CHK(ts.run_reduce(a, m, 4));
+        std::vector<zd> g(256);
+        HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 4), 256 * sizeof(zd), hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        for (int l = 0; l < m; ++l) bn[l] = std::sqrt(std::max(g[l * 16 + l].x, 0.0));
+    }
+    for (int j = 0; j < c.s; ++j) {
+        const zd *Xj = (const zd *)Xapi + (int64_t)j * c.n * m;
+        HIPCHK(wilson_apply(h->g, true, U64, c.kappa, Xj, api_site, api_comp, h->Rf64a.p, api_site,
+                            api_comp, m, false, h->lds_links, c.st));
+        HIPCHK(wilson_apply(h->g, true, U64, c.kappa, h->Rf64a.p, api_site, api_comp, h->Rf64b.p,
+                            api_site, api_comp, m, true, h->lds_links, c.st));
+        TsArgs a = ts_args();
+        a.K = 3;
+        a.X[0] = Bapi; a.ldx[0] = m; a.bx[0] = m; a.C[0] = nullptr;
+        a.X[1] = Xj; a.ldx[1] = m; a.bx[1] = m; a.C[1] = coef_slot(h, 2);
+        a.X[2] = h->Rf64b.p; a.ldx[2] = m; a.bx[2] = m; a.C[2] = coef_slot(h, 3);
+        a.bout = m;
+        a.gram = 1;
+        // coefficient matrices -sigma_j I and -I
+        std::vector<zd> cf(512, mk<double>(0, 0));
+        for (int l = 0; l < m; ++l) {
+            cf[l * 16 + l] = mk<double>(-sigma[j], 0);
+            cf[256 + l * 16 + l] = mk<double>(-1.0, 0);
+        }
+        HIPCHK(hipMemcpyAsync((void *)coef_slot(h, 2), cf.data(), 512 * sizeof(zd),
+                              hipMemcpyHostToDevice, c.st));
+        CHK(ts.run_reduce(a, m, 5));
+        std::vector<zd> g(256);
+        HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 5), 256 * sizeof(zd), hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        for (int l = 0; l < m; ++l) {
+            const double r = std::sqrt(std::max(g[l * 16 + l].x, 0.0));
+            out[j * m + l] = bn[l] > 0 ? r / bn[l] : 0.0;
+        }
+    }
+    return DSBCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dsbcg_default_opts(dsbcg_opts *o) {
+    if (!o) return;
+    o->precision = DSBCG_FP64;
+    o->max_iters = 10000;
+    o->fixed_iters = 0;
+    o->ru_interval = 50;
+    o->ru_delta = 1e-3;
+    o->tau_B = -1.0;  // resolved to 0.1 * tol
+    o->tau_W = -1.0;  // resolved per precision
+    o->refine = 1;
+    o->freeze = 1;
+}
+
+const char *dsbcg_last_error(void) { return g_err.c_str(); }
+
+int dsbcg_create(const int32_t *L, dsbcg_handle *out) {
+    if (!out) return fail(DSBCG_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    CHK(validate_geom(L));
+    dsbcg_ctx *h = new (std::nothrow) dsbcg_ctx();
+    if (!h) return fail(DSBCG_ERR_OOM, "host allocation failed");
+    for (int d = 0; d < 4; ++d) h->g.L[d] = L[d];
+    h->g.V = L[0] * L[1] * L[2] * L[3];
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(DSBCG_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    const char *v = getenv("DSBCG_LDS_LINKS");
+    if (v && v[0] == '0') h->lds_links = false;
+    *out = h;
+    return DSBCG_OK;
+}
+
+void dsbcg_destroy(dsbcg_handle h) { delete h; }
+
+int dsbcg_neighbors(dsbcg_handle h, int32_t *host_out) {
+    if (!h || !host_out) return fail(DSBCG_ERR_ARG, "NULL argument");
+    int32_t *dev = nullptr;
+    const size_t bytes = (size_t)h->g.V * 8 * sizeof(int32_t);
+    HIPCHK(hipMalloc((void **)&dev, bytes));
+    hipError_t e = neighbor_table(h->g, dev, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(host_out, dev, bytes, hipMemcpyDeviceToHost);
+    (void)hipFree(dev);
+    HIPCHK(e);
+    return DSBCG_OK;
+}
+
+int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y, int32_t m,
+                  int32_t dagger, dsbcg_stream stream) {
+    if (!h || !U || !X || !Y) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
+    if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
+    if (X == Y) return fail(DSBCG_ERR_ARG, "Y must not alias X");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(wilson_apply(h->g, true, U, kappa, X, 12 * (int64_t)m, m, Y, 12 * (int64_t)m, m, m,
+                        dagger != 0, h->lds_links, st));
+    return DSBCG_OK;
+}
+
+int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y, int32_t m,
+                  int32_t precision, dsbcg_stream stream) {
+    if (!h || !U || !X || !Y) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
+    if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
+    if (X == Y) return fail(DSBCG_ERR_ARG, "Y must not alias X");
+    if (precision != DSBCG_FP64 && precision != DSBCG_FP32_RELIABLE)
+        return fail(DSBCG_ERR_ARG, "unknown precision");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t V = h->g.V, n = 12 * V;
+    const int64_t api_site = 12 * (int64_t)m, api_comp = m;
+    if (precision == DSBCG_FP64) {
+        CHK(ensure(h->T, (size_t)n * m * sizeof(zd)));
+        HIPCHK(wilson_apply(h->g, true, U, kappa, X, api_site, api_comp, h->T.p, api_site, api_comp, m,
+                            false, h->lds_links, st));
+        HIPCHK(wilson_apply(h->g, true, U, kappa, h->T.p, api_site, api_comp, Y, api_site, api_comp, m,
+                            true, h->lds_links, st));
+        return DSBCG_OK;
+    }
+    // FP32: round links and X, apply in FP32 (plane layout), widen the result
+    CHK(ensure(h->U32, (size_t)V * 36 * sizeof(zf)));
+    CHK(ensure(h->X32in, (size_t)n * m * sizeof(zf)));
+    CHK(ensure(h->T, (size_t)n * m * sizeof(zf)));
+    CHK(ensure(h->W, (size_t)n * m * sizeof(zf)));
+    // links: [V][4][3][3] has the same shape as a [V*3][.][12] field... copy flat
+    HIPCHK(copy_field(true, false, V * 3, 1, U, 1, kPlane, 0, h->U32.p, 1, kPlane, false, 1.0, st));
+    HIPCHK(copy_field(true, false, V, m, X, m, kApi, 0, h->X32in.p, m, kPlane, false, 1.0, st));
+    CHK(apply_A_plane(h, false, h->U32.p, kappa, h->X32in.p, h->T.p, h->W.p, m, st));
+    HIPCHK(copy_field(false, true, V, m, h->W.p, m, kPlane, 0, Y, m, kApi, false, 1.0, st));
+    return DSBCG_OK;
+}
+
+int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
+                const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
+                dsbcg_stats *stats, dsbcg_stream stream) {
+    if (!h || !U || !B || !sigma || !X) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
+    if (s < 1 || s > DSBCG_MAX_SHIFTS) return fail(DSBCG_ERR_ARG, "s out of range");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(DSBCG_ERR_ARG, "tol must be > 0");
+    if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
+    for (int j = 0; j < s; ++j)
+        if (!std::isfinite(sigma[j])) return fail(DSBCG_ERR_ARG, "sigma not finite");
+    dsbcg_opts o;
+    dsbcg_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.precision != DSBCG_FP64 && o.precision != DSBCG_FP32_RELIABLE)
+        return fail(DSBCG_ERR_ARG, "unknown precision");
+    if (o.tau_B < 0) o.tau_B = 0.1 * tol;
+    if (o.tau_W < 0) o.tau_W = (o.precision == DSBCG_FP64) ? 1e-12 : 1e-6;
+    if (o.max_iters < 1) o.max_iters = 1;
+    if (o.precision != DSBCG_FP64)
+        return fail(DSBCG_ERR_ARG, "the FP32 reliable-update form is not available in this build");
+
+    hipStream_t st = (hipStream_t)stream;
+    SolveCtx c;
+    c.h = h;
+    c.st = st;
+    c.fp64 = true;
+    c.esz = sizeof(zd);
+    c.V = h->g.V;
+    c.n = 12 * c.V;
+    c.m = m;
+    c.s = s;
+    c.kappa = kappa;
+    c.tol = tol;
+    c.o = o;
+    c.Ulinks = U;
+    const int64_t n = c.n;
+    const size_t blk = (size_t)n * m * c.esz;
+
+    CHK(ensure_common(h));
+    CHK(ensure(h->Bint, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->Q, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
+    for (int k = 0; k < 3; ++k) CHK(ensure(h->V[k], blk));
+    CHK(ensure(h->T, blk));
+    CHK(ensure(h->W, blk));
+    CHK(ensure(h->P[0], blk * s));
+    CHK(ensure(h->P[1], blk * s));
+    CHK(ensure(h->X, blk * s));
+    CHK(ensure(h->Rf64a, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->Rf64b, (size_t)n * m * sizeof(zd)));
+
+    SmallState *S = stp(h);
+    StepReport *rep = repp(h);
+    CHK(check_finite_links(h, U, st));
+    HIPCHK(hipMemsetAsync(rep, 0, sizeof(StepReport), st));
+    HIPCHK(hipMemsetAsync(h->X.p, 0, blk * s, st));
+    HIPCHK(copy_field(true, true, c.V, m, B, m, kApi, 0, h->Bint.p, m, kPlane, false, 1.0, st));
+
+    dsbcg_stats stt;
+    memset(&stt, 0, sizeof(stt));
+    int m1 = 0;
+    CHK(initial_qr(c, &m1));
+    stt.rank0 = m1;
+    HIPCHK(small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, st));
+    CHK(read_report(h, st));
+
+    Ts ts{h, true, st, n};
+    int b = m1, bp = 0;
+    int cur = 0, prev = 2, next = 1;
+    int pcur = 0;  // P buffer holding P_{j,i-1}
+    int status = DSBCG_OK;
+    int iters = 0;
+    const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
+    std::vector<int32_t> act;
+
+    auto active_list = [&](void) {
+        act.clear();
+        for (int j = 0; j < s; ++j)
+            if (h->rep_host->colmask[j]) act.push_back(j);
+    };
+    active_list();
+    bool done = (m1 == 0) || (act.empty() && o.fixed_iters <= 0);
+
+    for (int i = 1; !done && i <= steps; ++i) {
+        iters = i;
+        stt.mvms += b;
+        void *Vc = h->V[cur].p, *Vp = h->V[prev].p, *Vn = h->V[next].p;
+        // W = A V_i
+        CHK(apply_A_plane(h, true, U, kappa, Vc, h->T.p, h->W.p, b, st));
+        // alpha_i = V_i^H (W - V_{i-1} beta_i^H)
+        {
+            TsArgs a = ts_args();
+            a.K = (i > 1) ? 2 : 1;
+            a.X[0] = h->W.p; a.ldx[0] = b; a.bx[0] = b; a.C[0] = nullptr;
+            a.X[1] = Vp; a.ldx[1] = bp; a.bx[1] = bp; a.C[1] = coef_slot(h, 0);
+            a.bout = b;
+            a.gram = 2; a.L = Vc; a.ldl = b; a.bl = b;
+            CHK(ts.run_reduce(a, b, 0));
+        }
+        // hermitised alpha_i, -alpha_i as a coefficient
+        HIPCHK(small_prep_alpha(S, red_slot(h, 0), st));
+        // per-shift coefficients and P_j / X_j updates
+        for (size_t q = 0; q < act.size(); ++q) h->list_host[q] = act[q];
+        HIPCHK(hipMemcpyAsync(h->list.p, h->list_host, act.size() * sizeof(int32_t) + 4,
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
+                                  (int)act.size(), st));
+        if (!act.empty()) {
+            ShiftArgs sa;
+            sa.nrows = n;
+            sa.V = Vc;
+            sa.b = b;
+            sa.bp = bp;
+            sa.m = m;
+            sa.Pold = h->P[pcur].p;
+            sa.Pnew = h->P[pcur ^ 1].p;
+            sa.pstride = n * m;
+            sa.X = h->X.p;
+            sa.xstride = n * m;
+            sa.N = S->N;
+            sa.M = S->M;
+            sa.shifts = (const int32_t *)h->list.p;
+            sa.nshift = (int)act.size();
+            sa.colmask = rep->colmask;
+            sa.first = (i == 1);
+            HIPCHK(shift_update(true, sa, st));
+        }
+        // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
+        {
+            TsArgs a = ts_args();
+            a.K = (i > 1) ? 3 : 2;
+            a.X[0] = h->W.p; a.ldx[0] = b; a.bx[0] = b; a.C[0] = nullptr;
+            a.X[1] = Vc; a.ldx[1] = b; a.bx[1] = b; a.C[1] = coef_slot(h, 1);
+            a.X[2] = Vp; a.ldx[2] = bp; a.bx[2] = bp; a.C[2] = coef_slot(h, 0);
+            a.bout = b;
+            a.out = h->W.p; a.ldo = b;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, b, 1));
+        }
+        // first CholQR pass with deflation
+        HIPCHK(small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1), o.tau_W, st));
+        // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new width
+        {
+            TsArgs a = ts_args();
+            a.K = 1;
+            a.X[0] = h->W.p; a.ldx[0] = b; a.bx[0] = b; a.C[0] = S->C1;
+            a.bout = b;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, b, 2));
+        }
+        HIPCHK(small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
+                            (int)act.size(), st));
+        // V_{i+1} = W Rinv (width b, zero columns past the new width)
+        {
+            TsArgs a = ts_args();
+            a.K = 1;
+            a.X[0] = h->W.p; a.ldx[0] = b; a.bx[0] = b; a.C[0] = S->Rinv;
+            a.bout = b;
+            a.out = Vn; a.ldo = b;
+            CHK(ts.run(a, nullptr));
+        }
+        CHK(read_report(h, st));
+        const StepReport &R = *h->rep_host;
+        if (R.flags & kFlagNotHPD) {
+            status = fail(DSBCG_ERR_NOT_HPD, "shifted block lost positive definiteness at step " +
+                                                 std::to_string(i) + ": sigma_j I + A is not hpd");
+            break;
+        }
+        if (R.flags & kFlagQR2) {
+            status = fail(DSBCG_ERR_NOT_CONVERGED, "orthonormalisation of the Lanczos block failed at step " +
+                                                       std::to_string(i));
+            break;
+        }
+        const int bnew = R.bnew;
+        stt.deflations += b - bnew;
+        if (bnew > 0 && bnew < b) {
+            // compact V_{i+1} to leading dimension bnew, into the buffer of V_{i-1}
+            HIPCHK(copy_field(true, true, c.V, bnew, Vn, b, kPlane, 0, Vp, bnew, kPlane, false, 1.0, st));
+            std::swap(prev, next);
+        }
+        active_list();
+        if (bnew == 0) done = true;
+        if (o.fixed_iters <= 0 && act.empty()) done = true;
+        // rotate the three-block window
+        const int old_prev = prev;
+        prev = cur;
+        cur = next;
+        next = old_prev;
+        pcur ^= 1;
+        bp = b;
+        b = bnew;
+        stt.final_width = bnew;
+    }
+    stt.block_iters = iters;
+    if (status == DSBCG_OK && !done && o.fixed_iters <= 0) {
+        status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
+    }
+    // iterates to the caller's layout
+    for (int j = 0; j < s; ++j)
+        HIPCHK(copy_field(true, true, c.V, m, (const zd *)h->X.p + (int64_t)j * n * m, m, kPlane, 0,
+                          (zd *)X + (int64_t)j * n * m, m, kApi, false, 1.0, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (stats) {
+        if (stats->est_relres)
+            for (int j = 0; j < s; ++j)
+                for (int l = 0; l < m; ++l) stats->est_relres[j * m + l] = h->rep_host->est[j][l];
+        if (stats->true_relres && status != DSBCG_ERR_NOT_HPD)
+            CHK(true_residuals(c, U, B, X, sigma, stats->true_relres));
+        stt.est_relres = stats->est_relres;
+        stt.true_relres = stats->true_relres;
+        *stats = stt;
+    }
+    return status;
+}
+
+int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *Psi, int32_t nvec,
+                    void *dU, dsbcg_stream stream) {
+    (void)h; (void)kappa; (void)Phi; (void)Psi; (void)nvec; (void)dU; (void)stream;
+    return fail(DSBCG_ERR_ARG, "link gradient not available in this build");
+}
+
+}  // extern "C"

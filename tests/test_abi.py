@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every function include/dsbcg.h declares."""
+import ctypes
+import subprocess
+
+import pytest
+
+from paper_1205_0359_amd import _lib
+
+
+def test_header_declares_the_boundary():
+    names = _lib.header_functions()
+    for want in ("dsbcg_create", "dsbcg_destroy", "dsbcg_neighbors", "dsbcg_apply_A",
+                 "dsbcg_apply_D", "dsbcg_solve", "dsbcg_link_grad", "dsbcg_last_error",
+                 "dsbcg_default_opts"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _lib.header_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in _lib.header_functions():
+        assert name in exported, name
+
+
+def test_default_opts_and_argument_errors_without_a_device():
+    o = _lib.default_opts()
+    assert o.precision == 0 and o.max_iters == 10000 and o.ru_interval == 50
+    assert o.refine == 1 and o.freeze == 1
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    bad = (ctypes.c_int32 * 4)(4, 4, 1, 4)
+    assert lib.dsbcg_create(bad, ctypes.byref(h)) == _lib.DSBCG_ERR_ARG
+    assert b"extent" in lib.dsbcg_last_error()
+    assert lib.dsbcg_create(None, ctypes.byref(h)) == _lib.DSBCG_ERR_ARG
+
+
+def test_opts_struct_matches_header_layout():
+    # sizes of the C structs as the header lays them out on x86-64
+    assert ctypes.sizeof(_lib.dsbcg_opts) == 48
+    assert ctypes.sizeof(_lib.dsbcg_stats) == 48

@@ -1,0 +1,185 @@
+"""DSBlockCG on the GPU against the CPU oracle.
+
+FP64 form: iterate parity at a fixed number of block steps (<= 1e-10, expected
+~1e-13), convergence to relative residual 1e-10 matching dense solves and the
+oracle, deflation of duplicated right-hand sides, zero columns, the error
+paths, determinism and the extreme sizes (m = s = 1, m = s = 16)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1205_0359_amd import inputs
+import paper_1205_0359_amd as dsb
+
+from gpu_util import announce, dev, host, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(L, U, kappa):
+    V = int(np.prod(L))
+
+    def f(Y):
+        return oracle.apply_A(L, U, kappa, np.ascontiguousarray(Y).reshape(V, 4, 3, -1)).reshape(12 * V, -1)
+    return f
+
+
+def _problem(L, m, seed, kind="haar", rhs="gaussian"):
+    V = int(np.prod(L))
+    U = inputs.make_links(L, kind, inputs.rng_for(seed, 0))
+    if rhs == "deflating":
+        B = inputs.deflating_rhs(inputs.rng_for(seed, 1), inputs.rng_for(seed, 2), V)
+    else:
+        B = inputs.make_rhs(rhs, V, m, inputs.rng_for(seed, 1))
+    return U, B
+
+
+def _gpu_solve(L, U, kappa, B, sig, tol, **kw):
+    h = dsb.Handle(L)
+    X, st = dsb.dsbcg_solve(h, dev(U), kappa, dev(B), sig, tol, **kw)
+    return host(X), st
+
+
+@pytest.mark.parametrize("L,m,sig,k,kind", [
+    ((4, 4, 4, 4), 4, (1e-3, 1e-2, 1e-1), 12, "haar"),
+    ((3, 4, 5, 6), 5, (1e-4, 0.3, 2.0, 0.05), 9, "smooth"),
+    ((8, 6, 4, 10), 12, (1e-2,), 6, "haar"),
+    ((4, 4, 4, 4), 1, (1e-3, 1e-1), 20, "smooth"),
+])
+def test_fixed_iteration_parity_fp64(L, m, sig, k, kind):
+    announce("solve fixed", L, m, sig, k)
+    kappa = 0.124
+    U, B = _problem(L, m, 800 + m, kind)
+    n = 12 * int(np.prod(L))
+    ref = oracle.dsbcg(_op(L, U, kappa), B.reshape(n, m), sig, 1e-30, fixed_iters=k)
+    X, st = _gpu_solve(L, U, kappa, B, sig, 1e-30, fixed_iters=k)
+    assert st["block_iters"] == ref.iters and st["rank0"] == ref.rank0
+    for j in range(len(sig)):
+        got = X[j].reshape(n, m)
+        assert rel_fro(got, ref.X[j]) <= 1e-10, j
+    np.testing.assert_allclose(st["est_relres"], ref.est, rtol=1e-8, atol=1e-14)
+
+
+def test_converges_to_dense_solution_4x4x4x4():
+    w = inputs.WORKLOADS["haar4^4_m4_s3"]
+    announce("solve converge", w.name)
+    U, B = w.make()
+    n, m = w.n, w.m
+    op = _op(w.L, U, w.kappa)
+    X, st = _gpu_solve(w.L, U, w.kappa, B, w.shifts, w.tol)
+    assert st["status"] == "OK"
+    Xs = X.reshape(len(w.shifts), n, m)
+    tr = oracle.true_relres(op, B.reshape(n, m), w.shifts, Xs)
+    assert tr.max() <= w.tol
+    np.testing.assert_allclose(st["true_relres"], tr, rtol=1e-6, atol=1e-15)
+    A = op(np.eye(n, dtype=complex))
+    ev = np.linalg.eigvalsh(A)
+    ref = oracle.dsbcg(op, B.reshape(n, m), w.shifts, w.tol)
+    assert abs(st["block_iters"] - ref.iters) <= 1
+    for j, sg in enumerate(w.shifts):
+        dense = np.linalg.solve(A + sg * np.eye(n), B.reshape(n, m))
+        cond = (ev[-1] + sg) / (ev[0] + sg)
+        assert rel_fro(Xs[j], dense) <= cond * w.tol
+        assert rel_fro(Xs[j], ref.X[j]) <= 2 * cond * w.tol
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (4, 4, 6, 8)])
+def test_deflation_of_duplicated_columns(L):
+    announce("solve deflating", L)
+    kappa = 0.124
+    U, B = _problem(L, 8, 830, "haar", "deflating")
+    sig = tuple(np.logspace(-5, 0, 10))
+    X, st = _gpu_solve(L, U, kappa, B, sig, 1e-10)
+    assert st["rank0"] == 5 and st["status"] == "OK"
+    assert st["true_relres"].max() <= 1e-10
+    n = 12 * int(np.prod(L))
+    tr = oracle.true_relres(_op(L, U, kappa), B.reshape(n, 8), sig, X.reshape(len(sig), n, 8))
+    assert tr.max() <= 1e-10
+    scale = np.abs(X).max()
+    assert np.abs(X[..., 2] - X[..., 0]).max() <= 1e-13 * scale
+    assert np.abs(X[..., 5] - X[..., 1]).max() <= 1e-13 * scale
+    assert np.abs(X[..., 7] - X[..., 4]).max() <= 1e-9 * scale
+
+
+def test_zero_columns_and_zero_rhs():
+    L = (4, 4, 4, 4)
+    announce("solve zero columns", L)
+    U, B = _problem(L, 4, 840)
+    B[..., 2] = 0
+    X, st = _gpu_solve(L, U, 0.12, B, (1e-2, 1.0), 1e-10)
+    assert st["rank0"] == 3
+    assert np.all(X[..., 2] == 0)
+    assert st["true_relres"][[0, 1, 3]].max() <= 1e-10
+    X0, st0 = _gpu_solve(L, U, 0.12, np.zeros_like(B), (1e-2, 1.0), 1e-10)
+    assert np.all(X0 == 0) and st0["block_iters"] == 0 and st0["rank0"] == 0
+
+
+def test_not_hpd_and_not_converged():
+    L = (4, 4, 4, 4)
+    announce("solve error paths", L)
+    U, B = _problem(L, 4, 850)
+    with pytest.raises(dsb.NotHPDError):
+        _gpu_solve(L, U, 0.12, B, (0.1, -10.0), 1e-10)
+    h = dsb.Handle(L)
+    X, st = dsb.dsbcg_solve(h, dev(U), 0.12, dev(B), (1e-2,), 1e-10, max_iters=3,
+                            raise_not_converged=False)
+    assert st["status"] == "ERR_NOT_CONVERGED" and st["block_iters"] == 3
+    n = 12 * 256
+    ref = oracle.dsbcg(_op(L, U, 0.12), B.reshape(n, 4), (1e-2,), 1e-10, fixed_iters=3)
+    assert rel_fro(host(X)[0].reshape(n, 4), ref.X[0]) <= 1e-11
+    with pytest.raises(dsb.NotConvergedError):
+        dsb.dsbcg_solve(h, dev(U), 0.12, dev(B), (1e-2,), 1e-10, max_iters=3)
+    with pytest.raises(dsb.DSBCGError):
+        dsb.dsbcg_solve(h, dev(U), 0.12, dev(B), (float("inf"),), 1e-10)
+    with pytest.raises(dsb.DSBCGError):
+        dsb.dsbcg_solve(h, dev(U), 0.12, dev(B), (1e-2,), 0.0)
+    Un = U.copy()
+    Un[3, 1, 0, 0] = np.nan
+    with pytest.raises(dsb.NotHPDError):
+        dsb.dsbcg_solve(h, dev(Un), 0.12, dev(B), (1e-2,), 1e-10)
+    Bn = B.copy()
+    Bn[7, 0, 0, 1] = np.inf
+    with pytest.raises(dsb.NotHPDError):
+        dsb.dsbcg_solve(h, dev(U), 0.12, dev(Bn), (1e-2,), 1e-10)
+
+
+def test_solve_repeatable_bitwise():
+    L = (4, 4, 6, 8)
+    announce("solve repeat", L)
+    U, B = _problem(L, 6, 860, "smooth")
+    h = dsb.Handle(L)
+    dU, dB = dev(U), dev(B)
+    X1, s1 = dsb.dsbcg_solve(h, dU, 0.125, dB, (1e-3, 1e-1), 1e-10)
+    X2, s2 = dsb.dsbcg_solve(h, dU, 0.125, dB, (1e-3, 1e-1), 1e-10)
+    assert np.array_equal(host(X1), host(X2)) and s1["block_iters"] == s2["block_iters"]
+
+
+@pytest.mark.parametrize("m,s", [(1, 1), (16, 16)])
+def test_extreme_widths(m, s):
+    L = (2, 2, 4, 4)
+    announce("solve extreme widths", L, m, s)
+    U, B = _problem(L, m, 870 + m, "smooth")
+    sig = tuple(np.logspace(-3, 0, s))
+    X, st = _gpu_solve(L, U, 0.125, B, sig, 1e-10)
+    n = 12 * int(np.prod(L))
+    tr = oracle.true_relres(_op(L, U, 0.125), B.reshape(n, m), sig, X.reshape(s, n, m))
+    assert tr.max() <= 1e-10
+    ref = oracle.dsbcg(_op(L, U, 0.125), B.reshape(n, m), sig, 1e-10)
+    for j in range(s):
+        assert rel_fro(X[j].reshape(n, m), ref.X[j]) <= 1e-6
+
+
+def test_full_size_fp64_16x16x16x16():
+    """The 16^4 smooth-link workload in FP64: every (l, j) converged to 1e-10; the
+    oracle recomputes the residual of the two extreme shifts."""
+    w = inputs.WORKLOADS["smooth16^4_m12_s8"]
+    announce("solve full size", w.name)
+    U, B = w.make()
+    X, st = _gpu_solve(w.L, U, w.kappa, B, w.shifts, w.tol)
+    assert st["status"] == "OK"
+    assert st["true_relres"].max() <= w.tol
+    op = _op(w.L, U, w.kappa)
+    for j in (0, len(w.shifts) - 1):
+        tr = oracle.true_relres(op, B.reshape(w.n, w.m), [w.shifts[j]], X[j].reshape(1, w.n, w.m))
+        assert tr.max() <= w.tol
+        np.testing.assert_allclose(tr[:, 0], st["true_relres"][:, j], rtol=1e-5)
