@@ -68,6 +68,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1205_0359_amd/build.py "
                            "(there is no CPU fallback)")
+    # PyTorch ships its own HIP runtime (same soname as the system one).  Load
+    # it first so that the library binds to that copy: two HIP runtimes in one
+    # process cannot share the device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     lib.dsbcg_default_opts.argtypes = [ctypes.POINTER(dsbcg_opts)]

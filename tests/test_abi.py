@@ -42,3 +42,13 @@ def test_opts_struct_matches_header_layout():
     # sizes of the C structs as the header lays them out on x86-64
     assert ctypes.sizeof(_lib.dsbcg_opts) == 48
     assert ctypes.sizeof(_lib.dsbcg_stats) == 48
+
+
+def test_single_hip_runtime_in_process():
+    # the library must bind to the HIP runtime PyTorch already loaded: two
+    # runtimes in one process cannot both open the device
+    _lib.load()
+    maps = open("/proc/self/maps").read().splitlines()
+    hip = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    hsa = {ln.split()[-1] for ln in maps if "libhsa-runtime64" in ln}
+    assert len(hip) == 1 and len(hsa) <= 1, (hip, hsa)
