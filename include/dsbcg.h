@@ -148,6 +148,20 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
 int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *Psi,
                     int32_t nvec, void *dU, dsbcg_stream stream);
 
+/* Kernel timing.  While enabled, every kernel the calls on h launch is
+ * bracketed by two HIP events on the call's stream (this adds a few
+ * microseconds per launch); durations and algorithmic bytes (the data each
+ * kernel must read and write, not cache traffic) accumulate per kernel class.
+ * dsbcg_profile_enable resets the totals.  Classes: 0 Wilson stencil pass
+ * (D or D^H), 1 block Gram / combination kernels, 2 per-shift P_j / X_j
+ * update, 3 small FP64 algebra and Gram reductions, 4 conversions.
+ * dsbcg_profile_read waits for the recorded events; any pointer may be NULL. */
+int dsbcg_profile_enable(dsbcg_handle h, int32_t enable);
+int dsbcg_profile_read(dsbcg_handle h, int32_t kclass, double *ms, int64_t *launches,
+                       double *bytes);
+/* Name of a kernel class, NULL past the last one. */
+const char *dsbcg_profile_name(int32_t kclass);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *dsbcg_last_error(void);
 

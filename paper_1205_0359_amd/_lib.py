@@ -91,6 +91,13 @@ def load():
     lib.dsbcg_solve.restype = ctypes.c_int
     lib.dsbcg_link_grad.argtypes = [P, dbl, P, P, i32, P, P]
     lib.dsbcg_link_grad.restype = ctypes.c_int
+    lib.dsbcg_profile_enable.argtypes = [P, i32]
+    lib.dsbcg_profile_enable.restype = ctypes.c_int
+    lib.dsbcg_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    lib.dsbcg_profile_read.restype = ctypes.c_int
+    lib.dsbcg_profile_name.argtypes = [i32]
+    lib.dsbcg_profile_name.restype = ctypes.c_char_p
     lib.dsbcg_last_error.argtypes = []
     lib.dsbcg_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -270,3 +277,24 @@ def dsbcg_link_grad(h: Handle, kappa: float, Phi, Psi, dU=None, stream=None):
     _check(load().dsbcg_link_grad(h.ptr, float(kappa), pPhi, pPsi, int(nvec), pdU,
                                   _stream(stream)))
     return dU
+
+
+def dsbcg_profile_enable(h: Handle, enable: bool = True):
+    """Start (and reset) or stop per-kernel-class timing with HIP events."""
+    _check(load().dsbcg_profile_enable(h.ptr, int(bool(enable))))
+
+
+def dsbcg_profile_read(h: Handle) -> dict:
+    """{class name: {"ms": total, "launches": n, "bytes": algorithmic bytes}}."""
+    lib = load()
+    out = {}
+    k = 0
+    while True:
+        name = lib.dsbcg_profile_name(k)
+        if not name:
+            break
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib.dsbcg_profile_read(h.ptr, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+        out[name.decode()] = {"ms": ms.value, "launches": int(n.value), "bytes": by.value}
+        k += 1
+    return out

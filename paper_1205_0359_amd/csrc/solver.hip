@@ -51,10 +51,34 @@ struct DevBuf {
 
 }  // namespace
 
+enum ProfClass {
+    kProfStencil = 0,   // one Wilson D or D^H pass
+    kProfBlock,         // tall-skinny combination / Gram kernels of the block step
+    kProfShift,         // fused per-shift P_j / X_j update
+    kProfSmall,         // small FP64 algebra and Gram reductions
+    kProfConvert,       // layout conversions, widening, accumulation
+    kProfClasses
+};
+const char *const kProfNames[kProfClasses] = {"wilson_stencil", "block_gram_update",
+                                              "shift_update", "small_algebra", "convert"};
+
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+};
+
 struct dsbcg_ctx {
     Geom g{};
     int device = 0;
     bool lds_links = true;
+    // kernel timing (dsbcg_profile_enable)
+    bool prof = false;
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    double prof_ms[kProfClasses] = {};
+    double prof_bytes[kProfClasses] = {};
+    int64_t prof_launches[kProfClasses] = {};
     // workspace
     DevBuf U32, T, W, V[3], P[2], X, Bint, Q, wbuf, Rf64a, Rf64b, X32in;
     DevBuf partials, red, list, st, rep;
@@ -70,6 +94,11 @@ struct dsbcg_ctx {
             if (b->p) (void)hipFree(b->p);
         if (rep_host) (void)hipHostFree(rep_host);
         if (list_host) (void)hipHostFree(list_host);
+        for (auto &r : prof_pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : prof_pool) (void)hipEventDestroy(e);
     }
 };
 
@@ -98,6 +127,83 @@ int ensure(DevBuf &b, size_t bytes) {
         int rc_ = (expr);                  \
         if (rc_ != DSBCG_OK) return rc_;   \
     } while (0)
+
+// ---- kernel timing: each profiled launch is bracketed by two events ----
+hipError_t prof_event(dsbcg_ctx *h, hipEvent_t *e) {
+    if (!h->prof_pool.empty()) {
+        *e = h->prof_pool.back();
+        h->prof_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+struct ProfToken {
+    bool on = false;
+    hipEvent_t a = nullptr;
+};
+
+ProfToken prof_begin(dsbcg_ctx *h, hipStream_t st) {
+    ProfToken t;
+    if (!h->prof) return t;
+    if (prof_event(h, &t.a) != hipSuccess) return t;
+    if (hipEventRecord(t.a, st) != hipSuccess) return t;
+    t.on = true;
+    return t;
+}
+
+hipError_t prof_end(dsbcg_ctx *h, const ProfToken &t, int cls, double bytes, hipStream_t st) {
+    if (!t.on) return hipSuccess;
+    hipEvent_t b;
+    hipError_t e = prof_event(h, &b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    if (e != hipSuccess) return e;
+    h->prof_pending.push_back({cls, t.a, b, bytes});
+    return hipSuccess;
+}
+
+// Accumulate the finished records (waits for their events).
+hipError_t prof_flush(dsbcg_ctx *h) {
+    for (auto &r : h->prof_pending) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return e;
+        h->prof_ms[r.cls] += ms;
+        h->prof_bytes[r.cls] += r.bytes;
+        h->prof_launches[r.cls] += 1;
+        h->prof_pool.push_back(r.a);
+        h->prof_pool.push_back(r.b);
+    }
+    h->prof_pending.clear();
+    return hipSuccess;
+}
+
+#define PROF_LAUNCH(h, cls, bytes, st, expr)                  \
+    do {                                                      \
+        ProfToken tok_ = prof_begin((h), (st));               \
+        HIPCHK(expr);                                         \
+        HIPCHK(prof_end((h), tok_, (cls), (bytes), (st)));    \
+    } while (0)
+
+// algorithmic bytes of one Wilson pass on nb columns: read nb spinors and
+// the links, write nb spinors
+double stencil_bytes(const Geom &g, int nb, size_t esz) {
+    return (double)g.V * (2.0 * 12 * nb + 36.0) * (double)esz;
+}
+
+double shift_bytes(const ShiftArgs &a, bool fp64) {
+    // V_i row once; per shift: P_{j,i-1} row, P_{j,i} row, X_j row read and written
+    double cols = a.b;
+    for (int js = 0; js < a.nshift; ++js) cols += (a.first ? 0 : a.bp) + a.b + 2.0 * a.m;
+    return cols * (double)a.nrows * (double)(fp64 ? sizeof(zd) : sizeof(zf));
+}
+
+double copy_bytes(int64_t V, int cols, size_t in_esz, size_t out_esz, bool accumulate) {
+    return (double)V * 12 * cols * ((double)in_esz + (accumulate ? 2.0 : 1.0) * (double)out_esz);
+}
 
 int ensure_common(dsbcg_ctx *h) {
     CHK(ensure(h->partials, (size_t)h->nwg_max * 256 * sizeof(zd)));
@@ -131,7 +237,12 @@ struct Ts {
         if (nwg < 1) nwg = 1;
         a.nrows = nrows;
         a.partials = (zd *)h->partials.p;
-        HIPCHK(ts_run(fp64, a, nwg, st));
+        double per_row = 0;
+        for (int k = 0; k < a.K; ++k) per_row += a.bx[k];
+        if (a.out) per_row += a.bout;
+        if (a.gram == 2) per_row += a.bl;
+        const double bytes = per_row * (double)nrows * (fp64 ? sizeof(zd) : sizeof(zf));
+        PROF_LAUNCH(h, kProfBlock, bytes, st, ts_run(fp64, a, nwg, st));
         if (nwg_out) *nwg_out = nwg;
         return DSBCG_OK;
     }
@@ -139,7 +250,9 @@ struct Ts {
     int run_reduce(TsArgs a, int rows_used, int k) {
         int nwg = 0;
         CHK(run(a, &nwg));
-        if (rows_used > 0) HIPCHK(reduce_partials((zd *)h->partials.p, nwg, rows_used * 16, red_slot(h, k), st));
+        if (rows_used > 0)
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        reduce_partials((zd *)h->partials.p, nwg, rows_used * 16, red_slot(h, k), st));
         return DSBCG_OK;
     }
 };
@@ -157,6 +270,7 @@ const zd *coef_slot(dsbcg_ctx *h, int k) { return stp(h)->coef[k]; }
 int read_report(dsbcg_ctx *h, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(h->rep_host, h->rep.p, sizeof(StepReport), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (h->prof_pending.size() > 4096) HIPCHK(prof_flush(h));
     return DSBCG_OK;
 }
 
@@ -179,10 +293,13 @@ inline int64_t plane_comp(const Geom &g, int b) { return (int64_t)g.V * b; }
 // leading dimension b, T scratch of the same shape.
 int apply_A_plane(dsbcg_ctx *h, bool fp64, const void *U, double kappa, const void *X, void *T,
                   void *Y, int b, hipStream_t st) {
-    HIPCHK(wilson_apply(h->g, fp64, U, kappa, X, plane_site(b), plane_comp(h->g, b), T,
-                        plane_site(b), plane_comp(h->g, b), b, false, h->lds_links, st));
-    HIPCHK(wilson_apply(h->g, fp64, U, kappa, T, plane_site(b), plane_comp(h->g, b), Y,
-                        plane_site(b), plane_comp(h->g, b), b, true, h->lds_links, st));
+    const double bytes = stencil_bytes(h->g, b, fp64 ? sizeof(zd) : sizeof(zf));
+    PROF_LAUNCH(h, kProfStencil, bytes, st,
+                wilson_apply(h->g, fp64, U, kappa, X, plane_site(b), plane_comp(h->g, b), T,
+                             plane_site(b), plane_comp(h->g, b), b, false, h->lds_links, st));
+    PROF_LAUNCH(h, kProfStencil, bytes, st,
+                wilson_apply(h->g, fp64, U, kappa, T, plane_site(b), plane_comp(h->g, b), Y,
+                             plane_site(b), plane_comp(h->g, b), b, true, h->lds_links, st));
     return DSBCG_OK;
 }
 
@@ -215,7 +332,7 @@ int initial_qr(SolveCtx &c, int *m1_out) {
         a.bout = m;
         a.gram = 1;
         CHK(ts.run_reduce(a, m, 0));
-        HIPCHK(small_bnorms(S, rep, red_slot(h, 0), m, c.st));
+        PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_bnorms(S, rep, red_slot(h, 0), m, c.st));
     }
     int k = 0;
     zd *Qp = (zd *)h->Q.p;
@@ -230,7 +347,7 @@ int initial_qr(SolveCtx &c, int *m1_out) {
             a.bout = 1;
             a.gram = 2; a.L = Qp; a.ldl = m; a.bl = k;
             CHK(ts.run_reduce(a, k, 1));
-            HIPCHK(small_neg_column(S, 0, red_slot(h, 1), k, c.st));
+            PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_neg_column(S, 0, red_slot(h, 1), k, c.st));
             // w = b_l - Q c1, c2 = Q^H w
             a = ts_args();
             a.K = 2;
@@ -240,7 +357,7 @@ int initial_qr(SolveCtx &c, int *m1_out) {
             a.out = wp; a.ldo = 1;
             a.gram = 2; a.L = Qp; a.ldl = m; a.bl = k;
             CHK(ts.run_reduce(a, k, 2));
-            HIPCHK(small_neg_column(S, 1, red_slot(h, 2), k, c.st));
+            PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_neg_column(S, 1, red_slot(h, 2), k, c.st));
             // w = w - Q c2, ||w||^2
             a = ts_args();
             a.K = 2;
@@ -250,7 +367,7 @@ int initial_qr(SolveCtx &c, int *m1_out) {
             a.out = wp; a.ldo = 1;
             a.gram = 1;
             CHK(ts.run_reduce(a, 1, 3));
-            HIPCHK(small_cgs_decide(S, rep, red_slot(h, 1), red_slot(h, 2), red_slot(h, 3), k, l,
+            PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_cgs_decide(S, rep, red_slot(h, 1), red_slot(h, 2), red_slot(h, 3), k, l,
                                     c.o.tau_B, c.st));
         } else {
             TsArgs a = ts_args();
@@ -260,7 +377,7 @@ int initial_qr(SolveCtx &c, int *m1_out) {
             a.out = wp; a.ldo = 1;
             a.gram = 1;
             CHK(ts.run_reduce(a, 1, 3));
-            HIPCHK(small_cgs_decide(S, rep, nullptr, nullptr, red_slot(h, 3), 0, l, c.o.tau_B, c.st));
+            PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_cgs_decide(S, rep, nullptr, nullptr, red_slot(h, 3), 0, l, c.o.tau_B, c.st));
         }
         CHK(read_report(h, c.st));
         if (h->rep_host->flags & kFlagNonFinite)
@@ -278,7 +395,7 @@ int initial_qr(SolveCtx &c, int *m1_out) {
     }
     // V_1 = Q[:, :k] with leading dimension k, in the iteration precision
     if (k > 0)
-        HIPCHK(copy_field(true, c.fp64, c.V, k, Qp, m, kPlane, 0, h->V[0].p, k, kPlane, false, 1.0,
+        PROF_LAUNCH(c.h, kProfConvert, copy_bytes(c.V, k, (true) ? 16 : 8, (c.fp64) ? 16 : 8, false), c.st, copy_field(true, c.fp64, c.V, k, Qp, m, kPlane, 0, h->V[0].p, k, kPlane, false, 1.0,
                           c.st));
     *m1_out = k;
     return DSBCG_OK;
@@ -287,7 +404,7 @@ int initial_qr(SolveCtx &c, int *m1_out) {
 int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
     StepReport *rep = repp(h);
     HIPCHK(hipMemsetAsync(&rep->flags, 0, sizeof(int32_t), st));
-    HIPCHK(find_nonfinite((const double *)U, (int64_t)h->g.V * 72, &rep->flags, st));
+    PROF_LAUNCH(h, kProfConvert, (double)h->g.V * 72 * 8, st, find_nonfinite((const double *)U, (int64_t)h->g.V * 72, &rep->flags, st));
     int32_t flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, &rep->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -318,10 +435,13 @@ int true_residuals(SolveCtx &c, const void *U64, const void *Bapi, const void *X
     }
     for (int j = 0; j < c.s; ++j) {
         const zd *Xj = (const zd *)Xapi + (int64_t)j * c.n * m;
-        HIPCHK(wilson_apply(h->g, true, U64, c.kappa, Xj, api_site, api_comp, h->Rf64a.p, api_site,
-                            api_comp, m, false, h->lds_links, c.st));
-        HIPCHK(wilson_apply(h->g, true, U64, c.kappa, h->Rf64a.p, api_site, api_comp, h->Rf64b.p,
-                            api_site, api_comp, m, true, h->lds_links, c.st));
+        const double sb = stencil_bytes(h->g, m, sizeof(zd));
+        PROF_LAUNCH(h, kProfStencil, sb, c.st,
+                    wilson_apply(h->g, true, U64, c.kappa, Xj, api_site, api_comp, h->Rf64a.p,
+                                 api_site, api_comp, m, false, h->lds_links, c.st));
+        PROF_LAUNCH(h, kProfStencil, sb, c.st,
+                    wilson_apply(h->g, true, U64, c.kappa, h->Rf64a.p, api_site, api_comp,
+                                 h->Rf64b.p, api_site, api_comp, m, true, h->lds_links, c.st));
         TsArgs a = ts_args();
         a.K = 3;
         a.X[0] = Bapi; a.ldx[0] = m; a.bx[0] = m; a.C[0] = nullptr;
@@ -368,6 +488,34 @@ void dsbcg_default_opts(dsbcg_opts *o) {
 
 const char *dsbcg_last_error(void) { return g_err.c_str(); }
 
+int dsbcg_profile_enable(dsbcg_handle h, int32_t enable) {
+    if (!h) return fail(DSBCG_ERR_ARG, "NULL handle");
+    HIPCHK(prof_flush(h));
+    for (int k = 0; k < kProfClasses; ++k) {
+        h->prof_ms[k] = 0;
+        h->prof_bytes[k] = 0;
+        h->prof_launches[k] = 0;
+    }
+    h->prof = enable != 0;
+    return DSBCG_OK;
+}
+
+int dsbcg_profile_read(dsbcg_handle h, int32_t kclass, double *ms, int64_t *launches,
+                       double *bytes) {
+    if (!h) return fail(DSBCG_ERR_ARG, "NULL handle");
+    if (kclass < 0 || kclass >= kProfClasses) return fail(DSBCG_ERR_ARG, "no such kernel class");
+    HIPCHK(prof_flush(h));
+    if (ms) *ms = h->prof_ms[kclass];
+    if (launches) *launches = h->prof_launches[kclass];
+    if (bytes) *bytes = h->prof_bytes[kclass];
+    return DSBCG_OK;
+}
+
+const char *dsbcg_profile_name(int32_t kclass) {
+    if (kclass < 0 || kclass >= kProfClasses) return nullptr;
+    return kProfNames[kclass];
+}
+
 int dsbcg_create(const int32_t *L, dsbcg_handle *out) {
     if (!out) return fail(DSBCG_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -408,8 +556,9 @@ int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
     if (X == Y) return fail(DSBCG_ERR_ARG, "Y must not alias X");
     hipStream_t st = (hipStream_t)stream;
-    HIPCHK(wilson_apply(h->g, true, U, kappa, X, 12 * (int64_t)m, m, Y, 12 * (int64_t)m, m, m,
-                        dagger != 0, h->lds_links, st));
+    PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, m, sizeof(zd)), st,
+                wilson_apply(h->g, true, U, kappa, X, 12 * (int64_t)m, m, Y, 12 * (int64_t)m, m, m,
+                             dagger != 0, h->lds_links, st));
     return DSBCG_OK;
 }
 
@@ -426,10 +575,13 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     const int64_t api_site = 12 * (int64_t)m, api_comp = m;
     if (precision == DSBCG_FP64) {
         CHK(ensure(h->T, (size_t)n * m * sizeof(zd)));
-        HIPCHK(wilson_apply(h->g, true, U, kappa, X, api_site, api_comp, h->T.p, api_site, api_comp, m,
-                            false, h->lds_links, st));
-        HIPCHK(wilson_apply(h->g, true, U, kappa, h->T.p, api_site, api_comp, Y, api_site, api_comp, m,
-                            true, h->lds_links, st));
+        const double sb = stencil_bytes(h->g, m, sizeof(zd));
+        PROF_LAUNCH(h, kProfStencil, sb, st,
+                    wilson_apply(h->g, true, U, kappa, X, api_site, api_comp, h->T.p, api_site,
+                                 api_comp, m, false, h->lds_links, st));
+        PROF_LAUNCH(h, kProfStencil, sb, st,
+                    wilson_apply(h->g, true, U, kappa, h->T.p, api_site, api_comp, Y, api_site,
+                                 api_comp, m, true, h->lds_links, st));
         return DSBCG_OK;
     }
     // FP32: round links and X, apply in FP32 (plane layout), widen the result
@@ -438,10 +590,10 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     CHK(ensure(h->T, (size_t)n * m * sizeof(zf)));
     CHK(ensure(h->W, (size_t)n * m * sizeof(zf)));
     // links: [V][4][3][3] has the same shape as a [V*3][.][12] field... copy flat
-    HIPCHK(copy_field(true, false, V * 3, 1, U, 1, kPlane, 0, h->U32.p, 1, kPlane, false, 1.0, st));
-    HIPCHK(copy_field(true, false, V, m, X, m, kApi, 0, h->X32in.p, m, kPlane, false, 1.0, st));
+    PROF_LAUNCH(h, kProfConvert, copy_bytes(V * 3, 1, (true) ? 16 : 8, (false) ? 16 : 8, false), st, copy_field(true, false, V * 3, 1, U, 1, kPlane, 0, h->U32.p, 1, kPlane, false, 1.0, st));
+    PROF_LAUNCH(h, kProfConvert, copy_bytes(V, m, (true) ? 16 : 8, (false) ? 16 : 8, false), st, copy_field(true, false, V, m, X, m, kApi, 0, h->X32in.p, m, kPlane, false, 1.0, st));
     CHK(apply_A_plane(h, false, h->U32.p, kappa, h->X32in.p, h->T.p, h->W.p, m, st));
-    HIPCHK(copy_field(false, true, V, m, h->W.p, m, kPlane, 0, Y, m, kApi, false, 1.0, st));
+    PROF_LAUNCH(h, kProfConvert, copy_bytes(V, m, (false) ? 16 : 8, (true) ? 16 : 8, false), st, copy_field(false, true, V, m, h->W.p, m, kPlane, 0, Y, m, kApi, false, 1.0, st));
     return DSBCG_OK;
 }
 
@@ -501,14 +653,14 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
     CHK(check_finite_links(h, U, st));
     HIPCHK(hipMemsetAsync(rep, 0, sizeof(StepReport), st));
     HIPCHK(hipMemsetAsync(h->X.p, 0, blk * s, st));
-    HIPCHK(copy_field(true, true, c.V, m, B, m, kApi, 0, h->Bint.p, m, kPlane, false, 1.0, st));
+    PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m, (true) ? 16 : 8, (true) ? 16 : 8, false), st, copy_field(true, true, c.V, m, B, m, kApi, 0, h->Bint.p, m, kPlane, false, 1.0, st));
 
     dsbcg_stats stt;
     memset(&stt, 0, sizeof(stt));
     int m1 = 0;
     CHK(initial_qr(c, &m1));
     stt.rank0 = m1;
-    HIPCHK(small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, st));
+    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, st));
     CHK(read_report(h, st));
 
     Ts ts{h, true, st, n};
@@ -545,12 +697,12 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
             CHK(ts.run_reduce(a, b, 0));
         }
         // hermitised alpha_i, -alpha_i as a coefficient
-        HIPCHK(small_prep_alpha(S, red_slot(h, 0), st));
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_prep_alpha(S, red_slot(h, 0), st));
         // per-shift coefficients and P_j / X_j updates
         for (size_t q = 0; q < act.size(); ++q) h->list_host[q] = act[q];
         HIPCHK(hipMemcpyAsync(h->list.p, h->list_host, act.size() * sizeof(int32_t) + 4,
                               hipMemcpyHostToDevice, st));
-        HIPCHK(small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
                                   (int)act.size(), st));
         if (!act.empty()) {
             ShiftArgs sa;
@@ -570,7 +722,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
             sa.nshift = (int)act.size();
             sa.colmask = rep->colmask;
             sa.first = (i == 1);
-            HIPCHK(shift_update(true, sa, st));
+            PROF_LAUNCH(h, kProfShift, shift_bytes(sa, true), st, shift_update(true, sa, st));
         }
         // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
         {
@@ -585,7 +737,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
             CHK(ts.run_reduce(a, b, 1));
         }
         // first CholQR pass with deflation
-        HIPCHK(small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1), o.tau_W, st));
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1), o.tau_W, st));
         // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new width
         {
             TsArgs a = ts_args();
@@ -595,7 +747,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
             a.gram = 1;
             CHK(ts.run_reduce(a, b, 2));
         }
-        HIPCHK(small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
                             (int)act.size(), st));
         // V_{i+1} = W Rinv (width b, zero columns past the new width)
         {
@@ -622,7 +774,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
         stt.deflations += b - bnew;
         if (bnew > 0 && bnew < b) {
             // compact V_{i+1} to leading dimension bnew, into the buffer of V_{i-1}
-            HIPCHK(copy_field(true, true, c.V, bnew, Vn, b, kPlane, 0, Vp, bnew, kPlane, false, 1.0, st));
+            PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, bnew, (true) ? 16 : 8, (true) ? 16 : 8, false), st, copy_field(true, true, c.V, bnew, Vn, b, kPlane, 0, Vp, bnew, kPlane, false, 1.0, st));
             std::swap(prev, next);
         }
         active_list();
@@ -644,7 +796,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
     }
     // iterates to the caller's layout
     for (int j = 0; j < s; ++j)
-        HIPCHK(copy_field(true, true, c.V, m, (const zd *)h->X.p + (int64_t)j * n * m, m, kPlane, 0,
+        PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m, (true) ? 16 : 8, (true) ? 16 : 8, false), st, copy_field(true, true, c.V, m, (const zd *)h->X.p + (int64_t)j * n * m, m, kPlane, 0,
                           (zd *)X + (int64_t)j * n * m, m, kApi, false, 1.0, st));
     HIPCHK(hipStreamSynchronize(st));
     if (stats) {
