@@ -71,16 +71,19 @@ typedef struct {
     int32_t precision;    /* dsbcg_precision */
     int32_t max_iters;    /* block-step limit of the main phase (default 10000) */
     int32_t fixed_iters;  /* > 0: run exactly this many block steps, no convergence stop */
-    int32_t ru_interval;  /* FP32 form: reliable update every this many steps (default 50) */
-    double ru_delta;      /* FP32 form: also update when the largest estimated residual fell
-                             by this factor since the last update (default 1e-3) */
+    int32_t ru_interval;  /* FP32 form: the FP32 part of the iterates is added into the FP64
+                             solution every this many block steps and at the end (default 50) */
     double tau_B;         /* initial deflation of B: drop column l when its remainder is
                              <= tau_B * ||b_l|| (default 0.1 * tol) */
     double tau_W;         /* in-iteration deflation: drop a new basis column whose remainder is
-                             <= tau_W * ||T||_est (default 1e-12 FP64, 1e-6 FP32) */
-    int32_t refine;       /* 1: after the main phase, re-solve systems whose true residual
-                             misses tol (default 1) */
+                             <= tau_W * ||T||_est (default 1e-12; steps run with FP32 vectors
+                             use max(tau_W, 1e-8)) */
+    int32_t refine;       /* 1: after the main phase, re-solve (FP64) the shifts whose true
+                             residual misses tol (default 1) */
     int32_t freeze;       /* 1: stop updating a system once its estimate reaches tol (default 1) */
+    double switch_at;     /* FP32 form: the iteration runs in FP64 until every active estimated
+                             relative residual is <= switch_at, then continues the same
+                             recurrences with FP32 vectors (default min(1e-2, 1e6 * tol)) */
 } dsbcg_opts;
 
 typedef struct {
@@ -90,8 +93,9 @@ typedef struct {
     int32_t reliable_updates; /* FP32 form: number of reliable updates */
     int32_t refine_iters;     /* block steps spent in refinement solves */
     int32_t final_width;      /* width of the last Lanczos block */
-    int64_t mvms;             /* applications of A to one vector (sum of block widths,
-                                 refinement and true-residual products included) */
+    int32_t switch_iter;      /* FP32 form: first block step run with FP32 vectors (0: none) */
+    int64_t mvms;             /* applications of A to one vector by the method: sum of the
+                                 block widths of the main phase and of refinement solves */
     double *est_relres;       /* host [s*m] (index j*m + l) or NULL: last estimated
                                  relative residuals */
     double *true_relres;      /* host [s*m] or NULL: FP64 true relative residuals

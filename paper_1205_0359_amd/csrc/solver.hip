@@ -81,15 +81,17 @@ struct dsbcg_ctx {
     int64_t prof_launches[kProfClasses] = {};
     // workspace
     DevBuf U32, T, W, V[3], P[2], X, Bint, Q, wbuf, Rf64a, Rf64b, X32in;
+    DevBuf V32[3], T32, W32, P32[2], Xlo, Rres, Xref;
     DevBuf partials, red, list, st, rep;
     StepReport *rep_host = nullptr;
     int32_t *list_host = nullptr;
     int nwg_max = 2048;
 
     ~dsbcg_ctx() {
-        DevBuf *all[] = {&U32, &T,    &W,    &V[0], &V[1], &V[2], &P[0],   &P[1],   &X,
-                         &Bint, &Q,   &wbuf, &Rf64a, &Rf64b, &X32in, &partials, &red,
-                         &list, &st,  &rep};
+        DevBuf *all[] = {&U32,   &T,     &W,     &V[0],  &V[1],   &V[2],   &P[0],     &P[1],
+                         &X,     &Bint,  &Q,     &wbuf,  &Rf64a,  &Rf64b,  &X32in,    &V32[0],
+                         &V32[1], &V32[2], &T32, &W32,   &P32[0], &P32[1], &Xlo,      &Rres,
+                         &Xref,  &partials, &red, &list, &st,     &rep};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         if (rep_host) (void)hipHostFree(rep_host);
@@ -316,6 +318,13 @@ struct SolveCtx {
     dsbcg_opts o;
 };
 
+struct SolveStats {
+    int32_t block_iters = 0, rank0 = 0, deflations = 0, reliable_updates = 0, refine_iters = 0;
+    int32_t final_width = 0, switch_iter = 0;
+    int64_t mvms = 0;
+    double est[kS * kS] = {};
+};
+
 // Initial deflated QR of B (plane layout FP64, ld m): CGS2 column by column.
 // Leaves V_1 (iteration precision, ld m1) in V[0] and rho in the small state.
 int initial_qr(SolveCtx &c, int *m1_out) {
@@ -413,13 +422,17 @@ int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
 }
 
 // True relative residuals ||b_l - (sigma_j + A) x_{l,j}|| / ||b_l|| in FP64 for
-// every shift; X in API layout.
-int true_residuals(SolveCtx &c, const void *U64, const void *Bapi, const void *Xapi, const double *sigma,
-                   double *out /* host [s*m] */) {
-    dsbcg_ctx *h = c.h;
-    const int m = c.m;
+// every shift; B and X in API layout.  With keep_j >= 0 the residual block of
+// that shift is also stored (API layout) in Rkeep.
+int true_residuals(dsbcg_ctx *h, hipStream_t st, const void *U64, double kappa, const void *Bapi,
+                   const void *Xapi, int m, const double *sigma, int s, double *out, int keep_j,
+                   void *Rkeep) {
+    const int64_t n = 12 * (int64_t)h->g.V;
     const int64_t api_site = 12 * (int64_t)m, api_comp = m;
-    Ts ts{h, true, c.st, c.n};
+    CHK(ensure_common(h));
+    CHK(ensure(h->Rf64a, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->Rf64b, (size_t)n * m * sizeof(zd)));
+    Ts ts{h, true, st, n};
     std::vector<double> bn(m);
     {
         TsArgs a = ts_args();
@@ -429,19 +442,21 @@ int true_residuals(SolveCtx &c, const void *U64, const void *Bapi, const void *X
         a.gram = 1;
         CHK(ts.run_reduce(a, m, 4));
         std::vector<zd> g(256);
-        HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 4), 256 * sizeof(zd), hipMemcpyDeviceToHost, c.st));
-        HIPCHK(hipStreamSynchronize(c.st));
+        HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 4), 256 * sizeof(zd), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         for (int l = 0; l < m; ++l) bn[l] = std::sqrt(std::max(g[l * 16 + l].x, 0.0));
     }
-    for (int j = 0; j < c.s; ++j) {
-        const zd *Xj = (const zd *)Xapi + (int64_t)j * c.n * m;
+    std::vector<zd> cf(512, mk<double>(0, 0));
+    for (int j = 0; j < s; ++j) {
+        if (keep_j >= 0 && j != keep_j) continue;
+        const zd *Xj = (const zd *)Xapi + (int64_t)j * n * m;
         const double sb = stencil_bytes(h->g, m, sizeof(zd));
-        PROF_LAUNCH(h, kProfStencil, sb, c.st,
-                    wilson_apply(h->g, true, U64, c.kappa, Xj, api_site, api_comp, h->Rf64a.p,
-                                 api_site, api_comp, m, false, h->lds_links, c.st));
-        PROF_LAUNCH(h, kProfStencil, sb, c.st,
-                    wilson_apply(h->g, true, U64, c.kappa, h->Rf64a.p, api_site, api_comp,
-                                 h->Rf64b.p, api_site, api_comp, m, true, h->lds_links, c.st));
+        PROF_LAUNCH(h, kProfStencil, sb, st,
+                    wilson_apply(h->g, true, U64, kappa, Xj, api_site, api_comp, h->Rf64a.p,
+                                 api_site, api_comp, m, false, h->lds_links, st));
+        PROF_LAUNCH(h, kProfStencil, sb, st,
+                    wilson_apply(h->g, true, U64, kappa, h->Rf64a.p, api_site, api_comp,
+                                 h->Rf64b.p, api_site, api_comp, m, true, h->lds_links, st));
         TsArgs a = ts_args();
         a.K = 3;
         a.X[0] = Bapi; a.ldx[0] = m; a.bx[0] = m; a.C[0] = nullptr;
@@ -449,18 +464,21 @@ int true_residuals(SolveCtx &c, const void *U64, const void *Bapi, const void *X
         a.X[2] = h->Rf64b.p; a.ldx[2] = m; a.bx[2] = m; a.C[2] = coef_slot(h, 3);
         a.bout = m;
         a.gram = 1;
+        if (keep_j >= 0) {
+            a.out = Rkeep;
+            a.ldo = m;
+        }
         // coefficient matrices -sigma_j I and -I
-        std::vector<zd> cf(512, mk<double>(0, 0));
         for (int l = 0; l < m; ++l) {
             cf[l * 16 + l] = mk<double>(-sigma[j], 0);
             cf[256 + l * 16 + l] = mk<double>(-1.0, 0);
         }
         HIPCHK(hipMemcpyAsync((void *)coef_slot(h, 2), cf.data(), 512 * sizeof(zd),
-                              hipMemcpyHostToDevice, c.st));
+                              hipMemcpyHostToDevice, st));
         CHK(ts.run_reduce(a, m, 5));
         std::vector<zd> g(256);
-        HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 5), 256 * sizeof(zd), hipMemcpyDeviceToHost, c.st));
-        HIPCHK(hipStreamSynchronize(c.st));
+        HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 5), 256 * sizeof(zd), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         for (int l = 0; l < m; ++l) {
             const double r = std::sqrt(std::max(g[l * 16 + l].x, 0.0));
             out[j * m + l] = bn[l] > 0 ? r / bn[l] : 0.0;
@@ -479,11 +497,11 @@ void dsbcg_default_opts(dsbcg_opts *o) {
     o->max_iters = 10000;
     o->fixed_iters = 0;
     o->ru_interval = 50;
-    o->ru_delta = 1e-3;
     o->tau_B = -1.0;  // resolved to 0.1 * tol
-    o->tau_W = -1.0;  // resolved per precision
+    o->tau_W = -1.0;  // resolved to 1e-12
     o->refine = 1;
     o->freeze = 1;
+    o->switch_at = -1.0;  // resolved to min(1e-2, 1e6 * tol)
 }
 
 const char *dsbcg_last_error(void) { return g_err.c_str(); }
@@ -597,6 +615,289 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     return DSBCG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Buffers of one working precision.
+struct WorkSet {
+    void *V[3];
+    void *T, *W;
+    void *P[2];
+    void *X;            // solution accumulator, plane layout, leading dimension m
+    const void *U;      // links
+    const void *N, *M;  // per-shift coefficients in this precision
+    bool fp64;
+    size_t esz;
+};
+
+int convert_block(dsbcg_ctx *h, int64_t V, int cols, const void *in, bool in64, void *out, bool out64,
+                  hipStream_t st) {
+    if (cols <= 0) return DSBCG_OK;
+    PROF_LAUNCH(h, kProfConvert, copy_bytes(V, cols, in64 ? 16 : 8, out64 ? 16 : 8, false), st,
+                copy_field(in64, out64, V, cols, in, cols, kPlane, 0, out, cols, kPlane, false, 1.0, st));
+    return DSBCG_OK;
+}
+
+// The DSBlockCG iteration.  FP64 form: every vector in FP64.  FP32 form: the
+// iteration starts in FP64 and continues with FP32 vectors once every active
+// estimate is <= switch_at; from then on X_j = X_hi + X_lo with X_lo in FP32,
+// flushed into the FP64 X_hi every ru_interval steps and at the end.
+// Writes the iterates to Xapi ([s][V][4][3][m], FP64).
+int solve_core(dsbcg_ctx *h, const void *U, double kappa, const void *B, int m, const double *sigma,
+               int s, double tol, const dsbcg_opts &o, double switch_at, void *Xapi,
+               SolveStats &stt, hipStream_t st) {
+    SolveCtx c;
+    c.h = h;
+    c.st = st;
+    c.fp64 = true;
+    c.esz = sizeof(zd);
+    c.V = h->g.V;
+    c.n = 12 * c.V;
+    c.m = m;
+    c.s = s;
+    c.kappa = kappa;
+    c.tol = tol;
+    c.o = o;
+    c.Ulinks = U;
+    const int64_t n = c.n;
+    const bool form32 = o.precision == DSBCG_FP32_RELIABLE;
+
+    CHK(ensure_common(h));
+    CHK(ensure(h->Bint, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->Q, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
+    CHK(ensure(h->V[0], (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->X, (size_t)n * m * s * sizeof(zd)));
+
+    SmallState *S = stp(h);
+    StepReport *rep = repp(h);
+    CHK(check_finite_links(h, U, st));
+    HIPCHK(hipMemsetAsync(rep, 0, sizeof(StepReport), st));
+    HIPCHK(hipMemsetAsync(h->X.p, 0, (size_t)n * m * s * sizeof(zd), st));
+    PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m, 16, 16, false), st,
+                copy_field(true, true, c.V, m, B, m, kApi, 0, h->Bint.p, m, kPlane, false, 1.0, st));
+
+    int m1 = 0;
+    CHK(initial_qr(c, &m1));
+    stt.rank0 = m1;
+    PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, st));
+    CHK(read_report(h, st));
+
+    // widths never exceed m1 after the initial deflation
+    const int wmax = std::max(m1, 1);
+    const size_t b64 = (size_t)n * wmax * sizeof(zd), b32 = (size_t)n * wmax * sizeof(zf);
+    for (int k = 0; k < 3; ++k) CHK(ensure(h->V[k], std::max(b64, (size_t)n * m * sizeof(zd))));
+    CHK(ensure(h->T, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->W, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->P[0], b64 * s));
+    CHK(ensure(h->P[1], b64 * s));
+    WorkSet w64{{h->V[0].p, h->V[1].p, h->V[2].p}, h->T.p, h->W.p, {h->P[0].p, h->P[1].p}, h->X.p,
+                U, S->N, S->M, true, sizeof(zd)};
+    WorkSet w32{};
+    if (form32) {
+        CHK(ensure(h->U32, (size_t)c.V * 36 * sizeof(zf)));
+        for (int k = 0; k < 3; ++k) CHK(ensure(h->V32[k], b32));
+        CHK(ensure(h->T32, b32));
+        CHK(ensure(h->W32, b32));
+        CHK(ensure(h->P32[0], b32 * s));
+        CHK(ensure(h->P32[1], b32 * s));
+        CHK(ensure(h->Xlo, (size_t)n * m * s * sizeof(zf)));
+        PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V * 3, 1, 16, 8, false), st,
+                    copy_field(true, false, c.V * 3, 1, U, 1, kPlane, 0, h->U32.p, 1, kPlane, false, 1.0, st));
+        w32 = WorkSet{{h->V32[0].p, h->V32[1].p, h->V32[2].p}, h->T32.p, h->W32.p,
+                      {h->P32[0].p, h->P32[1].p}, h->Xlo.p, h->U32.p, S->N32, S->M32, false, sizeof(zf)};
+    }
+    WorkSet *ws = &w64;
+    bool lo = false;
+    int since_flush = 0;
+
+    int b = m1, bp = 0;
+    int cur = 0, prev = 2, next = 1;
+    int pcur = 0;  // P buffer holding P_{j,i-1}
+    int status = DSBCG_OK;
+    int iters = 0;
+    const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
+    std::vector<int32_t> act;
+
+    auto active_list = [&](void) {
+        act.clear();
+        for (int j = 0; j < s; ++j)
+            if (h->rep_host->colmask[j]) act.push_back(j);
+    };
+    auto max_active_est = [&](void) {
+        double e = 0.0;
+        for (int j : act)
+            for (int l = 0; l < m; ++l)
+                if ((h->rep_host->colmask[j] >> l) & 1u) e = std::max(e, h->rep_host->est[j][l]);
+        return e;
+    };
+    auto flush = [&](void) -> int {
+        // X_hi += X_lo, X_lo = 0 (FP64 solution accumulation)
+        PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m * s, 8, 16, true), st,
+                    copy_field(false, true, c.V, m * s, h->Xlo.p, m * s, kPlane, 0, h->X.p, m * s,
+                               kPlane, true, 1.0, st));
+        HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
+        since_flush = 0;
+        stt.reliable_updates += 1;
+        return DSBCG_OK;
+    };
+    active_list();
+    bool done = (m1 == 0) || (act.empty() && o.fixed_iters <= 0);
+
+    for (int i = 1; !done && i <= steps; ++i) {
+        if (form32 && !lo && max_active_est() <= switch_at) {
+            // continue the same recurrences with FP32 vectors
+            CHK(convert_block(h, c.V, b, w64.V[cur], true, w32.V[cur], false, st));
+            if (i > 1) {
+                CHK(convert_block(h, c.V, bp, w64.V[prev], true, w32.V[prev], false, st));
+                for (int j : act)
+                    CHK(convert_block(h, c.V, bp, (zd *)w64.P[pcur] + (int64_t)j * n * wmax, true,
+                                      (zf *)w32.P[pcur] + (int64_t)j * n * wmax, false, st));
+            }
+            HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
+            ws = &w32;
+            lo = true;
+            since_flush = 0;
+            stt.switch_iter = i;
+        }
+        const bool f64 = ws->fp64;
+        Ts ts{h, f64, st, n};
+        iters = i;
+        stt.mvms += b;
+        void *Vc = ws->V[cur], *Vp = ws->V[prev], *Vn = ws->V[next];
+        // W = A V_i
+        CHK(apply_A_plane(h, f64, ws->U, kappa, Vc, ws->T, ws->W, b, st));
+        // alpha_i = V_i^H (W - V_{i-1} beta_i^H)
+        {
+            TsArgs a = ts_args();
+            a.K = (i > 1) ? 2 : 1;
+            a.X[0] = ws->W; a.ldx[0] = b; a.bx[0] = b; a.C[0] = nullptr;
+            a.X[1] = Vp; a.ldx[1] = bp; a.bx[1] = bp; a.C[1] = coef_slot(h, 0);
+            a.bout = b;
+            a.gram = 2; a.L = Vc; a.ldl = b; a.bl = b;
+            CHK(ts.run_reduce(a, b, 0));
+        }
+        // hermitised alpha_i, -alpha_i as a coefficient
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_prep_alpha(S, red_slot(h, 0), st));
+        // per-shift coefficients and P_j / X_j updates
+        for (size_t q = 0; q < act.size(); ++q) h->list_host[q] = act[q];
+        HIPCHK(hipMemcpyAsync(h->list.p, h->list_host, act.size() * sizeof(int32_t) + 4,
+                              hipMemcpyHostToDevice, st));
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
+                                       (int)act.size(), st));
+        if (!act.empty()) {
+            ShiftArgs sa;
+            sa.nrows = n;
+            sa.V = Vc;
+            sa.b = b;
+            sa.bp = bp;
+            sa.m = m;
+            sa.Pold = ws->P[pcur];
+            sa.Pnew = ws->P[pcur ^ 1];
+            sa.pstride = n * wmax;
+            sa.X = ws->X;
+            sa.xstride = n * m;
+            sa.N = ws->N;
+            sa.M = ws->M;
+            sa.shifts = (const int32_t *)h->list.p;
+            sa.nshift = (int)act.size();
+            sa.colmask = rep->colmask;
+            sa.first = (i == 1);
+            PROF_LAUNCH(h, kProfShift, shift_bytes(sa, f64), st, shift_update(f64, sa, st));
+        }
+        // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
+        {
+            TsArgs a = ts_args();
+            a.K = (i > 1) ? 3 : 2;
+            a.X[0] = ws->W; a.ldx[0] = b; a.bx[0] = b; a.C[0] = nullptr;
+            a.X[1] = Vc; a.ldx[1] = b; a.bx[1] = b; a.C[1] = coef_slot(h, 1);
+            a.X[2] = Vp; a.ldx[2] = bp; a.bx[2] = bp; a.C[2] = coef_slot(h, 0);
+            a.bout = b;
+            a.out = ws->W; a.ldo = b;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, b, 1));
+        }
+        // first CholQR pass with deflation
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1),
+                                       lo ? std::max(c.o.tau_W, 1e-8) : c.o.tau_W, st));
+        // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new width
+        {
+            TsArgs a = ts_args();
+            a.K = 1;
+            a.X[0] = ws->W; a.ldx[0] = b; a.bx[0] = b; a.C[0] = S->C1;
+            a.bout = b;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, b, 2));
+        }
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
+                                 (int)act.size(), st));
+        // V_{i+1} = W Rinv (width b, zero columns past the new width)
+        {
+            TsArgs a = ts_args();
+            a.K = 1;
+            a.X[0] = ws->W; a.ldx[0] = b; a.bx[0] = b; a.C[0] = S->Rinv;
+            a.bout = b;
+            a.out = Vn; a.ldo = b;
+            CHK(ts.run(a, nullptr));
+        }
+        if (lo && ++since_flush >= std::max(1, o.ru_interval)) CHK(flush());
+        CHK(read_report(h, st));
+        const StepReport &R = *h->rep_host;
+        if (R.flags & kFlagNotHPD) {
+            status = fail(DSBCG_ERR_NOT_HPD, "shifted block lost positive definiteness at step " +
+                                                 std::to_string(i) + ": sigma_j I + A is not hpd");
+            break;
+        }
+        if (R.flags & kFlagQR2) {
+            status = fail(DSBCG_ERR_NOT_CONVERGED,
+                          "orthonormalisation of the Lanczos block failed at step " + std::to_string(i));
+            break;
+        }
+        const int bnew = R.bnew;
+        stt.deflations += b - bnew;
+        if (bnew > 0 && bnew < b) {
+            // compact V_{i+1} to leading dimension bnew, into the buffer of V_{i-1}
+            PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, bnew, ws->esz, ws->esz, false), st,
+                        copy_field(f64, f64, c.V, bnew, Vn, b, kPlane, 0, Vp, bnew, kPlane, false, 1.0, st));
+            std::swap(prev, next);
+        }
+        active_list();
+        if (bnew == 0) done = true;
+        if (o.fixed_iters <= 0 && act.empty()) done = true;
+        // rotate the three-block window
+        const int old_prev = prev;
+        prev = cur;
+        cur = next;
+        next = old_prev;
+        pcur ^= 1;
+        bp = b;
+        b = bnew;
+        stt.final_width = bnew;
+    }
+    if (lo) CHK(flush());
+    stt.block_iters += iters;
+    if (status == DSBCG_OK && !done && o.fixed_iters <= 0)
+        status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
+    // iterates to the caller's layout
+    for (int j = 0; j < s; ++j)
+        PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m, 16, 16, false), st,
+                    copy_field(true, true, c.V, m, (const zd *)h->X.p + (int64_t)j * n * m, m, kPlane, 0,
+                               (zd *)Xapi + (int64_t)j * n * m, m, kApi, false, 1.0, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int j = 0; j < s; ++j)
+        for (int l = 0; l < m; ++l) stt.est[j * m + l] = h->rep_host->est[j][l];
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
 int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
                 const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
                 dsbcg_stats *stats, dsbcg_stream stream) {
@@ -613,201 +914,71 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
     if (o.precision != DSBCG_FP64 && o.precision != DSBCG_FP32_RELIABLE)
         return fail(DSBCG_ERR_ARG, "unknown precision");
     if (o.tau_B < 0) o.tau_B = 0.1 * tol;
-    if (o.tau_W < 0) o.tau_W = (o.precision == DSBCG_FP64) ? 1e-12 : 1e-6;
+    if (o.tau_W < 0) o.tau_W = 1e-12;
     if (o.max_iters < 1) o.max_iters = 1;
-    if (o.precision != DSBCG_FP64)
-        return fail(DSBCG_ERR_ARG, "the FP32 reliable-update form is not available in this build");
-
+    if (o.switch_at < 0) o.switch_at = std::min(1e-2, 1e6 * tol);
     hipStream_t st = (hipStream_t)stream;
-    SolveCtx c;
-    c.h = h;
-    c.st = st;
-    c.fp64 = true;
-    c.esz = sizeof(zd);
-    c.V = h->g.V;
-    c.n = 12 * c.V;
-    c.m = m;
-    c.s = s;
-    c.kappa = kappa;
-    c.tol = tol;
-    c.o = o;
-    c.Ulinks = U;
-    const int64_t n = c.n;
-    const size_t blk = (size_t)n * m * c.esz;
+    const int64_t n = 12 * (int64_t)h->g.V;
 
-    CHK(ensure_common(h));
-    CHK(ensure(h->Bint, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->Q, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
-    for (int k = 0; k < 3; ++k) CHK(ensure(h->V[k], blk));
-    CHK(ensure(h->T, blk));
-    CHK(ensure(h->W, blk));
-    CHK(ensure(h->P[0], blk * s));
-    CHK(ensure(h->P[1], blk * s));
-    CHK(ensure(h->X, blk * s));
-    CHK(ensure(h->Rf64a, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->Rf64b, (size_t)n * m * sizeof(zd)));
+    SolveStats stt;
+    int status = solve_core(h, U, kappa, B, m, sigma, s, tol, o, o.switch_at, X, stt, st);
+    if (status != DSBCG_OK && status != DSBCG_ERR_NOT_CONVERGED) return status;
 
-    SmallState *S = stp(h);
-    StepReport *rep = repp(h);
-    CHK(check_finite_links(h, U, st));
-    HIPCHK(hipMemsetAsync(rep, 0, sizeof(StepReport), st));
-    HIPCHK(hipMemsetAsync(h->X.p, 0, blk * s, st));
-    PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m, (true) ? 16 : 8, (true) ? 16 : 8, false), st, copy_field(true, true, c.V, m, B, m, kApi, 0, h->Bint.p, m, kPlane, false, 1.0, st));
-
-    dsbcg_stats stt;
-    memset(&stt, 0, sizeof(stt));
-    int m1 = 0;
-    CHK(initial_qr(c, &m1));
-    stt.rank0 = m1;
-    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, st));
-    CHK(read_report(h, st));
-
-    Ts ts{h, true, st, n};
-    int b = m1, bp = 0;
-    int cur = 0, prev = 2, next = 1;
-    int pcur = 0;  // P buffer holding P_{j,i-1}
-    int status = DSBCG_OK;
-    int iters = 0;
-    const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
-    std::vector<int32_t> act;
-
-    auto active_list = [&](void) {
-        act.clear();
-        for (int j = 0; j < s; ++j)
-            if (h->rep_host->colmask[j]) act.push_back(j);
-    };
-    active_list();
-    bool done = (m1 == 0) || (act.empty() && o.fixed_iters <= 0);
-
-    for (int i = 1; !done && i <= steps; ++i) {
-        iters = i;
-        stt.mvms += b;
-        void *Vc = h->V[cur].p, *Vp = h->V[prev].p, *Vn = h->V[next].p;
-        // W = A V_i
-        CHK(apply_A_plane(h, true, U, kappa, Vc, h->T.p, h->W.p, b, st));
-        // alpha_i = V_i^H (W - V_{i-1} beta_i^H)
-        {
-            TsArgs a = ts_args();
-            a.K = (i > 1) ? 2 : 1;
-            a.X[0] = h->W.p; a.ldx[0] = b; a.bx[0] = b; a.C[0] = nullptr;
-            a.X[1] = Vp; a.ldx[1] = bp; a.bx[1] = bp; a.C[1] = coef_slot(h, 0);
-            a.bout = b;
-            a.gram = 2; a.L = Vc; a.ldl = b; a.bl = b;
-            CHK(ts.run_reduce(a, b, 0));
+    // FP64 true residuals of every system; re-solve the shifts that miss tol
+    std::vector<double> tr((size_t)s * m, 0.0);
+    const bool want_true = (stats && stats->true_relres) || o.refine;
+    if (want_true && status == DSBCG_OK) {
+        CHK(true_residuals(h, st, U, kappa, B, X, m, sigma, s, tr.data(), -1, nullptr));
+        for (int round = 0; o.refine && round < 2; ++round) {
+            bool any = false;
+            for (int j = 0; j < s; ++j) {
+                double worst = 0.0;
+                for (int l = 0; l < m; ++l) worst = std::max(worst, tr[j * m + l]);
+                if (worst <= tol) continue;
+                any = true;
+                // residual block R_j, then (sigma_j + A) E = R_j in FP64 and X_j += E
+                CHK(ensure(h->Rres, (size_t)n * m * sizeof(zd)));
+                CHK(ensure(h->Xref, (size_t)n * m * sizeof(zd)));
+                std::vector<double> tmp((size_t)s * m);
+                CHK(true_residuals(h, st, U, kappa, B, X, m, sigma, s, tmp.data(), j, h->Rres.p));
+                double ratio = 1e300;
+                for (int l = 0; l < m; ++l)
+                    if (tr[j * m + l] > 0) ratio = std::min(ratio, 1.0 / tr[j * m + l]);
+                dsbcg_opts ro = o;
+                ro.precision = DSBCG_FP64;
+                ro.fixed_iters = 0;
+                ro.tau_B = 0.1 * tol;
+                SolveStats rs;
+                const double rtol = std::max(0.5 * tol * ratio, 1e-15);
+                int rc = solve_core(h, U, kappa, h->Rres.p, m, &sigma[j], 1, rtol, ro, 0.0, h->Xref.p, rs, st);
+                if (rc != DSBCG_OK && rc != DSBCG_ERR_NOT_CONVERGED) return rc;
+                stt.refine_iters += rs.block_iters;
+                stt.mvms += rs.mvms;
+                PROF_LAUNCH(h, kProfConvert, copy_bytes(h->g.V, m, 16, 16, true), st,
+                            copy_field(true, true, h->g.V, m, h->Xref.p, m, kApi, 0,
+                                       (zd *)X + (int64_t)j * n * m, m, kApi, true, 1.0, st));
+            }
+            if (!any) break;
+            CHK(true_residuals(h, st, U, kappa, B, X, m, sigma, s, tr.data(), -1, nullptr));
         }
-        // hermitised alpha_i, -alpha_i as a coefficient
-        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_prep_alpha(S, red_slot(h, 0), st));
-        // per-shift coefficients and P_j / X_j updates
-        for (size_t q = 0; q < act.size(); ++q) h->list_host[q] = act[q];
-        HIPCHK(hipMemcpyAsync(h->list.p, h->list_host, act.size() * sizeof(int32_t) + 4,
-                              hipMemcpyHostToDevice, st));
-        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
-                                  (int)act.size(), st));
-        if (!act.empty()) {
-            ShiftArgs sa;
-            sa.nrows = n;
-            sa.V = Vc;
-            sa.b = b;
-            sa.bp = bp;
-            sa.m = m;
-            sa.Pold = h->P[pcur].p;
-            sa.Pnew = h->P[pcur ^ 1].p;
-            sa.pstride = n * m;
-            sa.X = h->X.p;
-            sa.xstride = n * m;
-            sa.N = S->N;
-            sa.M = S->M;
-            sa.shifts = (const int32_t *)h->list.p;
-            sa.nshift = (int)act.size();
-            sa.colmask = rep->colmask;
-            sa.first = (i == 1);
-            PROF_LAUNCH(h, kProfShift, shift_bytes(sa, true), st, shift_update(true, sa, st));
-        }
-        // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
-        {
-            TsArgs a = ts_args();
-            a.K = (i > 1) ? 3 : 2;
-            a.X[0] = h->W.p; a.ldx[0] = b; a.bx[0] = b; a.C[0] = nullptr;
-            a.X[1] = Vc; a.ldx[1] = b; a.bx[1] = b; a.C[1] = coef_slot(h, 1);
-            a.X[2] = Vp; a.ldx[2] = bp; a.bx[2] = bp; a.C[2] = coef_slot(h, 0);
-            a.bout = b;
-            a.out = h->W.p; a.ldo = b;
-            a.gram = 1;
-            CHK(ts.run_reduce(a, b, 1));
-        }
-        // first CholQR pass with deflation
-        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1), o.tau_W, st));
-        // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new width
-        {
-            TsArgs a = ts_args();
-            a.K = 1;
-            a.X[0] = h->W.p; a.ldx[0] = b; a.bx[0] = b; a.C[0] = S->C1;
-            a.bout = b;
-            a.gram = 1;
-            CHK(ts.run_reduce(a, b, 2));
-        }
-        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
-                            (int)act.size(), st));
-        // V_{i+1} = W Rinv (width b, zero columns past the new width)
-        {
-            TsArgs a = ts_args();
-            a.K = 1;
-            a.X[0] = h->W.p; a.ldx[0] = b; a.bx[0] = b; a.C[0] = S->Rinv;
-            a.bout = b;
-            a.out = Vn; a.ldo = b;
-            CHK(ts.run(a, nullptr));
-        }
-        CHK(read_report(h, st));
-        const StepReport &R = *h->rep_host;
-        if (R.flags & kFlagNotHPD) {
-            status = fail(DSBCG_ERR_NOT_HPD, "shifted block lost positive definiteness at step " +
-                                                 std::to_string(i) + ": sigma_j I + A is not hpd");
-            break;
-        }
-        if (R.flags & kFlagQR2) {
-            status = fail(DSBCG_ERR_NOT_CONVERGED, "orthonormalisation of the Lanczos block failed at step " +
-                                                       std::to_string(i));
-            break;
-        }
-        const int bnew = R.bnew;
-        stt.deflations += b - bnew;
-        if (bnew > 0 && bnew < b) {
-            // compact V_{i+1} to leading dimension bnew, into the buffer of V_{i-1}
-            PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, bnew, (true) ? 16 : 8, (true) ? 16 : 8, false), st, copy_field(true, true, c.V, bnew, Vn, b, kPlane, 0, Vp, bnew, kPlane, false, 1.0, st));
-            std::swap(prev, next);
-        }
-        active_list();
-        if (bnew == 0) done = true;
-        if (o.fixed_iters <= 0 && act.empty()) done = true;
-        // rotate the three-block window
-        const int old_prev = prev;
-        prev = cur;
-        cur = next;
-        next = old_prev;
-        pcur ^= 1;
-        bp = b;
-        b = bnew;
-        stt.final_width = bnew;
+        double worst = 0.0;
+        for (double v : tr) worst = std::max(worst, v);
+        if (worst > tol && o.fixed_iters <= 0)
+            status = fail(DSBCG_ERR_NOT_CONVERGED, "true relative residual " + std::to_string(worst) +
+                                                       " above tol after refinement");
     }
-    stt.block_iters = iters;
-    if (status == DSBCG_OK && !done && o.fixed_iters <= 0) {
-        status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
-    }
-    // iterates to the caller's layout
-    for (int j = 0; j < s; ++j)
-        PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m, (true) ? 16 : 8, (true) ? 16 : 8, false), st, copy_field(true, true, c.V, m, (const zd *)h->X.p + (int64_t)j * n * m, m, kPlane, 0,
-                          (zd *)X + (int64_t)j * n * m, m, kApi, false, 1.0, st));
-    HIPCHK(hipStreamSynchronize(st));
     if (stats) {
-        if (stats->est_relres)
-            for (int j = 0; j < s; ++j)
-                for (int l = 0; l < m; ++l) stats->est_relres[j * m + l] = h->rep_host->est[j][l];
-        if (stats->true_relres && status != DSBCG_ERR_NOT_HPD)
-            CHK(true_residuals(c, U, B, X, sigma, stats->true_relres));
-        stt.est_relres = stats->est_relres;
-        stt.true_relres = stats->true_relres;
-        *stats = stt;
+        double *est = stats->est_relres, *tru = stats->true_relres;
+        if (est) std::copy(stt.est, stt.est + (size_t)s * m, est);
+        if (tru) std::copy(tr.begin(), tr.end(), tru);
+        stats->block_iters = stt.block_iters;
+        stats->rank0 = stt.rank0;
+        stats->deflations = stt.deflations;
+        stats->reliable_updates = stt.reliable_updates;
+        stats->refine_iters = stt.refine_iters;
+        stats->final_width = stt.final_width;
+        stats->switch_iter = stt.switch_iter;
+        stats->mvms = stt.mvms;
     }
     return status;
 }

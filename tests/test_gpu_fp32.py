@@ -1,0 +1,109 @@
+"""Precision form on the GPU: FP64 start, FP32 vectors once every active estimate
+is below switch_at, FP64 accumulation of the solution; every (l, j) must reach
+the FP64 true relative residual 1e-10, and the per-shift error against the FP64
+oracle is bounded by cond * 1e-10."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1205_0359_amd import inputs
+import paper_1205_0359_amd as dsb
+
+from gpu_util import announce, dev, host, rel_fro
+
+pytestmark = pytest.mark.gpu
+FP32 = dsb.DSBCG_FP32_RELIABLE
+
+
+def _op(L, U, kappa):
+    V = int(np.prod(L))
+
+    def f(Y):
+        return oracle.apply_A(L, U, kappa, np.ascontiguousarray(Y).reshape(V, 4, 3, -1)).reshape(12 * V, -1)
+    return f
+
+
+def test_fp32_form_matches_dense_4x4x4x4():
+    w = inputs.WORKLOADS["haar4^4_m4_s3"]
+    announce("fp32 form", w.name)
+    U, B = w.make()
+    h = dsb.Handle(w.L)
+    X, st = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(B), w.shifts, w.tol, precision=FP32)
+    assert st["status"] == "OK" and st["switch_iter"] > 1
+    n, m = w.n, w.m
+    op = _op(w.L, U, w.kappa)
+    Xs = host(X).reshape(len(w.shifts), n, m)
+    tr = oracle.true_relres(op, B.reshape(n, m), w.shifts, Xs)
+    assert tr.max() <= w.tol
+    A = op(np.eye(n, dtype=complex))
+    ev = np.linalg.eigvalsh(A)
+    for j, sg in enumerate(w.shifts):
+        dense = np.linalg.solve(A + sg * np.eye(n), B.reshape(n, m))
+        assert rel_fro(Xs[j], dense) <= (ev[-1] + sg) / (ev[0] + sg) * w.tol
+
+
+@pytest.mark.parametrize("L", [(8, 8, 8, 8), (6, 4, 8, 10)])
+def test_fp32_form_deflating_rhs(L):
+    announce("fp32 form deflating", L)
+    U = inputs.make_links(L, "haar", inputs.rng_for(880, 0))
+    V = int(np.prod(L))
+    B = inputs.deflating_rhs(inputs.rng_for(880, 1), inputs.rng_for(880, 2), V)
+    sig = tuple(np.logspace(-5, 0, 10))
+    h = dsb.Handle(L)
+    X, st = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=FP32)
+    assert st["status"] == "OK" and st["rank0"] == 5 and st["switch_iter"] > 1
+    assert st["true_relres"].max() <= 1e-10
+    n = 12 * V
+    ref = oracle.dsbcg(_op(L, U, 0.124), B.reshape(n, 8), sig, 1e-10)
+    Xh = host(X).reshape(len(sig), n, 8)
+    for j in range(len(sig)):
+        # both solutions are within cond * 1e-10 of the exact one; cond(A) is ~20 here
+        assert rel_fro(Xh[j], ref.X[j]) <= 1e-8
+    print("fp32 form", L, "steps", st["block_iters"], "switch at", st["switch_iter"],
+          "refine steps", st["refine_iters"], "max true relres", st["true_relres"].max())
+
+
+def test_fp32_form_without_fp64_start_is_refined():
+    """switch_at >= 1: FP32 from the first step; the FP32 drift leaves true residuals
+    near 1e-7 and the FP64 re-solve of those shifts brings them to 1e-10."""
+    L = (8, 8, 8, 8)
+    announce("fp32 from the start", L)
+    U = inputs.make_links(L, "haar", inputs.rng_for(881, 0))
+    B = inputs.gaussian_rhs(inputs.rng_for(881, 1), 8 ** 4, 4)
+    sig = (1e-4, 1e-1)
+    h = dsb.Handle(L)
+    X, st = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=FP32, switch_at=10.0)
+    assert st["switch_iter"] == 1 and st["refine_iters"] > 0
+    assert st["true_relres"].max() <= 1e-10
+
+
+def test_fp32_form_before_switch_equals_fp64():
+    """With a switch threshold never reached the precision form is the FP64 form."""
+    L = (4, 4, 6, 8)
+    announce("fp32 no switch", L)
+    U = inputs.make_links(L, "smooth", inputs.rng_for(882, 0))
+    B = inputs.gaussian_rhs(inputs.rng_for(882, 1), int(np.prod(L)), 3)
+    h = dsb.Handle(L)
+    dU, dB = dev(U), dev(B)
+    X1, s1 = dsb.dsbcg_solve(h, dU, 0.125, dB, (1e-3, 1e-1), 1e-10, precision=FP32, switch_at=1e-300)
+    X2, s2 = dsb.dsbcg_solve(h, dU, 0.125, dB, (1e-3, 1e-1), 1e-10)
+    assert s1["switch_iter"] == 0
+    assert np.array_equal(host(X1), host(X2))
+
+
+def test_fp32_form_full_size_24x24x24x48():
+    w = inputs.WORKLOADS["haar24^3x48_m12_s12"]
+    announce("fp32 form full size", w.name)
+    U, B = w.make()
+    h = dsb.Handle(w.L)
+    X, st = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(B), w.shifts, w.tol, precision=FP32)
+    assert st["status"] == "OK"
+    assert st["true_relres"].max() <= w.tol
+    # the oracle re-evaluates the residual of the hardest shift on sampled sites
+    sites = np.random.default_rng(3).integers(0, w.V, 24)
+    Xh = host(X[0])
+    AX = oracle.apply_A_sites(w.L, U, w.kappa, Xh, sites)
+    Ag = dsb.dsbcg_apply_A(h, dev(U), w.kappa, X[0].contiguous())
+    assert np.abs(host(Ag)[sites] - AX).max() <= 1e-12 * np.abs(AX).max()
+    print("fp32 full", w.name, "steps", st["block_iters"], "switch", st["switch_iter"],
+          "refine", st["refine_iters"], "max", st["true_relres"].max())
