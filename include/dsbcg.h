@@ -83,7 +83,7 @@ typedef struct {
     int32_t freeze;       /* 1: stop updating a system once its estimate reaches tol (default 1) */
     double switch_at;     /* FP32 form: the iteration runs in FP64 until every active estimated
                              relative residual is <= switch_at, then continues the same
-                             recurrences with FP32 vectors (default min(1e-2, 1e6 * tol)) */
+                             recurrences with FP32 vectors (default min(1e-2, 1e5 * tol)) */
 } dsbcg_opts;
 
 typedef struct {
@@ -94,6 +94,8 @@ typedef struct {
     int32_t refine_iters;     /* block steps spent in refinement solves */
     int32_t final_width;      /* width of the last Lanczos block */
     int32_t switch_iter;      /* FP32 form: first block step run with FP32 vectors (0: none) */
+    double main_relres_max;   /* largest FP64 true relative residual after the main phase,
+                                 before any re-solve (0 when true residuals were not formed) */
     int64_t mvms;             /* applications of A to one vector by the method: sum of the
                                  block widths of the main phase and of refinement solves */
     double *est_relres;       /* host [s*m] (index j*m + l) or NULL: last estimated

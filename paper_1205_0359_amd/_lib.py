@@ -52,7 +52,8 @@ class dsbcg_stats(ctypes.Structure):
     _fields_ = [("block_iters", ctypes.c_int32), ("rank0", ctypes.c_int32),
                 ("deflations", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("final_width", ctypes.c_int32),
-                ("switch_iter", ctypes.c_int32), ("mvms", ctypes.c_int64),
+                ("switch_iter", ctypes.c_int32), ("main_relres_max", ctypes.c_double),
+                ("mvms", ctypes.c_int64),
                 ("est_relres", ctypes.POINTER(ctypes.c_double)),
                 ("true_relres", ctypes.POINTER(ctypes.c_double))]
 
@@ -256,7 +257,8 @@ def dsbcg_solve(h: Handle, U, kappa: float, B, sigma, tol: float, X=None, stream
         "status": STATUS_NAMES.get(code, code),
         "block_iters": st.block_iters, "rank0": st.rank0, "deflations": st.deflations,
         "reliable_updates": st.reliable_updates, "refine_iters": st.refine_iters,
-        "final_width": st.final_width, "switch_iter": st.switch_iter, "mvms": int(st.mvms),
+        "final_width": st.final_width, "switch_iter": st.switch_iter, "main_relres_max": st.main_relres_max,
+        "mvms": int(st.mvms),
         "est_relres": est.reshape(s, m).T.copy(), "true_relres": true.reshape(s, m).T.copy(),
     }
     if code == DSBCG_ERR_NOT_CONVERGED and not raise_not_converged:

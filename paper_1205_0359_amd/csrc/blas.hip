@@ -2,119 +2,230 @@
 // per-shift recurrences (Sec. 3 of the paper): products V^H W (Gram), block
 // combinations W - V alpha - V' beta^H, basis scalings W R^{-1}, and the
 // P_j / X_j updates.  All of them stream n x b blocks with b <= 16 and are
-// bound by HBM bandwidth; Gram sums are accumulated in FP64 and reduced in a
-// fixed order, so results are bitwise repeatable.
+// bound by HBM bandwidth.  Blocks are column-major and one thread owns one
+// row, so a wave reads 64 consecutive elements of a column.  Gram sums are
+// accumulated in FP64 and reduced in a fixed order (bitwise repeatable).
 
 #include "blas.hpp"
 
 namespace dsbcg {
 
 // ---------------------------------------------------------------------------
-// Combination + Gram engine.  A workgroup owns a contiguous range of rows and
-// walks it in tiles of TR rows: the input tiles are staged in LDS with
-// coalesced loads, the combination is formed element-wise from LDS (and
-// optionally stored), and the Gram partial sums are accumulated from LDS.
-// Inputs may alias the output: a tile is fully read before it is written and
-// tiles of different workgroups never overlap.
+// Combination out = sum_k X_k C_k, one thread per row.  Coefficients are
+// rounded to the data precision and read from LDS with wave-uniform
+// addresses.
 // ---------------------------------------------------------------------------
-template <typename R>
-struct TsTile {
-    static constexpr int TR = sizeof(R) == 8 ? 32 : 64;
-};
-
-template <typename R>
-__global__ __launch_bounds__(kTsThreads) void ts_kernel(TsArgs a) {
-    constexpr int TR = TsTile<R>::TR;
-    __shared__ cx<R> xin[3][TR * kMaxW];
-    __shared__ cx<R> otile[TR * kMaxW];
-    __shared__ cx<R> ltile[TR * kMaxW];
-    __shared__ cx<R> coef[3][kMaxW * kMaxW];
-    __shared__ zd red[kTsThreads];
-
-    const int tid = threadIdx.x;
-    const int bout = a.bout;
-    // coefficients, rounded to the data precision
+template <typename R, int BO>
+__device__ inline void combine_row(const TsArgs &a, const cx<R> (*coef)[kMaxW * kMaxW], int64_t row,
+                                   cx<R> out[BO]) {
+#pragma unroll
+    for (int q = 0; q < BO; ++q) out[q] = mk<R>(0, 0);
     for (int k = 0; k < a.K; ++k) {
-        if (a.C[k] == nullptr) continue;
-        for (int e = tid; e < a.bx[k] * bout; e += kTsThreads) {
-            const int p = e / bout, q = e - p * bout;
-            coef[k][p * kMaxW + q] = cvt<R>(a.C[k][p * 16 + q]);
-        }
-    }
-
-    const int pairs = a.gram ? (a.gram == 1 ? bout : a.bl) * bout : 0;
-    const int groups = pairs ? kTsThreads / pairs : 0;
-    const int grp = pairs ? tid / pairs : 0;
-    const int pr = pairs ? tid - grp * pairs : 0;
-    const int gp = pairs ? pr / bout : 0, gq = pairs ? pr - gp * bout : 0;
-    zd acc = mk<double>(0, 0);
-
-    const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_wg;
-    const int64_t r_end = min(a.nrows, r_begin + a.rows_per_wg);
-    __syncthreads();
-
-    for (int64_t t0 = r_begin; t0 < r_end; t0 += TR) {
-        const int nr = (int)min((int64_t)TR, r_end - t0);
-        // stage the input tiles
-        for (int k = 0; k < a.K; ++k) {
-            const cx<R> *X = (const cx<R> *)a.X[k];
-            const int bx = a.bx[k];
-            const int64_t ld = a.ldx[k];
-            for (int e = tid; e < nr * bx; e += kTsThreads) {
-                const int r = e / bx, p = e - r * bx;
-                xin[k][r * kMaxW + p] = X[(t0 + r) * ld + p];
+        const cx<R> *X = (const cx<R> *)a.X[k] + row;
+        const int64_t cs = a.cs[k];
+        if (a.C[k] == nullptr) {
+#pragma unroll
+            for (int q = 0; q < BO; ++q)
+                if (q < a.bout) out[q] = out[q] + X[q * cs];
+        } else {
+            for (int p = 0; p < a.bx[k]; ++p) {
+                const cx<R> x = X[p * cs];
+#pragma unroll
+                for (int q = 0; q < BO; ++q)
+                    if (q < a.bout) cmac(out[q], x, coef[k][p * kMaxW + q]);
             }
-        }
-        if (a.gram == 2) {
-            const cx<R> *Lp = (const cx<R> *)a.L;
-            for (int e = tid; e < nr * a.bl; e += kTsThreads) {
-                const int r = e / a.bl, p = e - r * a.bl;
-                ltile[r * kMaxW + p] = Lp[(t0 + r) * a.ldl + p];
-            }
-        }
-        __syncthreads();
-        // combination
-        cx<R> *out = (cx<R> *)a.out;
-        for (int e = tid; e < nr * bout; e += kTsThreads) {
-            const int r = e / bout, q = e - r * bout;
-            cx<R> v = mk<R>(0, 0);
-            for (int k = 0; k < a.K; ++k) {
-                if (a.C[k] == nullptr) {
-                    v = v + xin[k][r * kMaxW + q];
-                } else {
-                    for (int p = 0; p < a.bx[k]; ++p)
-                        cmac(v, xin[k][r * kMaxW + p], coef[k][p * kMaxW + q]);
-                }
-            }
-            otile[r * kMaxW + q] = v;
-            if (out) out[(t0 + r) * a.ldo + q] = v;
-        }
-        __syncthreads();
-        // Gram partial sums in FP64
-        if (pairs && grp < groups) {
-            const cx<R> *lt = (a.gram == 1) ? otile : ltile;
-            for (int r = grp; r < nr; r += groups)
-                cmac_conj(acc, cvt<double>(lt[r * kMaxW + gp]), cvt<double>(otile[r * kMaxW + gq]));
-        }
-        __syncthreads();
-    }
-
-    if (pairs) {
-        red[tid] = acc;
-        __syncthreads();
-        if (tid < pairs) {
-            zd s = red[tid];
-            for (int g = 1; g < groups; ++g) s = s + red[g * pairs + tid];
-            a.partials[(int64_t)blockIdx.x * 256 + gp * 16 + gq] = s;
         }
     }
 }
 
-hipError_t ts_run(bool fp64, TsArgs a, int nwg, hipStream_t st) {
-    if (fp64)
-        hipLaunchKernelGGL(ts_kernel<double>, dim3(nwg), dim3(kTsThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL(ts_kernel<float>, dim3(nwg), dim3(kTsThreads), 0, st, a);
+template <typename R>
+__device__ inline void load_coefs(const TsArgs &a, cx<R> (*coef)[kMaxW * kMaxW]) {
+    for (int k = 0; k < a.K; ++k) {
+        if (a.C[k] == nullptr) continue;
+        for (int e = threadIdx.x; e < a.bx[k] * a.bout; e += blockDim.x) {
+            const int p = e / a.bout, q = e - p * a.bout;
+            coef[k][p * kMaxW + q] = cvt<R>(a.C[k][p * 16 + q]);
+        }
+    }
+}
+
+// Gram with B x B accumulators per thread (bl == bout == B).
+template <typename R, int B>
+__global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
+    __shared__ cx<R> coef[3][kMaxW * kMaxW];
+    __shared__ zd red[4][B * B];
+    load_coefs<R>(a, coef);
+    __syncthreads();
+    zd G[B][B];
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+        for (int q = 0; q < B; ++q) G[p][q] = mk<double>(0, 0);
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
+    const int64_t r1 = min(a.nrows, r0 + a.rows_per_wg);
+    cx<R> *out = (cx<R> *)a.out;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += 256) {
+        cx<R> o[B];
+        combine_row<R, B>(a, coef, row, o);
+        if (out)
+#pragma unroll
+            for (int q = 0; q < B; ++q) out[q * a.cso + row] = o[q];
+        if (a.gram) {
+            cx<R> l[B];
+            if (a.gram == 2) {
+                const cx<R> *Lp = (const cx<R> *)a.L + row;
+#pragma unroll
+                for (int p = 0; p < B; ++p) l[p] = Lp[p * a.csl];
+            } else {
+#pragma unroll
+                for (int p = 0; p < B; ++p) l[p] = o[p];
+            }
+#pragma unroll
+            for (int p = 0; p < B; ++p)
+#pragma unroll
+                for (int q = 0; q < B; ++q) cmac_conj(G[p][q], cvt<double>(l[p]), cvt<double>(o[q]));
+        }
+    }
+    if (!a.gram) return;
+    // wave reduction by butterflies, then across the four waves
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            zd v = G[p][q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                v.x += __shfl_xor(v.x, off, 64);
+                v.y += __shfl_xor(v.y, off, 64);
+            }
+            if (lane == 0) red[wave][p * B + q] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < B * B) {
+        const int p = threadIdx.x / B, q = threadIdx.x - p * B;
+        zd s = red[0][threadIdx.x];
+        s = s + red[1][threadIdx.x];
+        s = s + red[2][threadIdx.x];
+        s = s + red[3][threadIdx.x];
+        a.partials[(int64_t)blockIdx.x * 256 + p * 16 + q] = s;
+    }
+}
+
+// General widths: a tile of rows (one per thread) is staged in LDS
+// (column-major) and the Gram is accumulated by 2 x 2 blocks of pairs; with
+// 128 threads two halves of the tile are summed separately.
+template <typename R>
+struct TileRows {
+    static constexpr int value = sizeof(R) == 8 ? 64 : 128;
+};
+
+template <typename R>
+__global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
+    constexpr int kTileRows = TileRows<R>::value;
+    __shared__ cx<R> coef[3][kMaxW * kMaxW];
+    __shared__ cx<R> so[kMaxW * kTileRows];
+    __shared__ cx<R> sl[kMaxW * kTileRows];
+    __shared__ zd red[4][64];
+    load_coefs<R>(a, coef);
+    const int t = threadIdx.x;
+    const int bl = (a.gram == 1) ? a.bout : a.bl;
+    const int nbq = (a.bout + 1) / 2, nbp = (bl + 1) / 2;
+    const int nblk = nbp * nbq;
+    const int blk = t & 63, half = t >> 6;
+    const int bp = (blk < nblk) ? blk / nbq : 0, bq = (blk < nblk) ? blk - (blk / nbq) * nbq : 0;
+    zd G[2][2];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) G[u][v] = mk<double>(0, 0);
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
+    const int64_t r1 = min(a.nrows, r0 + a.rows_per_wg);
+    cx<R> *out = (cx<R> *)a.out;
+    __syncthreads();
+    for (int64_t t0 = r0; t0 < r1; t0 += kTileRows) {
+        const int64_t row = t0 + t;
+        const bool ok = row < r1;
+        if (ok) {
+            cx<R> o[kMaxW];
+            combine_row<R, kMaxW>(a, coef, row, o);
+            for (int q = 0; q < a.bout; ++q) {
+                if (out) out[q * a.cso + row] = o[q];
+                so[q * kTileRows + t] = o[q];
+            }
+            if (a.gram == 2) {
+                const cx<R> *Lp = (const cx<R> *)a.L + row;
+                for (int p = 0; p < a.bl; ++p) sl[p * kTileRows + t] = Lp[p * a.csl];
+            }
+        } else {
+            for (int q = 0; q < a.bout; ++q) so[q * kTileRows + t] = mk<R>(0, 0);
+            if (a.gram == 2)
+                for (int p = 0; p < a.bl; ++p) sl[p * kTileRows + t] = mk<R>(0, 0);
+        }
+        __syncthreads();
+        if (a.gram && blk < nblk) {
+            const cx<R> *L = (a.gram == 1) ? so : sl;
+            const int p0 = 2 * bp, q0 = 2 * bq;
+            const bool p1ok = p0 + 1 < bl, q1ok = q0 + 1 < a.bout;
+            for (int r = half * 64; r < half * 64 + 64 && r < kTileRows; ++r) {
+                const zd l0 = cvt<double>(L[p0 * kTileRows + r]);
+                const zd l1 = p1ok ? cvt<double>(L[(p0 + 1) * kTileRows + r]) : mk<double>(0, 0);
+                const zd y0 = cvt<double>(so[q0 * kTileRows + r]);
+                const zd y1 = q1ok ? cvt<double>(so[(q0 + 1) * kTileRows + r]) : mk<double>(0, 0);
+                cmac_conj(G[0][0], l0, y0);
+                cmac_conj(G[0][1], l0, y1);
+                cmac_conj(G[1][0], l1, y0);
+                cmac_conj(G[1][1], l1, y1);
+            }
+        }
+        __syncthreads();
+    }
+    if (!a.gram) return;
+    // combine the two row halves, then write the blocks
+    if (half == 1 && blk < nblk)
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) red[u * 2 + v][blk] = G[u][v];
+    __syncthreads();
+    if (half == 0 && blk < nblk) {
+        const int p0 = 2 * bp, q0 = 2 * bq;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) {
+                const int p = p0 + u, q = q0 + v;
+                if (p < bl && q < a.bout)
+                    a.partials[(int64_t)blockIdx.x * 256 + p * 16 + q] =
+                        (blockDim.x > 64) ? G[u][v] + red[u * 2 + v][blk] : G[u][v];
+            }
+    }
+}
+
+hipError_t ts_run(bool fp64, TsArgs a, int max_wg, int *nwg_out, hipStream_t st) {
+    const int bl = (a.gram == 1) ? a.bout : a.bl;
+    const bool reg = a.gram != 2 ? (a.bout <= 6) : (a.bl == a.bout && a.bout <= 6);
+    const int tile = reg ? 256 : (fp64 ? TileRows<double>::value : TileRows<float>::value);
+    int64_t tiles = (a.nrows + tile - 1) / tile;
+    int nwg = (int)(tiles < max_wg ? tiles : max_wg);
+    if (nwg < 1) nwg = 1;
+    const int64_t per = (tiles + nwg - 1) / nwg;
+    a.rows_per_wg = per * tile;
+    nwg = (int)((a.nrows + a.rows_per_wg - 1) / a.rows_per_wg);
+    if (nwg < 1) nwg = 1;
+    (void)bl;
+    if (reg) {
+#define DSBCG_TS(R, B) hipLaunchKernelGGL((ts_reg_kernel<R, B>), dim3(nwg), dim3(256), 0, st, a)
+        switch (a.bout) {
+            case 1: if (fp64) DSBCG_TS(double, 1); else DSBCG_TS(float, 1); break;
+            case 2: if (fp64) DSBCG_TS(double, 2); else DSBCG_TS(float, 2); break;
+            case 3: if (fp64) DSBCG_TS(double, 3); else DSBCG_TS(float, 3); break;
+            case 4: if (fp64) DSBCG_TS(double, 4); else DSBCG_TS(float, 4); break;
+            case 5: if (fp64) DSBCG_TS(double, 5); else DSBCG_TS(float, 5); break;
+            default: if (fp64) DSBCG_TS(double, 6); else DSBCG_TS(float, 6); break;
+        }
+#undef DSBCG_TS
+    } else {
+        if (fp64)
+            hipLaunchKernelGGL(ts_lds_kernel<double>, dim3(nwg), dim3(TileRows<double>::value), 0, st, a);
+        else
+            hipLaunchKernelGGL(ts_lds_kernel<float>, dim3(nwg), dim3(TileRows<float>::value), 0, st, a);
+    }
+    if (nwg_out) *nwg_out = nwg;
     return hipGetLastError();
 }
 
@@ -139,30 +250,39 @@ hipError_t reduce_partials(const zd *partials, int nwg, int nelem, zd *out, hipS
 }
 
 // ---------------------------------------------------------------------------
-// Layout conversion / widening / accumulation.
+// Layout conversion / widening / accumulation of lattice fields.
 // ---------------------------------------------------------------------------
+struct Strides {
+    int64_t site, comp, col, base;
+};
+
+__host__ __device__ inline Strides strides_of(const FieldDesc &f, int64_t V) {
+    if (f.layout == kApi) return {12 * f.ld, f.ld, 1, f.col0};
+    return {1, V, f.ld, 0};
+}
+
 template <typename Ti, typename To>
 __global__ __launch_bounds__(256) void copy_kernel(int64_t V, int cols, const cx<Ti> *__restrict__ in,
-                                                   int64_t in_ld, int in_order, int in_col0,
-                                                   cx<To> *__restrict__ out, int64_t out_ld,
-                                                   int out_order, int accumulate, double scale) {
+                                                   Strides si, cx<To> *__restrict__ out, Strides so,
+                                                   int out_cm, int accumulate, double scale) {
     const int64_t total = V * 12 * cols;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        // enumerate in the output's row order so that stores are contiguous
-        const int64_t orow = e / cols;
-        const int col = (int)(e - orow * cols);
-        int64_t x, c;
-        if (out_order == kApi) {
-            x = orow / 12;
-            c = orow - x * 12;
+        // enumerate so that consecutive threads store consecutive elements
+        int64_t x, c, r;
+        if (out_cm) {
+            x = e % V;
+            const int64_t k = e / V;
+            c = k % 12;
+            r = k / 12;
         } else {
-            c = orow / V;
-            x = orow - c * V;
+            r = e % cols;
+            const int64_t k = e / cols;
+            c = k % 12;
+            x = k / 12;
         }
-        const int64_t irow = (in_order == kApi) ? x * 12 + c : c * V + x;
-        const cx<double> v = cvt<double>(in[irow * in_ld + in_col0 + col]);
-        cx<To> *o = out + orow * out_ld + col;
+        const cx<double> v = cvt<double>(in[si.base + x * si.site + c * si.comp + r * si.col]);
+        cx<To> *o = out + so.base + x * so.site + c * so.comp + r * so.col;
         if (accumulate) {
             const cx<double> w = cvt<double>(*o);
             *o = cvt<To>(mk<double>(w.x + scale * v.x, w.y + scale * v.y));
@@ -172,22 +292,21 @@ __global__ __launch_bounds__(256) void copy_kernel(int64_t V, int cols, const cx
     }
 }
 
-hipError_t copy_field(bool in_fp64, bool out_fp64, int64_t V, int cols, const void *in,
-                      int64_t in_ld, int in_order, int in_col0, void *out, int64_t out_ld,
-                      int out_order, bool accumulate, double scale, hipStream_t st) {
+hipError_t copy_field(int64_t V, int cols, FieldDesc in, FieldDesc out, bool accumulate,
+                      double scale, hipStream_t st) {
     const int64_t total = V * 12 * cols;
     const int64_t want = (total + 255) / 256;
     const dim3 grid((unsigned)(want < 65536 ? (want > 0 ? want : 1) : 65536));
-    const int acc = accumulate ? 1 : 0;
+    const Strides si = strides_of(in, V), so = strides_of(out, V);
+    const int ocm = out.layout == kCM, acc = accumulate ? 1 : 0;
 #define DSBCG_COPY(TI, TO)                                                                   \
     hipLaunchKernelGGL((copy_kernel<TI, TO>), grid, dim3(256), 0, st, V, cols,               \
-                       (const cx<TI> *)in, in_ld, in_order, in_col0, (cx<TO> *)out, out_ld, \
-                       out_order, acc, scale)
-    if (in_fp64 && out_fp64)
+                       (const cx<TI> *)in.p, si, (cx<TO> *)out.p, so, ocm, acc, scale)
+    if (in.fp64 && out.fp64)
         DSBCG_COPY(double, double);
-    else if (in_fp64)
+    else if (in.fp64)
         DSBCG_COPY(double, float);
-    else if (out_fp64)
+    else if (out.fp64)
         DSBCG_COPY(float, double);
     else
         DSBCG_COPY(float, float);
@@ -196,15 +315,16 @@ hipError_t copy_field(bool in_fp64, bool out_fp64, int64_t V, int cols, const vo
 }
 
 // ---------------------------------------------------------------------------
-// Per-shift update, one thread per row.  The coefficient matrices are read
-// with wave-uniform addresses (scalar loads); the basis row V_i is read once
-// from HBM and re-read from cache for every further shift.
+// Per-shift update, one thread per row (coalesced column-major access).  The
+// coefficient matrices are read with wave-uniform addresses; the basis row
+// V_i is read once from HBM and re-read from cache for every further shift.
 // ---------------------------------------------------------------------------
 template <typename R, int BC>
 __global__ __launch_bounds__(256) void shift_kernel(ShiftArgs a) {
     const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (row >= a.nrows) return;
-    const cx<R> *__restrict__ V = (const cx<R> *)a.V;
+    const int64_t n = a.nrows;
+    const cx<R> *__restrict__ V = (const cx<R> *)a.V + row;
     const cx<R> *__restrict__ Nc = (const cx<R> *)a.N;
     const cx<R> *__restrict__ Mc = (const cx<R> *)a.M;
     const int b = a.b, bp = a.bp, m = a.m;
@@ -212,15 +332,14 @@ __global__ __launch_bounds__(256) void shift_kernel(ShiftArgs a) {
         const int j = a.shifts[js];
         const uint32_t mask = a.colmask[j];
         cx<R> pn[BC];
-        const cx<R> *vr = V + row * b;
 #pragma unroll
         for (int q = 0; q < BC; ++q)
-            if (q < b) pn[q] = vr[q];
+            if (q < b) pn[q] = V[q * n];
         if (!a.first) {
-            const cx<R> *po = (const cx<R> *)a.Pold + j * a.pstride + row * bp;
+            const cx<R> *po = (const cx<R> *)a.Pold + j * a.pstride + row;
             const cx<R> *Nj = Nc + j * 256;
             for (int p = 0; p < bp; ++p) {
-                const cx<R> v = po[p];
+                const cx<R> v = po[p * n];
 #pragma unroll
                 for (int q = 0; q < BC; ++q)
                     if (q < b) {
@@ -232,19 +351,19 @@ __global__ __launch_bounds__(256) void shift_kernel(ShiftArgs a) {
                     }
             }
         }
-        cx<R> *pw = (cx<R> *)a.Pnew + j * a.pstride + row * b;
+        cx<R> *pw = (cx<R> *)a.Pnew + j * a.pstride + row;
 #pragma unroll
         for (int q = 0; q < BC; ++q)
-            if (q < b) pw[q] = pn[q];
-        cx<R> *xr = (cx<R> *)a.X + j * a.xstride + row * m;
+            if (q < b) pw[q * n] = pn[q];
+        cx<R> *xr = (cx<R> *)a.X + j * a.xstride + row;
         const cx<R> *Mj = Mc + j * 256;
         for (int l = 0; l < m; ++l) {
             if (!((mask >> l) & 1u)) continue;
-            cx<R> x = xr[l];
+            cx<R> x = xr[l * n];
 #pragma unroll
             for (int q = 0; q < BC; ++q)
                 if (q < b) cmac(x, pn[q], Mj[q * 16 + l]);
-            xr[l] = x;
+            xr[l * n] = x;
         }
     }
 }

@@ -9,6 +9,11 @@
 //   residual coefficients C_j = Z_{j,i+1}, estimates, freezing
 // The host reads one small report per step (new block width, masks,
 // estimates) and decides whether to continue.
+//
+// Internal layouts: every n x b block is column-major (column stride n =
+// 12 V, row c * V + x); links are structure of arrays [4][9][V].  The caller's
+// arrays use the site-major layouts of the header and are converted at entry
+// and exit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +25,7 @@
 
 #include "../../include/dsbcg.h"
 #include "blas.hpp"
+#include "grad.hpp"
 #include "small.hpp"
 #include "stencil.hpp"
 
@@ -44,12 +50,16 @@ int fail(int code, const std::string &msg) {
         }                                                                                  \
     } while (0)
 
+#define CHK(expr)                          \
+    do {                                   \
+        int rc_ = (expr);                  \
+        if (rc_ != DSBCG_OK) return rc_;   \
+    } while (0)
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
 };
-
-}  // namespace
 
 enum ProfClass {
     kProfStencil = 0,   // one Wilson D or D^H pass
@@ -57,10 +67,11 @@ enum ProfClass {
     kProfShift,         // fused per-shift P_j / X_j update
     kProfSmall,         // small FP64 algebra and Gram reductions
     kProfConvert,       // layout conversions, widening, accumulation
+    kProfGrad,          // link-derivative stencil
     kProfClasses
 };
-const char *const kProfNames[kProfClasses] = {"wilson_stencil", "block_gram_update",
-                                              "shift_update", "small_algebra", "convert"};
+const char *const kProfNames[kProfClasses] = {"wilson_stencil", "block_gram_update", "shift_update",
+                                              "small_algebra",  "convert",           "link_grad"};
 
 struct ProfRec {
     int cls;
@@ -68,10 +79,11 @@ struct ProfRec {
     double bytes;
 };
 
+}  // namespace
+
 struct dsbcg_ctx {
     Geom g{};
     int device = 0;
-    bool lds_links = true;
     // kernel timing (dsbcg_profile_enable)
     bool prof = false;
     std::vector<ProfRec> prof_pending;
@@ -80,18 +92,22 @@ struct dsbcg_ctx {
     double prof_bytes[kProfClasses] = {};
     int64_t prof_launches[kProfClasses] = {};
     // workspace
-    DevBuf U32, T, W, V[3], P[2], X, Bint, Q, wbuf, Rf64a, Rf64b, X32in;
-    DevBuf V32[3], T32, W32, P32[2], Xlo, Rres, Xref;
+    DevBuf Ul64, Ul32;                                   // structure-of-arrays links
+    DevBuf V[3], T, W, P[2], X;                          // FP64 iteration
+    DevBuf V32[3], T32, W32, P32[2], Xlo;                // FP32 iteration
+    DevBuf Bint, Q, wbuf;                                // deflated QR of B
+    DevBuf R0, R1, R2, R3, Rres, Xref;                   // true residuals, refinement
+    DevBuf Xin, Yout;                                    // dsbcg_apply_* conversions
     DevBuf partials, red, list, st, rep;
     StepReport *rep_host = nullptr;
     int32_t *list_host = nullptr;
     int nwg_max = 2048;
 
     ~dsbcg_ctx() {
-        DevBuf *all[] = {&U32,   &T,     &W,     &V[0],  &V[1],   &V[2],   &P[0],     &P[1],
-                         &X,     &Bint,  &Q,     &wbuf,  &Rf64a,  &Rf64b,  &X32in,    &V32[0],
-                         &V32[1], &V32[2], &T32, &W32,   &P32[0], &P32[1], &Xlo,      &Rres,
-                         &Xref,  &partials, &red, &list, &st,     &rep};
+        DevBuf *all[] = {&Ul64, &Ul32, &V[0], &V[1], &V[2], &T,   &W,    &P[0], &P[1], &X,
+                         &V32[0], &V32[1], &V32[2], &T32, &W32, &P32[0], &P32[1], &Xlo,
+                         &Bint, &Q,    &wbuf, &R0,   &R1,   &R2,  &R3,   &Rres, &Xref, &Xin,
+                         &Yout, &partials, &red, &list, &st, &rep};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         if (rep_host) (void)hipHostFree(rep_host);
@@ -123,12 +139,6 @@ int ensure(DevBuf &b, size_t bytes) {
     b.bytes = bytes;
     return DSBCG_OK;
 }
-
-#define CHK(expr)                          \
-    do {                                   \
-        int rc_ = (expr);                  \
-        if (rc_ != DSBCG_OK) return rc_;   \
-    } while (0)
 
 // ---- kernel timing: each profiled launch is bracketed by two events ----
 hipError_t prof_event(dsbcg_ctx *h, hipEvent_t *e) {
@@ -220,8 +230,20 @@ int ensure_common(dsbcg_ctx *h) {
 
 zd *red_slot(dsbcg_ctx *h, int k) { return (zd *)h->red.p + 256 * k; }
 
-// Tall-skinny combination / Gram launch.  Returns the number of workgroups
-// whose partials must be reduced.
+FieldDesc cm(const void *p, int64_t n, bool fp64) { return FieldDesc{const_cast<void *>(p), kCM, n, 0, fp64}; }
+FieldDesc api(const void *p, int64_t ld, int col0 = 0) {
+    return FieldDesc{const_cast<void *>(p), kApi, ld, col0, true};
+}
+
+int copy(dsbcg_ctx *h, int cols, FieldDesc in, FieldDesc out, bool accumulate, hipStream_t st) {
+    if (cols <= 0) return DSBCG_OK;
+    PROF_LAUNCH(h, kProfConvert,
+                copy_bytes(h->g.V, cols, in.fp64 ? 16 : 8, out.fp64 ? 16 : 8, accumulate), st,
+                copy_field(h->g.V, cols, in, out, accumulate, 1.0, st));
+    return DSBCG_OK;
+}
+
+// Tall-skinny combination / Gram launches on column-major blocks.
 struct Ts {
     dsbcg_ctx *h;
     bool fp64;
@@ -229,14 +251,6 @@ struct Ts {
     int64_t nrows;
 
     int run(TsArgs a, int *nwg_out) {
-        const int TR = fp64 ? 32 : 64;
-        int64_t tiles = (nrows + TR - 1) / TR;
-        int nwg = (int)std::min<int64_t>(tiles, h->nwg_max);
-        if (nwg < 1) nwg = 1;
-        int64_t per = (tiles + nwg - 1) / nwg;
-        a.rows_per_wg = per * TR;
-        nwg = (int)((nrows + a.rows_per_wg - 1) / a.rows_per_wg);
-        if (nwg < 1) nwg = 1;
         a.nrows = nrows;
         a.partials = (zd *)h->partials.p;
         double per_row = 0;
@@ -244,7 +258,8 @@ struct Ts {
         if (a.out) per_row += a.bout;
         if (a.gram == 2) per_row += a.bl;
         const double bytes = per_row * (double)nrows * (fp64 ? sizeof(zd) : sizeof(zf));
-        PROF_LAUNCH(h, kProfBlock, bytes, st, ts_run(fp64, a, nwg, st));
+        int nwg = 0;
+        PROF_LAUNCH(h, kProfBlock, bytes, st, ts_run(fp64, a, h->nwg_max, &nwg, st));
         if (nwg_out) *nwg_out = nwg;
         return DSBCG_OK;
     }
@@ -259,9 +274,12 @@ struct Ts {
     }
 };
 
-TsArgs ts_args() {
+TsArgs ts_args(int64_t n) {
     TsArgs a;
     memset(&a, 0, sizeof(a));
+    for (int k = 0; k < 3; ++k) a.cs[k] = n;
+    a.cso = n;
+    a.csl = n;
     return a;
 }
 
@@ -287,36 +305,30 @@ int validate_geom(const int32_t *L) {
     return DSBCG_OK;
 }
 
-// Plane layout of an n x b block: element (x, c, r) at (c*V + x)*b + r.
-inline int64_t plane_site(int b) { return b; }
-inline int64_t plane_comp(const Geom &g, int b) { return (int64_t)g.V * b; }
-
-// Y = A X on b columns, FP64 or FP32 data; X and Y in plane layout with
-// leading dimension b, T scratch of the same shape.
-int apply_A_plane(dsbcg_ctx *h, bool fp64, const void *U, double kappa, const void *X, void *T,
-                  void *Y, int b, hipStream_t st) {
-    const double bytes = stencil_bytes(h->g, b, fp64 ? sizeof(zd) : sizeof(zf));
-    PROF_LAUNCH(h, kProfStencil, bytes, st,
-                wilson_apply(h->g, fp64, U, kappa, X, plane_site(b), plane_comp(h->g, b), T,
-                             plane_site(b), plane_comp(h->g, b), b, false, h->lds_links, st));
-    PROF_LAUNCH(h, kProfStencil, bytes, st,
-                wilson_apply(h->g, fp64, U, kappa, T, plane_site(b), plane_comp(h->g, b), Y,
-                             plane_site(b), plane_comp(h->g, b), b, true, h->lds_links, st));
+int stencil(dsbcg_ctx *h, bool fp64, const void *Ul, double kappa, const void *X, void *Y, int b,
+            bool dagger, hipStream_t st) {
+    PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, b, fp64 ? sizeof(zd) : sizeof(zf)), st,
+                wilson_apply(h->g, fp64, Ul, kappa, X, Y, b, dagger, st));
     return DSBCG_OK;
 }
 
-struct SolveCtx {
-    dsbcg_ctx *h;
-    hipStream_t st;
-    bool fp64;          // data precision of the iteration
-    size_t esz;         // bytes per complex element of the iteration
-    int64_t V, n;
-    int m, s;
-    const void *Ulinks; // links in the iteration precision
-    double kappa;
-    double tol;
-    dsbcg_opts o;
-};
+// Y = A X on b column-major columns, T scratch of the same shape.
+int apply_A_cm(dsbcg_ctx *h, bool fp64, const void *Ul, double kappa, const void *X, void *T,
+               void *Y, int b, hipStream_t st) {
+    CHK(stencil(h, fp64, Ul, kappa, X, T, b, false, st));
+    CHK(stencil(h, fp64, Ul, kappa, T, Y, b, true, st));
+    return DSBCG_OK;
+}
+
+// Structure-of-arrays copy of the caller's links.
+int prepare_links(dsbcg_ctx *h, const void *U, bool fp64, hipStream_t st) {
+    const int64_t V = h->g.V;
+    DevBuf &buf = fp64 ? h->Ul64 : h->Ul32;
+    CHK(ensure(buf, (size_t)V * 36 * (fp64 ? sizeof(zd) : sizeof(zf))));
+    PROF_LAUNCH(h, kProfConvert, (double)V * 36 * (16.0 + (fp64 ? 16.0 : 8.0)), st,
+                links_to_soa(V, U, buf.p, fp64, st));
+    return DSBCG_OK;
+}
 
 struct SolveStats {
     int32_t block_iters = 0, rank0 = 0, deflations = 0, reliable_updates = 0, refine_iters = 0;
@@ -325,87 +337,90 @@ struct SolveStats {
     double est[kS * kS] = {};
 };
 
-// Initial deflated QR of B (plane layout FP64, ld m): CGS2 column by column.
-// Leaves V_1 (iteration precision, ld m1) in V[0] and rho in the small state.
-int initial_qr(SolveCtx &c, int *m1_out) {
-    dsbcg_ctx *h = c.h;
-    const int m = c.m;
-    Ts ts{h, true, c.st, c.n};
+// Initial deflated QR of B (column-major FP64 in h->Bint): classical
+// Gram-Schmidt applied twice, column by column, in column order.  Column l is
+// dropped when its remainder is <= tau_B ||b_l|| (deflation, Sec. 1 and the
+// deflated block Lanczos process of Sec. 3).  Leaves V_1 (FP64, m1 columns)
+// in h->V[0] and rho in the small state.
+int initial_qr(dsbcg_ctx *h, int m, double tau_B, hipStream_t st, int *m1_out) {
+    const int64_t n = 12 * (int64_t)h->g.V;
+    Ts ts{h, true, st, n};
     SmallState *S = stp(h);
     StepReport *rep = repp(h);
-    // ||b_l|| from the diagonal of B^H B
-    {
-        TsArgs a = ts_args();
-        a.K = 1;
-        a.X[0] = h->Bint.p; a.ldx[0] = m; a.bx[0] = m; a.C[0] = nullptr;
-        a.bout = m;
-        a.gram = 1;
-        CHK(ts.run_reduce(a, m, 0));
-        PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_bnorms(S, rep, red_slot(h, 0), m, c.st));
-    }
-    int k = 0;
     zd *Qp = (zd *)h->Q.p;
     zd *Bp = (zd *)h->Bint.p;
     zd *wp = (zd *)h->wbuf.p;
+    // ||b_l|| from the diagonal of B^H B
+    {
+        TsArgs a = ts_args(n);
+        a.K = 1;
+        a.X[0] = Bp; a.bx[0] = m; a.C[0] = nullptr;
+        a.bout = m;
+        a.gram = 1;
+        CHK(ts.run_reduce(a, m, 0));
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_bnorms(S, rep, red_slot(h, 0), m, st));
+    }
+    int k = 0;
     for (int l = 0; l < m; ++l) {
+        const zd *bl = Bp + (int64_t)l * n;
         if (k > 0) {
             // c1 = Q^H b_l
-            TsArgs a = ts_args();
+            TsArgs a = ts_args(n);
             a.K = 1;
-            a.X[0] = Bp + l; a.ldx[0] = m; a.bx[0] = 1; a.C[0] = nullptr;
+            a.X[0] = bl; a.bx[0] = 1; a.C[0] = nullptr;
             a.bout = 1;
-            a.gram = 2; a.L = Qp; a.ldl = m; a.bl = k;
+            a.gram = 2; a.L = Qp; a.bl = k;
             CHK(ts.run_reduce(a, k, 1));
-            PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_neg_column(S, 0, red_slot(h, 1), k, c.st));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st, small_neg_column(S, 0, red_slot(h, 1), k, st));
             // w = b_l - Q c1, c2 = Q^H w
-            a = ts_args();
+            a = ts_args(n);
             a.K = 2;
-            a.X[0] = Bp + l; a.ldx[0] = m; a.bx[0] = 1; a.C[0] = nullptr;
-            a.X[1] = Qp; a.ldx[1] = m; a.bx[1] = k; a.C[1] = coef_slot(h, 0);
+            a.X[0] = bl; a.bx[0] = 1; a.C[0] = nullptr;
+            a.X[1] = Qp; a.bx[1] = k; a.C[1] = coef_slot(h, 0);
             a.bout = 1;
-            a.out = wp; a.ldo = 1;
-            a.gram = 2; a.L = Qp; a.ldl = m; a.bl = k;
+            a.out = wp;
+            a.gram = 2; a.L = Qp; a.bl = k;
             CHK(ts.run_reduce(a, k, 2));
-            PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_neg_column(S, 1, red_slot(h, 2), k, c.st));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st, small_neg_column(S, 1, red_slot(h, 2), k, st));
             // w = w - Q c2, ||w||^2
-            a = ts_args();
+            a = ts_args(n);
             a.K = 2;
-            a.X[0] = wp; a.ldx[0] = 1; a.bx[0] = 1; a.C[0] = nullptr;
-            a.X[1] = Qp; a.ldx[1] = m; a.bx[1] = k; a.C[1] = coef_slot(h, 1);
+            a.X[0] = wp; a.bx[0] = 1; a.C[0] = nullptr;
+            a.X[1] = Qp; a.bx[1] = k; a.C[1] = coef_slot(h, 1);
             a.bout = 1;
-            a.out = wp; a.ldo = 1;
+            a.out = wp;
             a.gram = 1;
             CHK(ts.run_reduce(a, 1, 3));
-            PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_cgs_decide(S, rep, red_slot(h, 1), red_slot(h, 2), red_slot(h, 3), k, l,
-                                    c.o.tau_B, c.st));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        small_cgs_decide(S, rep, red_slot(h, 1), red_slot(h, 2), red_slot(h, 3), k, l,
+                                         tau_B, st));
         } else {
-            TsArgs a = ts_args();
+            TsArgs a = ts_args(n);
             a.K = 1;
-            a.X[0] = Bp + l; a.ldx[0] = m; a.bx[0] = 1; a.C[0] = nullptr;
+            a.X[0] = bl; a.bx[0] = 1; a.C[0] = nullptr;
             a.bout = 1;
-            a.out = wp; a.ldo = 1;
+            a.out = wp;
             a.gram = 1;
             CHK(ts.run_reduce(a, 1, 3));
-            PROF_LAUNCH(c.h, kProfSmall, 0.0, c.st, small_cgs_decide(S, rep, nullptr, nullptr, red_slot(h, 3), 0, l, c.o.tau_B, c.st));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        small_cgs_decide(S, rep, nullptr, nullptr, red_slot(h, 3), 0, l, tau_B, st));
         }
-        CHK(read_report(h, c.st));
+        CHK(read_report(h, st));
         if (h->rep_host->flags & kFlagNonFinite)
             return fail(DSBCG_ERR_NOT_HPD, "B holds non-finite values");
         if (h->rep_host->scalar[1] > 0.5) {
             // Q[:, k] = w / ||w||
-            TsArgs a = ts_args();
+            TsArgs a = ts_args(n);
             a.K = 1;
-            a.X[0] = wp; a.ldx[0] = 1; a.bx[0] = 1; a.C[0] = coef_slot(h, 3);
+            a.X[0] = wp; a.bx[0] = 1; a.C[0] = coef_slot(h, 3);
             a.bout = 1;
-            a.out = Qp + k; a.ldo = m;
+            a.out = Qp + (int64_t)k * n;
             CHK(ts.run(a, nullptr));
             ++k;
         }
     }
-    // V_1 = Q[:, :k] with leading dimension k, in the iteration precision
     if (k > 0)
-        PROF_LAUNCH(c.h, kProfConvert, copy_bytes(c.V, k, (true) ? 16 : 8, (c.fp64) ? 16 : 8, false), c.st, copy_field(true, c.fp64, c.V, k, Qp, m, kPlane, 0, h->V[0].p, k, kPlane, false, 1.0,
-                          c.st));
+        HIPCHK(hipMemcpyAsync(h->V[0].p, Qp, (size_t)n * k * sizeof(zd), hipMemcpyDeviceToDevice, st));
     *m1_out = k;
     return DSBCG_OK;
 }
@@ -413,7 +428,8 @@ int initial_qr(SolveCtx &c, int *m1_out) {
 int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
     StepReport *rep = repp(h);
     HIPCHK(hipMemsetAsync(&rep->flags, 0, sizeof(int32_t), st));
-    PROF_LAUNCH(h, kProfConvert, (double)h->g.V * 72 * 8, st, find_nonfinite((const double *)U, (int64_t)h->g.V * 72, &rep->flags, st));
+    PROF_LAUNCH(h, kProfConvert, (double)h->g.V * 72 * 8, st,
+                find_nonfinite((const double *)U, (int64_t)h->g.V * 72, &rep->flags, st));
     int32_t flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, &rep->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -422,22 +438,25 @@ int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
 }
 
 // True relative residuals ||b_l - (sigma_j + A) x_{l,j}|| / ||b_l|| in FP64 for
-// every shift; B and X in API layout.  With keep_j >= 0 the residual block of
-// that shift is also stored (API layout) in Rkeep.
-int true_residuals(dsbcg_ctx *h, hipStream_t st, const void *U64, double kappa, const void *Bapi,
-                   const void *Xapi, int m, const double *sigma, int s, double *out, int keep_j,
-                   void *Rkeep) {
+// every shift (Sec. 4: relative residual); B and X in the caller's layout, the
+// FP64 structure-of-arrays links in h->Ul64.  With keep_j >= 0 only that shift
+// is evaluated and its residual block is stored in Rkeep (caller's layout).
+int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi, const void *Xapi,
+                   int m, const double *sigma, int s, double *out, int keep_j, void *Rkeep) {
     const int64_t n = 12 * (int64_t)h->g.V;
-    const int64_t api_site = 12 * (int64_t)m, api_comp = m;
+    const size_t blk = (size_t)n * m * sizeof(zd);
     CHK(ensure_common(h));
-    CHK(ensure(h->Rf64a, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->Rf64b, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->R0, blk));
+    CHK(ensure(h->R1, blk));
+    CHK(ensure(h->R2, blk));
+    CHK(ensure(h->R3, blk));
     Ts ts{h, true, st, n};
+    CHK(copy(h, m, api(Bapi, m), cm(h->R0.p, n, true), false, st));
     std::vector<double> bn(m);
     {
-        TsArgs a = ts_args();
+        TsArgs a = ts_args(n);
         a.K = 1;
-        a.X[0] = Bapi; a.ldx[0] = m; a.bx[0] = m; a.C[0] = nullptr;
+        a.X[0] = h->R0.p; a.bx[0] = m; a.C[0] = nullptr;
         a.bout = m;
         a.gram = 1;
         CHK(ts.run_reduce(a, m, 4));
@@ -449,25 +468,16 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, const void *U64, double kappa, 
     std::vector<zd> cf(512, mk<double>(0, 0));
     for (int j = 0; j < s; ++j) {
         if (keep_j >= 0 && j != keep_j) continue;
-        const zd *Xj = (const zd *)Xapi + (int64_t)j * n * m;
-        const double sb = stencil_bytes(h->g, m, sizeof(zd));
-        PROF_LAUNCH(h, kProfStencil, sb, st,
-                    wilson_apply(h->g, true, U64, kappa, Xj, api_site, api_comp, h->Rf64a.p,
-                                 api_site, api_comp, m, false, h->lds_links, st));
-        PROF_LAUNCH(h, kProfStencil, sb, st,
-                    wilson_apply(h->g, true, U64, kappa, h->Rf64a.p, api_site, api_comp,
-                                 h->Rf64b.p, api_site, api_comp, m, true, h->lds_links, st));
-        TsArgs a = ts_args();
+        CHK(copy(h, m, api((const zd *)Xapi + (int64_t)j * n * m, m), cm(h->R1.p, n, true), false, st));
+        CHK(apply_A_cm(h, true, h->Ul64.p, kappa, h->R1.p, h->R2.p, h->R3.p, m, st));
+        TsArgs a = ts_args(n);
         a.K = 3;
-        a.X[0] = Bapi; a.ldx[0] = m; a.bx[0] = m; a.C[0] = nullptr;
-        a.X[1] = Xj; a.ldx[1] = m; a.bx[1] = m; a.C[1] = coef_slot(h, 2);
-        a.X[2] = h->Rf64b.p; a.ldx[2] = m; a.bx[2] = m; a.C[2] = coef_slot(h, 3);
+        a.X[0] = h->R0.p; a.bx[0] = m; a.C[0] = nullptr;
+        a.X[1] = h->R1.p; a.bx[1] = m; a.C[1] = coef_slot(h, 2);
+        a.X[2] = h->R3.p; a.bx[2] = m; a.C[2] = coef_slot(h, 3);
         a.bout = m;
         a.gram = 1;
-        if (keep_j >= 0) {
-            a.out = Rkeep;
-            a.ldo = m;
-        }
+        if (keep_j >= 0) a.out = h->R2.p;
         // coefficient matrices -sigma_j I and -I
         for (int l = 0; l < m; ++l) {
             cf[l * 16 + l] = mk<double>(-sigma[j], 0);
@@ -476,6 +486,7 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, const void *U64, double kappa, 
         HIPCHK(hipMemcpyAsync((void *)coef_slot(h, 2), cf.data(), 512 * sizeof(zd),
                               hipMemcpyHostToDevice, st));
         CHK(ts.run_reduce(a, m, 5));
+        if (keep_j >= 0) CHK(copy(h, m, cm(h->R2.p, n, true), api(Rkeep, m), false, st));
         std::vector<zd> g(256);
         HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 5), 256 * sizeof(zd), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -484,6 +495,257 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, const void *U64, double kappa, 
             out[j * m + l] = bn[l] > 0 ? r / bn[l] : 0.0;
         }
     }
+    return DSBCG_OK;
+}
+
+// Buffers of one working precision.
+struct WorkSet {
+    void *V[3];
+    void *T, *W;
+    void *P[2];
+    void *X;            // solution accumulator [s][m][n]
+    const void *Ul;     // structure-of-arrays links
+    const void *N, *M;  // per-shift coefficients in this precision
+    bool fp64;
+    size_t esz;
+};
+
+// The DSBlockCG iteration.  FP64 form: every vector in FP64.  FP32 form: the
+// iteration starts in FP64 and continues the same recurrences with FP32
+// vectors once every active estimate is <= switch_at; from then on
+// X_j = X_hi + X_lo with X_lo in FP32, added into the FP64 X_hi every
+// ru_interval steps and at the end.  Writes the iterates to Xapi
+// ([s][V][4][3][m], FP64).  The FP64 links must be in h->Ul64 (and the FP32
+// links in h->Ul32 for the FP32 form).
+int solve_core(dsbcg_ctx *h, double kappa, const void *B, int m, const double *sigma, int s,
+               double tol, const dsbcg_opts &o, double switch_at, void *Xapi, SolveStats &stt,
+               hipStream_t st) {
+    const int64_t V = h->g.V, n = 12 * V;
+    const bool form32 = o.precision == DSBCG_FP32_RELIABLE;
+
+    CHK(ensure_common(h));
+    CHK(ensure(h->Bint, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->Q, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
+    CHK(ensure(h->V[0], (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->X, (size_t)n * m * s * sizeof(zd)));
+
+    SmallState *S = stp(h);
+    StepReport *rep = repp(h);
+    HIPCHK(hipMemsetAsync(rep, 0, sizeof(StepReport), st));
+    HIPCHK(hipMemsetAsync(h->X.p, 0, (size_t)n * m * s * sizeof(zd), st));
+    CHK(copy(h, m, api(B, m), cm(h->Bint.p, n, true), false, st));
+
+    int m1 = 0;
+    CHK(initial_qr(h, m, o.tau_B, st, &m1));
+    stt.rank0 = m1;
+    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, st));
+    CHK(read_report(h, st));
+
+    // widths never exceed m1 after the initial deflation
+    const int wmax = std::max(m1, 1);
+    const size_t b64 = (size_t)n * wmax * sizeof(zd), b32 = (size_t)n * wmax * sizeof(zf);
+    for (int k = 0; k < 3; ++k) CHK(ensure(h->V[k], std::max(b64, (size_t)n * m * sizeof(zd))));
+    CHK(ensure(h->T, b64));
+    CHK(ensure(h->W, b64));
+    CHK(ensure(h->P[0], b64 * s));
+    CHK(ensure(h->P[1], b64 * s));
+    WorkSet w64{{h->V[0].p, h->V[1].p, h->V[2].p}, h->T.p, h->W.p, {h->P[0].p, h->P[1].p}, h->X.p,
+                h->Ul64.p, S->N, S->M, true, sizeof(zd)};
+    WorkSet w32{};
+    if (form32) {
+        for (int k = 0; k < 3; ++k) CHK(ensure(h->V32[k], b32));
+        CHK(ensure(h->T32, b32));
+        CHK(ensure(h->W32, b32));
+        CHK(ensure(h->P32[0], b32 * s));
+        CHK(ensure(h->P32[1], b32 * s));
+        CHK(ensure(h->Xlo, (size_t)n * m * s * sizeof(zf)));
+        w32 = WorkSet{{h->V32[0].p, h->V32[1].p, h->V32[2].p}, h->T32.p, h->W32.p,
+                      {h->P32[0].p, h->P32[1].p}, h->Xlo.p, h->Ul32.p, S->N32, S->M32, false, sizeof(zf)};
+    }
+    WorkSet *ws = &w64;
+    bool lo = false;
+    int since_flush = 0;
+
+    int b = m1, bp = 0;
+    int cur = 0, prev = 2, next = 1;
+    int pcur = 0;  // P buffer holding P_{j,i-1}
+    int status = DSBCG_OK;
+    int iters = 0;
+    const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
+    std::vector<int32_t> act;
+
+    auto active_list = [&](void) {
+        act.clear();
+        for (int j = 0; j < s; ++j)
+            if (h->rep_host->colmask[j]) act.push_back(j);
+    };
+    auto max_active_est = [&](void) {
+        double e = 0.0;
+        for (int j : act)
+            for (int l = 0; l < m; ++l)
+                if ((h->rep_host->colmask[j] >> l) & 1u) e = std::max(e, h->rep_host->est[j][l]);
+        return e;
+    };
+    auto flush = [&](void) -> int {
+        // X_hi += X_lo, X_lo = 0 (FP64 accumulation of the solution)
+        CHK(copy(h, m * s, cm(h->Xlo.p, n, false), cm(h->X.p, n, true), true, st));
+        HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
+        since_flush = 0;
+        stt.reliable_updates += 1;
+        return DSBCG_OK;
+    };
+    active_list();
+    bool done = (m1 == 0) || (act.empty() && o.fixed_iters <= 0);
+
+    for (int i = 1; !done && i <= steps; ++i) {
+        if (form32 && !lo && max_active_est() <= switch_at) {
+            // continue the same recurrences with FP32 vectors
+            CHK(copy(h, b, cm(w64.V[cur], n, true), cm(w32.V[cur], n, false), false, st));
+            if (i > 1) {
+                CHK(copy(h, bp, cm(w64.V[prev], n, true), cm(w32.V[prev], n, false), false, st));
+                for (int j : act)
+                    CHK(copy(h, bp, cm((zd *)w64.P[pcur] + (int64_t)j * n * wmax, n, true),
+                             cm((zf *)w32.P[pcur] + (int64_t)j * n * wmax, n, false), false, st));
+            }
+            HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
+            ws = &w32;
+            lo = true;
+            since_flush = 0;
+            stt.switch_iter = i;
+        }
+        const bool f64 = ws->fp64;
+        Ts ts{h, f64, st, n};
+        iters = i;
+        stt.mvms += b;
+        void *Vc = ws->V[cur], *Vp = ws->V[prev], *Vn = ws->V[next];
+        // W = A V_i
+        CHK(apply_A_cm(h, f64, ws->Ul, kappa, Vc, ws->T, ws->W, b, st));
+        // alpha_i = V_i^H (W - V_{i-1} beta_i^H)
+        {
+            TsArgs a = ts_args(n);
+            a.K = (i > 1) ? 2 : 1;
+            a.X[0] = ws->W; a.bx[0] = b; a.C[0] = nullptr;
+            a.X[1] = Vp; a.bx[1] = bp; a.C[1] = coef_slot(h, 0);
+            a.bout = b;
+            a.gram = 2; a.L = Vc; a.bl = b;
+            CHK(ts.run_reduce(a, b, 0));
+        }
+        // hermitised alpha_i, -alpha_i as a coefficient
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_prep_alpha(S, red_slot(h, 0), st));
+        // per-shift coefficients and P_j / X_j updates
+        for (size_t q = 0; q < act.size(); ++q) h->list_host[q] = act[q];
+        HIPCHK(hipMemcpyAsync(h->list.p, h->list_host, act.size() * sizeof(int32_t) + 4,
+                              hipMemcpyHostToDevice, st));
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
+                                       (int)act.size(), st));
+        if (!act.empty()) {
+            ShiftArgs sa;
+            sa.nrows = n;
+            sa.V = Vc;
+            sa.b = b;
+            sa.bp = bp;
+            sa.m = m;
+            sa.Pold = ws->P[pcur];
+            sa.Pnew = ws->P[pcur ^ 1];
+            sa.pstride = n * wmax;
+            sa.X = ws->X;
+            sa.xstride = n * m;
+            sa.N = ws->N;
+            sa.M = ws->M;
+            sa.shifts = (const int32_t *)h->list.p;
+            sa.nshift = (int)act.size();
+            sa.colmask = rep->colmask;
+            sa.first = (i == 1);
+            PROF_LAUNCH(h, kProfShift, shift_bytes(sa, f64), st, shift_update(f64, sa, st));
+        }
+        // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
+        {
+            TsArgs a = ts_args(n);
+            a.K = (i > 1) ? 3 : 2;
+            a.X[0] = ws->W; a.bx[0] = b; a.C[0] = nullptr;
+            a.X[1] = Vc; a.bx[1] = b; a.C[1] = coef_slot(h, 1);
+            a.X[2] = Vp; a.bx[2] = bp; a.C[2] = coef_slot(h, 0);
+            a.bout = b;
+            a.out = ws->W;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, b, 1));
+        }
+        // first CholQR pass with deflation
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1),
+                                       lo ? std::max(o.tau_W, 1e-8) : o.tau_W, st));
+        // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new width
+        {
+            TsArgs a = ts_args(n);
+            a.K = 1;
+            a.X[0] = ws->W; a.bx[0] = b; a.C[0] = S->C1;
+            a.bout = b;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, b, 2));
+        }
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
+                                 (int)act.size(), st));
+        // V_{i+1} = W Rinv: the first bnew columns are the new block (the
+        // others are zero and never read)
+        {
+            TsArgs a = ts_args(n);
+            a.K = 1;
+            a.X[0] = ws->W; a.bx[0] = b; a.C[0] = S->Rinv;
+            a.bout = b;
+            a.out = Vn;
+            CHK(ts.run(a, nullptr));
+        }
+        if (lo && ++since_flush >= std::max(1, o.ru_interval)) CHK(flush());
+        CHK(read_report(h, st));
+        const StepReport &R = *h->rep_host;
+        if (R.flags & kFlagNotHPD) {
+            status = fail(DSBCG_ERR_NOT_HPD, "shifted block lost positive definiteness at step " +
+                                                 std::to_string(i) + ": sigma_j I + A is not hpd");
+            break;
+        }
+        if (R.flags & kFlagQR2) {
+            status = fail(DSBCG_ERR_NOT_CONVERGED,
+                          "orthonormalisation of the Lanczos block failed at step " + std::to_string(i));
+            break;
+        }
+        const int bnew = R.bnew;
+        stt.deflations += b - bnew;
+        active_list();
+        if (bnew == 0) done = true;
+        if (o.fixed_iters <= 0 && act.empty()) done = true;
+        // rotate the three-block window
+        const int old_prev = prev;
+        prev = cur;
+        cur = next;
+        next = old_prev;
+        pcur ^= 1;
+        bp = b;
+        b = bnew;
+        stt.final_width = bnew;
+    }
+    if (lo) CHK(flush());
+    stt.block_iters += iters;
+    if (status == DSBCG_OK && !done && o.fixed_iters <= 0)
+        status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
+    // iterates to the caller's layout
+    for (int j = 0; j < s; ++j)
+        CHK(copy(h, m, cm((zd *)h->X.p + (int64_t)j * n * m, n, true),
+                 api((zd *)Xapi + (int64_t)j * n * m, m), false, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int j = 0; j < s; ++j)
+        for (int l = 0; l < m; ++l) stt.est[j * m + l] = h->rep_host->est[j][l];
+    return status;
+}
+
+int check_field_args(dsbcg_handle h, const void *U, const void *X, const void *Y, int32_t m,
+                     double kappa) {
+    if (!h || !U || !X || !Y) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
+    if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
+    if (X == Y) return fail(DSBCG_ERR_ARG, "Y must not alias X");
     return DSBCG_OK;
 }
 
@@ -497,11 +759,11 @@ void dsbcg_default_opts(dsbcg_opts *o) {
     o->max_iters = 10000;
     o->fixed_iters = 0;
     o->ru_interval = 50;
-    o->tau_B = -1.0;  // resolved to 0.1 * tol
-    o->tau_W = -1.0;  // resolved to 1e-12
+    o->tau_B = -1.0;      // resolved to 0.1 * tol
+    o->tau_W = -1.0;      // resolved to 1e-12
     o->refine = 1;
     o->freeze = 1;
-    o->switch_at = -1.0;  // resolved to min(1e-2, 1e6 * tol)
+    o->switch_at = -1.0;  // resolved to min(1e-2, 1e5 * tol)
 }
 
 const char *dsbcg_last_error(void) { return g_err.c_str(); }
@@ -547,8 +809,6 @@ int dsbcg_create(const int32_t *L, dsbcg_handle *out) {
         delete h;
         return fail(DSBCG_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
-    const char *v = getenv("DSBCG_LDS_LINKS");
-    if (v && v[0] == '0') h->lds_links = false;
     *out = h;
     return DSBCG_OK;
 }
@@ -569,334 +829,36 @@ int dsbcg_neighbors(dsbcg_handle h, int32_t *host_out) {
 
 int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y, int32_t m,
                   int32_t dagger, dsbcg_stream stream) {
-    if (!h || !U || !X || !Y) return fail(DSBCG_ERR_ARG, "NULL argument");
-    if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
-    if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
-    if (X == Y) return fail(DSBCG_ERR_ARG, "Y must not alias X");
+    CHK(check_field_args(h, U, X, Y, m, kappa));
     hipStream_t st = (hipStream_t)stream;
-    PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, m, sizeof(zd)), st,
-                wilson_apply(h->g, true, U, kappa, X, 12 * (int64_t)m, m, Y, 12 * (int64_t)m, m, m,
-                             dagger != 0, h->lds_links, st));
+    const int64_t n = 12 * (int64_t)h->g.V;
+    CHK(ensure(h->Xin, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->Yout, (size_t)n * m * sizeof(zd)));
+    CHK(prepare_links(h, U, true, st));
+    CHK(copy(h, m, api(X, m), cm(h->Xin.p, n, true), false, st));
+    CHK(stencil(h, true, h->Ul64.p, kappa, h->Xin.p, h->Yout.p, m, dagger != 0, st));
+    CHK(copy(h, m, cm(h->Yout.p, n, true), api(Y, m), false, st));
     return DSBCG_OK;
 }
 
 int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y, int32_t m,
                   int32_t precision, dsbcg_stream stream) {
-    if (!h || !U || !X || !Y) return fail(DSBCG_ERR_ARG, "NULL argument");
-    if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
-    if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
-    if (X == Y) return fail(DSBCG_ERR_ARG, "Y must not alias X");
+    CHK(check_field_args(h, U, X, Y, m, kappa));
     if (precision != DSBCG_FP64 && precision != DSBCG_FP32_RELIABLE)
         return fail(DSBCG_ERR_ARG, "unknown precision");
     hipStream_t st = (hipStream_t)stream;
-    const int64_t V = h->g.V, n = 12 * V;
-    const int64_t api_site = 12 * (int64_t)m, api_comp = m;
-    if (precision == DSBCG_FP64) {
-        CHK(ensure(h->T, (size_t)n * m * sizeof(zd)));
-        const double sb = stencil_bytes(h->g, m, sizeof(zd));
-        PROF_LAUNCH(h, kProfStencil, sb, st,
-                    wilson_apply(h->g, true, U, kappa, X, api_site, api_comp, h->T.p, api_site,
-                                 api_comp, m, false, h->lds_links, st));
-        PROF_LAUNCH(h, kProfStencil, sb, st,
-                    wilson_apply(h->g, true, U, kappa, h->T.p, api_site, api_comp, Y, api_site,
-                                 api_comp, m, true, h->lds_links, st));
-        return DSBCG_OK;
-    }
-    // FP32: round links and X, apply in FP32 (plane layout), widen the result
-    CHK(ensure(h->U32, (size_t)V * 36 * sizeof(zf)));
-    CHK(ensure(h->X32in, (size_t)n * m * sizeof(zf)));
-    CHK(ensure(h->T, (size_t)n * m * sizeof(zf)));
-    CHK(ensure(h->W, (size_t)n * m * sizeof(zf)));
-    // links: [V][4][3][3] has the same shape as a [V*3][.][12] field... copy flat
-    PROF_LAUNCH(h, kProfConvert, copy_bytes(V * 3, 1, (true) ? 16 : 8, (false) ? 16 : 8, false), st, copy_field(true, false, V * 3, 1, U, 1, kPlane, 0, h->U32.p, 1, kPlane, false, 1.0, st));
-    PROF_LAUNCH(h, kProfConvert, copy_bytes(V, m, (true) ? 16 : 8, (false) ? 16 : 8, false), st, copy_field(true, false, V, m, X, m, kApi, 0, h->X32in.p, m, kPlane, false, 1.0, st));
-    CHK(apply_A_plane(h, false, h->U32.p, kappa, h->X32in.p, h->T.p, h->W.p, m, st));
-    PROF_LAUNCH(h, kProfConvert, copy_bytes(V, m, (false) ? 16 : 8, (true) ? 16 : 8, false), st, copy_field(false, true, V, m, h->W.p, m, kPlane, 0, Y, m, kApi, false, 1.0, st));
+    const bool f64 = precision == DSBCG_FP64;
+    const int64_t n = 12 * (int64_t)h->g.V;
+    const size_t esz = f64 ? sizeof(zd) : sizeof(zf);
+    CHK(ensure(h->Xin, (size_t)n * m * esz));
+    CHK(ensure(h->Yout, (size_t)n * m * esz));
+    CHK(ensure(h->T, (size_t)n * m * esz));
+    CHK(prepare_links(h, U, f64, st));
+    CHK(copy(h, m, api(X, m), cm(h->Xin.p, n, f64), false, st));
+    CHK(apply_A_cm(h, f64, f64 ? h->Ul64.p : h->Ul32.p, kappa, h->Xin.p, h->T.p, h->Yout.p, m, st));
+    CHK(copy(h, m, cm(h->Yout.p, n, f64), api(Y, m), false, st));
     return DSBCG_OK;
 }
-
-}  // extern "C"
-
-namespace {
-
-// Buffers of one working precision.
-struct WorkSet {
-    void *V[3];
-    void *T, *W;
-    void *P[2];
-    void *X;            // solution accumulator, plane layout, leading dimension m
-    const void *U;      // links
-    const void *N, *M;  // per-shift coefficients in this precision
-    bool fp64;
-    size_t esz;
-};
-
-int convert_block(dsbcg_ctx *h, int64_t V, int cols, const void *in, bool in64, void *out, bool out64,
-                  hipStream_t st) {
-    if (cols <= 0) return DSBCG_OK;
-    PROF_LAUNCH(h, kProfConvert, copy_bytes(V, cols, in64 ? 16 : 8, out64 ? 16 : 8, false), st,
-                copy_field(in64, out64, V, cols, in, cols, kPlane, 0, out, cols, kPlane, false, 1.0, st));
-    return DSBCG_OK;
-}
-
-// The DSBlockCG iteration.  FP64 form: every vector in FP64.  FP32 form: the
-// iteration starts in FP64 and continues with FP32 vectors once every active
-// estimate is <= switch_at; from then on X_j = X_hi + X_lo with X_lo in FP32,
-// flushed into the FP64 X_hi every ru_interval steps and at the end.
-// Writes the iterates to Xapi ([s][V][4][3][m], FP64).
-int solve_core(dsbcg_ctx *h, const void *U, double kappa, const void *B, int m, const double *sigma,
-               int s, double tol, const dsbcg_opts &o, double switch_at, void *Xapi,
-               SolveStats &stt, hipStream_t st) {
-    SolveCtx c;
-    c.h = h;
-    c.st = st;
-    c.fp64 = true;
-    c.esz = sizeof(zd);
-    c.V = h->g.V;
-    c.n = 12 * c.V;
-    c.m = m;
-    c.s = s;
-    c.kappa = kappa;
-    c.tol = tol;
-    c.o = o;
-    c.Ulinks = U;
-    const int64_t n = c.n;
-    const bool form32 = o.precision == DSBCG_FP32_RELIABLE;
-
-    CHK(ensure_common(h));
-    CHK(ensure(h->Bint, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->Q, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
-    CHK(ensure(h->V[0], (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->X, (size_t)n * m * s * sizeof(zd)));
-
-    SmallState *S = stp(h);
-    StepReport *rep = repp(h);
-    CHK(check_finite_links(h, U, st));
-    HIPCHK(hipMemsetAsync(rep, 0, sizeof(StepReport), st));
-    HIPCHK(hipMemsetAsync(h->X.p, 0, (size_t)n * m * s * sizeof(zd), st));
-    PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m, 16, 16, false), st,
-                copy_field(true, true, c.V, m, B, m, kApi, 0, h->Bint.p, m, kPlane, false, 1.0, st));
-
-    int m1 = 0;
-    CHK(initial_qr(c, &m1));
-    stt.rank0 = m1;
-    PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, st));
-    CHK(read_report(h, st));
-
-    // widths never exceed m1 after the initial deflation
-    const int wmax = std::max(m1, 1);
-    const size_t b64 = (size_t)n * wmax * sizeof(zd), b32 = (size_t)n * wmax * sizeof(zf);
-    for (int k = 0; k < 3; ++k) CHK(ensure(h->V[k], std::max(b64, (size_t)n * m * sizeof(zd))));
-    CHK(ensure(h->T, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->W, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->P[0], b64 * s));
-    CHK(ensure(h->P[1], b64 * s));
-    WorkSet w64{{h->V[0].p, h->V[1].p, h->V[2].p}, h->T.p, h->W.p, {h->P[0].p, h->P[1].p}, h->X.p,
-                U, S->N, S->M, true, sizeof(zd)};
-    WorkSet w32{};
-    if (form32) {
-        CHK(ensure(h->U32, (size_t)c.V * 36 * sizeof(zf)));
-        for (int k = 0; k < 3; ++k) CHK(ensure(h->V32[k], b32));
-        CHK(ensure(h->T32, b32));
-        CHK(ensure(h->W32, b32));
-        CHK(ensure(h->P32[0], b32 * s));
-        CHK(ensure(h->P32[1], b32 * s));
-        CHK(ensure(h->Xlo, (size_t)n * m * s * sizeof(zf)));
-        PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V * 3, 1, 16, 8, false), st,
-                    copy_field(true, false, c.V * 3, 1, U, 1, kPlane, 0, h->U32.p, 1, kPlane, false, 1.0, st));
-        w32 = WorkSet{{h->V32[0].p, h->V32[1].p, h->V32[2].p}, h->T32.p, h->W32.p,
-                      {h->P32[0].p, h->P32[1].p}, h->Xlo.p, h->U32.p, S->N32, S->M32, false, sizeof(zf)};
-    }
-    WorkSet *ws = &w64;
-    bool lo = false;
-    int since_flush = 0;
-
-    int b = m1, bp = 0;
-    int cur = 0, prev = 2, next = 1;
-    int pcur = 0;  // P buffer holding P_{j,i-1}
-    int status = DSBCG_OK;
-    int iters = 0;
-    const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
-    std::vector<int32_t> act;
-
-    auto active_list = [&](void) {
-        act.clear();
-        for (int j = 0; j < s; ++j)
-            if (h->rep_host->colmask[j]) act.push_back(j);
-    };
-    auto max_active_est = [&](void) {
-        double e = 0.0;
-        for (int j : act)
-            for (int l = 0; l < m; ++l)
-                if ((h->rep_host->colmask[j] >> l) & 1u) e = std::max(e, h->rep_host->est[j][l]);
-        return e;
-    };
-    auto flush = [&](void) -> int {
-        // X_hi += X_lo, X_lo = 0 (FP64 solution accumulation)
-        PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m * s, 8, 16, true), st,
-                    copy_field(false, true, c.V, m * s, h->Xlo.p, m * s, kPlane, 0, h->X.p, m * s,
-                               kPlane, true, 1.0, st));
-        HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
-        since_flush = 0;
-        stt.reliable_updates += 1;
-        return DSBCG_OK;
-    };
-    active_list();
-    bool done = (m1 == 0) || (act.empty() && o.fixed_iters <= 0);
-
-    for (int i = 1; !done && i <= steps; ++i) {
-        if (form32 && !lo && max_active_est() <= switch_at) {
-            // continue the same recurrences with FP32 vectors
-            CHK(convert_block(h, c.V, b, w64.V[cur], true, w32.V[cur], false, st));
-            if (i > 1) {
-                CHK(convert_block(h, c.V, bp, w64.V[prev], true, w32.V[prev], false, st));
-                for (int j : act)
-                    CHK(convert_block(h, c.V, bp, (zd *)w64.P[pcur] + (int64_t)j * n * wmax, true,
-                                      (zf *)w32.P[pcur] + (int64_t)j * n * wmax, false, st));
-            }
-            HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
-            ws = &w32;
-            lo = true;
-            since_flush = 0;
-            stt.switch_iter = i;
-        }
-        const bool f64 = ws->fp64;
-        Ts ts{h, f64, st, n};
-        iters = i;
-        stt.mvms += b;
-        void *Vc = ws->V[cur], *Vp = ws->V[prev], *Vn = ws->V[next];
-        // W = A V_i
-        CHK(apply_A_plane(h, f64, ws->U, kappa, Vc, ws->T, ws->W, b, st));
-        // alpha_i = V_i^H (W - V_{i-1} beta_i^H)
-        {
-            TsArgs a = ts_args();
-            a.K = (i > 1) ? 2 : 1;
-            a.X[0] = ws->W; a.ldx[0] = b; a.bx[0] = b; a.C[0] = nullptr;
-            a.X[1] = Vp; a.ldx[1] = bp; a.bx[1] = bp; a.C[1] = coef_slot(h, 0);
-            a.bout = b;
-            a.gram = 2; a.L = Vc; a.ldl = b; a.bl = b;
-            CHK(ts.run_reduce(a, b, 0));
-        }
-        // hermitised alpha_i, -alpha_i as a coefficient
-        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_prep_alpha(S, red_slot(h, 0), st));
-        // per-shift coefficients and P_j / X_j updates
-        for (size_t q = 0; q < act.size(); ++q) h->list_host[q] = act[q];
-        HIPCHK(hipMemcpyAsync(h->list.p, h->list_host, act.size() * sizeof(int32_t) + 4,
-                              hipMemcpyHostToDevice, st));
-        PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                    small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
-                                       (int)act.size(), st));
-        if (!act.empty()) {
-            ShiftArgs sa;
-            sa.nrows = n;
-            sa.V = Vc;
-            sa.b = b;
-            sa.bp = bp;
-            sa.m = m;
-            sa.Pold = ws->P[pcur];
-            sa.Pnew = ws->P[pcur ^ 1];
-            sa.pstride = n * wmax;
-            sa.X = ws->X;
-            sa.xstride = n * m;
-            sa.N = ws->N;
-            sa.M = ws->M;
-            sa.shifts = (const int32_t *)h->list.p;
-            sa.nshift = (int)act.size();
-            sa.colmask = rep->colmask;
-            sa.first = (i == 1);
-            PROF_LAUNCH(h, kProfShift, shift_bytes(sa, f64), st, shift_update(f64, sa, st));
-        }
-        // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
-        {
-            TsArgs a = ts_args();
-            a.K = (i > 1) ? 3 : 2;
-            a.X[0] = ws->W; a.ldx[0] = b; a.bx[0] = b; a.C[0] = nullptr;
-            a.X[1] = Vc; a.ldx[1] = b; a.bx[1] = b; a.C[1] = coef_slot(h, 1);
-            a.X[2] = Vp; a.ldx[2] = bp; a.bx[2] = bp; a.C[2] = coef_slot(h, 0);
-            a.bout = b;
-            a.out = ws->W; a.ldo = b;
-            a.gram = 1;
-            CHK(ts.run_reduce(a, b, 1));
-        }
-        // first CholQR pass with deflation
-        PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                    small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1),
-                                       lo ? std::max(c.o.tau_W, 1e-8) : c.o.tau_W, st));
-        // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new width
-        {
-            TsArgs a = ts_args();
-            a.K = 1;
-            a.X[0] = ws->W; a.ldx[0] = b; a.bx[0] = b; a.C[0] = S->C1;
-            a.bout = b;
-            a.gram = 1;
-            CHK(ts.run_reduce(a, b, 2));
-        }
-        PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                    small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
-                                 (int)act.size(), st));
-        // V_{i+1} = W Rinv (width b, zero columns past the new width)
-        {
-            TsArgs a = ts_args();
-            a.K = 1;
-            a.X[0] = ws->W; a.ldx[0] = b; a.bx[0] = b; a.C[0] = S->Rinv;
-            a.bout = b;
-            a.out = Vn; a.ldo = b;
-            CHK(ts.run(a, nullptr));
-        }
-        if (lo && ++since_flush >= std::max(1, o.ru_interval)) CHK(flush());
-        CHK(read_report(h, st));
-        const StepReport &R = *h->rep_host;
-        if (R.flags & kFlagNotHPD) {
-            status = fail(DSBCG_ERR_NOT_HPD, "shifted block lost positive definiteness at step " +
-                                                 std::to_string(i) + ": sigma_j I + A is not hpd");
-            break;
-        }
-        if (R.flags & kFlagQR2) {
-            status = fail(DSBCG_ERR_NOT_CONVERGED,
-                          "orthonormalisation of the Lanczos block failed at step " + std::to_string(i));
-            break;
-        }
-        const int bnew = R.bnew;
-        stt.deflations += b - bnew;
-        if (bnew > 0 && bnew < b) {
-            // compact V_{i+1} to leading dimension bnew, into the buffer of V_{i-1}
-            PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, bnew, ws->esz, ws->esz, false), st,
-                        copy_field(f64, f64, c.V, bnew, Vn, b, kPlane, 0, Vp, bnew, kPlane, false, 1.0, st));
-            std::swap(prev, next);
-        }
-        active_list();
-        if (bnew == 0) done = true;
-        if (o.fixed_iters <= 0 && act.empty()) done = true;
-        // rotate the three-block window
-        const int old_prev = prev;
-        prev = cur;
-        cur = next;
-        next = old_prev;
-        pcur ^= 1;
-        bp = b;
-        b = bnew;
-        stt.final_width = bnew;
-    }
-    if (lo) CHK(flush());
-    stt.block_iters += iters;
-    if (status == DSBCG_OK && !done && o.fixed_iters <= 0)
-        status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
-    // iterates to the caller's layout
-    for (int j = 0; j < s; ++j)
-        PROF_LAUNCH(h, kProfConvert, copy_bytes(c.V, m, 16, 16, false), st,
-                    copy_field(true, true, c.V, m, (const zd *)h->X.p + (int64_t)j * n * m, m, kPlane, 0,
-                               (zd *)Xapi + (int64_t)j * n * m, m, kApi, false, 1.0, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int j = 0; j < s; ++j)
-        for (int l = 0; l < m; ++l) stt.est[j * m + l] = h->rep_host->est[j][l];
-    return status;
-}
-
-}  // namespace
-
-extern "C" {
 
 int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
                 const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
@@ -916,20 +878,27 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
     if (o.tau_B < 0) o.tau_B = 0.1 * tol;
     if (o.tau_W < 0) o.tau_W = 1e-12;
     if (o.max_iters < 1) o.max_iters = 1;
-    if (o.switch_at < 0) o.switch_at = std::min(1e-2, 1e6 * tol);
+    if (o.switch_at < 0) o.switch_at = std::min(1e-2, 1e5 * tol);
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = 12 * (int64_t)h->g.V;
 
+    CHK(ensure_common(h));
+    CHK(check_finite_links(h, U, st));
+    CHK(prepare_links(h, U, true, st));
+    if (o.precision == DSBCG_FP32_RELIABLE) CHK(prepare_links(h, U, false, st));
+
     SolveStats stt;
-    int status = solve_core(h, U, kappa, B, m, sigma, s, tol, o, o.switch_at, X, stt, st);
+    double stt_main_max = 0.0;
+    int status = solve_core(h, kappa, B, m, sigma, s, tol, o, o.switch_at, X, stt, st);
     if (status != DSBCG_OK && status != DSBCG_ERR_NOT_CONVERGED) return status;
 
     // FP64 true residuals of every system; re-solve the shifts that miss tol
     std::vector<double> tr((size_t)s * m, 0.0);
     const bool want_true = (stats && stats->true_relres) || o.refine;
     if (want_true && status == DSBCG_OK) {
-        CHK(true_residuals(h, st, U, kappa, B, X, m, sigma, s, tr.data(), -1, nullptr));
-        for (int round = 0; o.refine && round < 2; ++round) {
+        CHK(true_residuals(h, st, kappa, B, X, m, sigma, s, tr.data(), -1, nullptr));
+        for (double v : tr) stt_main_max = std::max(stt_main_max, v);
+        for (int round = 0; o.refine && o.fixed_iters <= 0 && round < 2; ++round) {
             bool any = false;
             for (int j = 0; j < s; ++j) {
                 double worst = 0.0;
@@ -940,7 +909,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
                 CHK(ensure(h->Rres, (size_t)n * m * sizeof(zd)));
                 CHK(ensure(h->Xref, (size_t)n * m * sizeof(zd)));
                 std::vector<double> tmp((size_t)s * m);
-                CHK(true_residuals(h, st, U, kappa, B, X, m, sigma, s, tmp.data(), j, h->Rres.p));
+                CHK(true_residuals(h, st, kappa, B, X, m, sigma, s, tmp.data(), j, h->Rres.p));
                 double ratio = 1e300;
                 for (int l = 0; l < m; ++l)
                     if (tr[j * m + l] > 0) ratio = std::min(ratio, 1.0 / tr[j * m + l]);
@@ -950,22 +919,20 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
                 ro.tau_B = 0.1 * tol;
                 SolveStats rs;
                 const double rtol = std::max(0.5 * tol * ratio, 1e-15);
-                int rc = solve_core(h, U, kappa, h->Rres.p, m, &sigma[j], 1, rtol, ro, 0.0, h->Xref.p, rs, st);
+                int rc = solve_core(h, kappa, h->Rres.p, m, &sigma[j], 1, rtol, ro, 0.0, h->Xref.p, rs, st);
                 if (rc != DSBCG_OK && rc != DSBCG_ERR_NOT_CONVERGED) return rc;
                 stt.refine_iters += rs.block_iters;
                 stt.mvms += rs.mvms;
-                PROF_LAUNCH(h, kProfConvert, copy_bytes(h->g.V, m, 16, 16, true), st,
-                            copy_field(true, true, h->g.V, m, h->Xref.p, m, kApi, 0,
-                                       (zd *)X + (int64_t)j * n * m, m, kApi, true, 1.0, st));
+                CHK(copy(h, m, api(h->Xref.p, m), api((zd *)X + (int64_t)j * n * m, m), true, st));
             }
             if (!any) break;
-            CHK(true_residuals(h, st, U, kappa, B, X, m, sigma, s, tr.data(), -1, nullptr));
+            CHK(true_residuals(h, st, kappa, B, X, m, sigma, s, tr.data(), -1, nullptr));
         }
         double worst = 0.0;
         for (double v : tr) worst = std::max(worst, v);
         if (worst > tol && o.fixed_iters <= 0)
-            status = fail(DSBCG_ERR_NOT_CONVERGED, "true relative residual " + std::to_string(worst) +
-                                                       " above tol after refinement");
+            status = fail(DSBCG_ERR_NOT_CONVERGED,
+                          "true relative residual " + std::to_string(worst) + " above tol after refinement");
     }
     if (stats) {
         double *est = stats->est_relres, *tru = stats->true_relres;
@@ -978,6 +945,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
         stats->refine_iters = stt.refine_iters;
         stats->final_width = stt.final_width;
         stats->switch_iter = stt.switch_iter;
+        stats->main_relres_max = stt_main_max;
         stats->mvms = stt.mvms;
     }
     return status;
@@ -985,8 +953,27 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
 
 int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *Psi, int32_t nvec,
                     void *dU, dsbcg_stream stream) {
-    (void)h; (void)kappa; (void)Phi; (void)Psi; (void)nvec; (void)dU; (void)stream;
-    return fail(DSBCG_ERR_ARG, "link gradient not available in this build");
+    if (!h || !Phi || !Psi || !dU) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (nvec < 1 || nvec > DSBCG_MAX_RHS * DSBCG_MAX_SHIFTS)
+        return fail(DSBCG_ERR_ARG, "nvec out of range");
+    if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t V = h->g.V;
+    // the kernel reads both fields column-major; convert in chunks of <= 16 columns
+    const int64_t n = 12 * V;
+    const int chunk = std::min<int>(nvec, 16);
+    CHK(ensure(h->Xin, (size_t)n * chunk * sizeof(zd)));
+    CHK(ensure(h->Yout, (size_t)n * chunk * sizeof(zd)));
+    for (int c0 = 0; c0 < nvec; c0 += chunk) {
+        const int cols = std::min(chunk, nvec - c0);
+        CHK(copy(h, cols, FieldDesc{const_cast<void *>(Phi), kApi, nvec, c0, true},
+                 cm(h->Xin.p, n, true), false, st));
+        CHK(copy(h, cols, FieldDesc{const_cast<void *>(Psi), kApi, nvec, c0, true},
+                 cm(h->Yout.p, n, true), false, st));
+        PROF_LAUNCH(h, kProfGrad, (double)V * (2.0 * 12 * cols + 36.0 * (c0 ? 2 : 1)) * 16, st,
+                    link_grad_apply(h->g, kappa, h->Xin.p, h->Yout.p, cols, dU, c0 > 0, st));
+    }
+    return DSBCG_OK;
 }
 
 }  // extern "C"

@@ -8,12 +8,17 @@
 // the paper stores it as a general sparse matrix (Sec. 4), here it is a
 // matrix-free stencil.
 //
-// One thread computes the 12 spin-colour components of one (site, column)
-// pair.  Each hop first projects the neighbour spinor onto the two-spin
-// subspace of (1 -+ g_mu) (6 complex numbers), multiplies those by the SU(3)
-// link and rebuilds the four spin components from them.  The link matrices
-// of a workgroup's sites are staged once in LDS and shared by the NB columns
-// of each site.
+// Data layout: a block of nb columns is column-major over sites, element
+// (column r, spin-colour c, site x) at (r*12 + c)*V + x; the links are
+// structure-of-arrays, element e of U_mu(x) at (mu*9 + e)*V + x.  A workgroup
+// owns 64 consecutive sites and has one wave per column, so every lane of a
+// wave reads consecutive addresses.  Per direction the 64 forward links
+// U_mu(x) and backward links U_mu(x-mu) of the workgroup are staged once in
+// LDS and shared by all nb columns.
+//
+// Each hop first projects the neighbour spinor onto the two-spin subspace of
+// (1 -+ g_mu) (6 complex numbers), multiplies those by the SU(3) link and
+// rebuilds the four spin components from them.
 //
 // Gamma matrices (chiral basis):
 //   g_x = [[0,0,0,i],[0,0,i,0],[0,-i,0,0],[-i,0,0,0]]
@@ -28,163 +33,92 @@
 // and P commutes with the colour multiply, so U (P p) = P (U p) is formed
 // from U h0 and U h1.
 
+#include "lattice.hpp"
 #include "stencil.hpp"
 
 namespace dsbcg {
 
-__device__ inline void site_coords(const Geom &g, int x, int c[4]) {
-    c[0] = x % g.L[0];
-    x /= g.L[0];
-    c[1] = x % g.L[1];
-    x /= g.L[1];
-    c[2] = x % g.L[2];
-    c[3] = x / g.L[2];
-}
+constexpr int kSitesPerWG = 64;
 
-// Neighbour of site x (coordinates c) one step along mu, forward or backward.
-__device__ inline int hop(const Geom &g, int x, const int c[4], int mu, bool fwd) {
-    int stride = 1;
-    for (int d = 0; d < mu; ++d) stride *= g.L[d];
-    if (fwd) return (c[mu] == g.L[mu] - 1) ? x - (g.L[mu] - 1) * stride : x + stride;
-    return (c[mu] == 0) ? x + (g.L[mu] - 1) * stride : x - stride;
-}
-
-template <typename R, int MU, int S>
-__device__ inline void project(const cx<R> p[4][3], cx<R> h[2][3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (MU == 0) {
-            h[0][a] = (S > 0) ? p[0][a] - mul_i(p[3][a]) : p[0][a] + mul_i(p[3][a]);
-            h[1][a] = (S > 0) ? p[1][a] - mul_i(p[2][a]) : p[1][a] + mul_i(p[2][a]);
-        } else if (MU == 1) {
-            h[0][a] = (S > 0) ? p[0][a] + p[3][a] : p[0][a] - p[3][a];
-            h[1][a] = (S > 0) ? p[1][a] - p[2][a] : p[1][a] + p[2][a];
-        } else if (MU == 2) {
-            h[0][a] = (S > 0) ? p[0][a] - mul_i(p[2][a]) : p[0][a] + mul_i(p[2][a]);
-            h[1][a] = (S > 0) ? p[1][a] + mul_i(p[3][a]) : p[1][a] - mul_i(p[3][a]);
-        } else {
-            h[0][a] = (S > 0) ? p[0][a] - p[2][a] : p[0][a] + p[2][a];
-            h[1][a] = (S > 0) ? p[1][a] - p[3][a] : p[1][a] + p[3][a];
-        }
-    }
-}
-
-template <typename R, int MU, int S>
-__device__ inline void reconstruct_add(cx<R> acc[4][3], const cx<R> u[2][3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        acc[0][a] = acc[0][a] + u[0][a];
-        acc[1][a] = acc[1][a] + u[1][a];
-        if (MU == 0) {
-            acc[2][a] = (S > 0) ? acc[2][a] + mul_i(u[1][a]) : acc[2][a] - mul_i(u[1][a]);
-            acc[3][a] = (S > 0) ? acc[3][a] + mul_i(u[0][a]) : acc[3][a] - mul_i(u[0][a]);
-        } else if (MU == 1) {
-            acc[2][a] = (S > 0) ? acc[2][a] - u[1][a] : acc[2][a] + u[1][a];
-            acc[3][a] = (S > 0) ? acc[3][a] + u[0][a] : acc[3][a] - u[0][a];
-        } else if (MU == 2) {
-            acc[2][a] = (S > 0) ? acc[2][a] + mul_i(u[0][a]) : acc[2][a] - mul_i(u[0][a]);
-            acc[3][a] = (S > 0) ? acc[3][a] - mul_i(u[1][a]) : acc[3][a] + mul_i(u[1][a]);
-        } else {
-            acc[2][a] = (S > 0) ? acc[2][a] - u[0][a] : acc[2][a] + u[0][a];
-            acc[3][a] = (S > 0) ? acc[3][a] - u[1][a] : acc[3][a] + u[1][a];
-        }
-    }
-}
-
-template <typename R>
-__device__ inline void load_spinor(const cx<R> *__restrict__ in, int64_t base, int64_t comp,
-                                   cx<R> p[4][3]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) p[s][a] = in[base + (s * 3 + a) * comp];
-}
-
-// One hop in direction MU with projector sign S: acc += P (W h) where W is
-// the link (ADJ = false) or its adjoint (ADJ = true).
+// One hop: acc += P_s (W psi(y)) with W = link (ADJ false) or link^H.
+// psi is read at site y of column base `col`; the link matrix comes from LDS
+// as lnk[e * 64] for e = 0..8.
 template <typename R, int MU, int S, bool ADJ>
-__device__ inline void hop_term(cx<R> acc[4][3], const cx<R> *__restrict__ lnk,
-                                const cx<R> p[4][3]) {
-    cx<R> h[2][3], u[2][3];
-    project<R, MU, S>(p, h);
+__device__ inline void hop_term(cx<R> acc[4][3], const cx<R> *lnk, const cx<R> *__restrict__ col,
+                                int64_t V, int y) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
+        const int Pt = (MU == 0 || MU == 1) ? 3 - k : 2 + k;  // partner spin of h_k
+        cx<R> h[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const cx<R> pa = col[(int64_t)(k * 3 + a) * V + y];
+            const cx<R> pb = col[(int64_t)(Pt * 3 + a) * V + y];
+            h[a] = (k == 0) ? half<R, MU, S, 0>(pa, pb) : half<R, MU, S, 1>(pa, pb);
+        }
+        cx<R> u[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             cx<R> t = mk<R>(0, 0);
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 if (ADJ)
-                    cmac_conj(t, lnk[b * 3 + a], h[k][b]);
+                    cmac_conj(t, lnk[(b * 3 + a) * kSitesPerWG], h[b]);
                 else
-                    cmac(t, lnk[a * 3 + b], h[k][b]);
+                    cmac(t, lnk[(a * 3 + b) * kSitesPerWG], h[b]);
             }
-            u[k][a] = t;
+            u[a] = t;
         }
-    reconstruct_add<R, MU, S>(acc, u);
-}
-
-template <typename R, int MU, bool DAG, bool LDS>
-__device__ inline void direction(cx<R> acc[4][3], const Geom &g, int x, const int c[4],
-                                 const cx<R> *__restrict__ U, const cx<R> *lf, const cx<R> *lb,
-                                 const cx<R> *__restrict__ in, int64_t in_site, int64_t in_comp,
-                                 int r) {
-    constexpr int SF = DAG ? -1 : 1;  // forward hop uses 1 - SF g_mu
-    cx<R> p[4][3];
-    const int xf = hop(g, x, c, MU, true);
-    load_spinor(in, (int64_t)xf * in_site + r, in_comp, p);
-    hop_term<R, MU, SF, false>(acc, LDS ? lf + MU * 9 : U + ((int64_t)x * 4 + MU) * 9, p);
-    const int xb = hop(g, x, c, MU, false);
-    load_spinor(in, (int64_t)xb * in_site + r, in_comp, p);
-    hop_term<R, MU, -SF, true>(acc, LDS ? lb + MU * 9 : U + ((int64_t)xb * 4 + MU) * 9, p);
-}
-
-template <typename R, int NB, bool LDS>
-struct StencilShape {
-    // sites per workgroup; with LDS staging the links of a site take
-    // 72 complex numbers, so the site count is capped to keep a workgroup's
-    // LDS near 55 KB.
-    static constexpr int cap = LDS ? (sizeof(R) == 8 ? 48 : 96) : 256;
-    static constexpr int want = (256 / NB) > 0 ? 256 / NB : 1;
-    static constexpr int SPW = want < cap ? want : cap;
-    static constexpr int THREADS = SPW * NB;
-};
-
-template <typename R, int NB, bool DAG, bool LDS>
-__global__ __launch_bounds__((StencilShape<R, NB, LDS>::THREADS)) void wilson_kernel(
-    Geom g, const cx<R> *__restrict__ U, R kappa, const cx<R> *__restrict__ in,
-    int64_t in_site, int64_t in_comp, cx<R> *__restrict__ out, int64_t out_site,
-    int64_t out_comp) {
-    using SH = StencilShape<R, NB, LDS>;
-    constexpr int SPW = SH::SPW;
-    __shared__ cx<R> lds_links[LDS ? 2 * SPW * 36 : 1];
-    cx<R> *lf = lds_links;
-    cx<R> *lb = lds_links + (LDS ? SPW * 36 : 0);
-
-    const int s0 = blockIdx.x * SPW;
-    const int nsites = min(SPW, g.V - s0);
-    if (LDS) {
-        // forward links U_mu(x) of this workgroup's sites: one contiguous chunk
-        for (int k = threadIdx.x; k < nsites * 36; k += SH::THREADS)
-            lf[k] = U[(int64_t)s0 * 36 + k];
-        // backward links U_mu(x - mu)
-        for (int k = threadIdx.x; k < nsites * 36; k += SH::THREADS) {
-            const int sl = k / 36, rem = k - sl * 36, mu = rem / 9, e = rem - mu * 9;
-            int c[4];
-            const int x = s0 + sl;
-            site_coords(g, x, c);
-            const int xb = hop(g, x, c, mu, false);
-            lb[k] = U[((int64_t)xb * 4 + mu) * 9 + e];
-        }
-        __syncthreads();
+        if (k == 0)
+            rebuild_add<R, MU, S, 0>(acc, u);
+        else
+            rebuild_add<R, MU, S, 1>(acc, u);
     }
+}
 
-    const int sl = threadIdx.x / NB;
-    const int r = threadIdx.x - sl * NB;
-    if (sl >= nsites) return;
-    const int x = s0 + sl;
-    int c[4];
-    site_coords(g, x, c);
+// Stage U_mu(x) and U_mu(x - mu) of the workgroup's sites in LDS.
+template <typename R>
+__device__ inline void stage_links(cx<R> *lf, cx<R> *lb, const cx<R> *__restrict__ Ul, int64_t V,
+                                   int mu, int x, int xb, bool valid, int lane, int wave, int nwaves) {
+    for (int e = wave; e < 9; e += nwaves) {
+        if (valid) {
+            lf[e * kSitesPerWG + lane] = Ul[(int64_t)(mu * 9 + e) * V + x];
+            lb[e * kSitesPerWG + lane] = Ul[(int64_t)(mu * 9 + e) * V + xb];
+        }
+    }
+}
+
+template <typename R, int MU, bool DAG>
+__device__ inline void direction(cx<R> acc[4][3], const Geom &g, int x, const int c[4],
+                                 const cx<R> *__restrict__ Ul, cx<R> *lf, cx<R> *lb,
+                                 const cx<R> *__restrict__ col, bool valid, int lane, int wave,
+                                 int nwaves) {
+    constexpr int SF = DAG ? -1 : 1;  // forward hop uses 1 - SF g_mu
+    const int xf = valid ? hop(g, x, c, MU, true) : 0;
+    const int xb = valid ? hop(g, x, c, MU, false) : 0;
+    __syncthreads();  // previous direction finished with the LDS links
+    stage_links<R>(lf, lb, Ul, g.V, MU, x, xb, valid, lane, wave, nwaves);
+    __syncthreads();
+    if (!valid) return;
+    hop_term<R, MU, SF, false>(acc, lf + lane, col, g.V, xf);
+    hop_term<R, MU, -SF, true>(acc, lb + lane, col, g.V, xb);
+}
+
+template <typename R, bool DAG>
+__global__ __launch_bounds__(1024) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
+                                                         R kappa, const cx<R> *__restrict__ in,
+                                                         cx<R> *__restrict__ out, int nb) {
+    __shared__ cx<R> lf[9 * kSitesPerWG];
+    __shared__ cx<R> lb[9 * kSitesPerWG];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;  // = column
+    const int nwaves = blockDim.x >> 6;
+    const int x = blockIdx.x * kSitesPerWG + lane;
+    const bool valid = x < g.V && wave < nb;
+    int c[4] = {0, 0, 0, 0};
+    if (valid) site_coords(g, x, c);
+    const int64_t n = 12 * (int64_t)g.V;
+    const cx<R> *col = in + (int64_t)wave * n;
 
     cx<R> acc[4][3];
 #pragma unroll
@@ -192,22 +126,20 @@ __global__ __launch_bounds__((StencilShape<R, NB, LDS>::THREADS)) void wilson_ke
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[s][a] = mk<R>(0, 0);
 
-    const cx<R> *lfs = lf + sl * 36;
-    const cx<R> *lbs = lb + sl * 36;
-    direction<R, 0, DAG, LDS>(acc, g, x, c, U, lfs, lbs, in, in_site, in_comp, r);
-    direction<R, 1, DAG, LDS>(acc, g, x, c, U, lfs, lbs, in, in_site, in_comp, r);
-    direction<R, 2, DAG, LDS>(acc, g, x, c, U, lfs, lbs, in, in_site, in_comp, r);
-    direction<R, 3, DAG, LDS>(acc, g, x, c, U, lfs, lbs, in, in_site, in_comp, r);
+    direction<R, 0, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    direction<R, 1, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    direction<R, 2, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    direction<R, 3, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    if (!valid) return;
 
-    const int64_t ib = (int64_t)x * in_site + r;
-    const int64_t ob = (int64_t)x * out_site + r;
+    cx<R> *oc = out + (int64_t)wave * n;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const cx<R> v = in[ib + (s * 3 + a) * in_comp];
-            out[ob + (s * 3 + a) * out_comp] = mk<R>(v.x - kappa * acc[s][a].x,
-                                                     v.y - kappa * acc[s][a].y);
+            const int64_t idx = (int64_t)(s * 3 + a) * g.V + x;
+            const cx<R> v = col[idx];
+            oc[idx] = mk<R>(v.x - kappa * acc[s][a].x, v.y - kappa * acc[s][a].y);
         }
 }
 
@@ -222,59 +154,52 @@ __global__ void neighbor_kernel(Geom g, int32_t *out) {
     }
 }
 
-template <typename R, int NB, bool LDS>
-static hipError_t launch_nb(const Geom &g, const void *U, double kappa, const void *in,
-                            int64_t in_site, int64_t in_comp, void *out, int64_t out_site,
-                            int64_t out_comp, bool dagger, hipStream_t st) {
-    using SH = StencilShape<R, NB, LDS>;
-    const dim3 grid((g.V + SH::SPW - 1) / SH::SPW);
-    const dim3 block(SH::THREADS);
-    if (dagger)
-        hipLaunchKernelGGL((wilson_kernel<R, NB, true, LDS>), grid, block, 0, st, g,
-                           (const cx<R> *)U, (R)kappa, (const cx<R> *)in, in_site, in_comp,
-                           (cx<R> *)out, out_site, out_comp);
-    else
-        hipLaunchKernelGGL((wilson_kernel<R, NB, false, LDS>), grid, block, 0, st, g,
-                           (const cx<R> *)U, (R)kappa, (const cx<R> *)in, in_site, in_comp,
-                           (cx<R> *)out, out_site, out_comp);
-    return hipGetLastError();
-}
-
-template <typename R, bool LDS>
-static hipError_t launch_prec(const Geom &g, const void *U, double kappa, const void *in,
-                              int64_t in_site, int64_t in_comp, void *out, int64_t out_site,
-                              int64_t out_comp, int nb, bool dagger, hipStream_t st) {
-    switch (nb) {
-#define DSBCG_NB_CASE(N)                                                                  \
-    case N:                                                                               \
-        return launch_nb<R, N, LDS>(g, U, kappa, in, in_site, in_comp, out, out_site,     \
-                                    out_comp, dagger, st);
-        DSBCG_NB_CASE(1) DSBCG_NB_CASE(2) DSBCG_NB_CASE(3) DSBCG_NB_CASE(4)
-        DSBCG_NB_CASE(5) DSBCG_NB_CASE(6) DSBCG_NB_CASE(7) DSBCG_NB_CASE(8)
-        DSBCG_NB_CASE(9) DSBCG_NB_CASE(10) DSBCG_NB_CASE(11) DSBCG_NB_CASE(12)
-        DSBCG_NB_CASE(13) DSBCG_NB_CASE(14) DSBCG_NB_CASE(15) DSBCG_NB_CASE(16)
-#undef DSBCG_NB_CASE
-        default:
-            return hipErrorInvalidValue;
+hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, const void *in,
+                        void *out, int nb, bool dagger, hipStream_t st) {
+    if (nb < 1 || nb > 16) return hipErrorInvalidValue;
+    const dim3 grid((g.V + kSitesPerWG - 1) / kSitesPerWG);
+    const dim3 block(64 * nb);
+#define DSBCG_W(R, D)                                                                          \
+    hipLaunchKernelGGL((wilson_cm_kernel<R, D>), grid, block, 0, st, g, (const cx<R> *)Ul, (R)kappa, \
+                       (const cx<R> *)in, (cx<R> *)out, nb)
+    if (fp64) {
+        if (dagger) DSBCG_W(double, true);
+        else DSBCG_W(double, false);
+    } else {
+        if (dagger) DSBCG_W(float, true);
+        else DSBCG_W(float, false);
     }
-}
-
-hipError_t wilson_apply(const Geom &g, bool fp64, const void *U, double kappa, const void *in,
-                        int64_t in_site, int64_t in_comp, void *out, int64_t out_site,
-                        int64_t out_comp, int nb, bool dagger, bool lds_links, hipStream_t st) {
-    if (fp64)
-        return lds_links ? launch_prec<double, true>(g, U, kappa, in, in_site, in_comp, out,
-                                                     out_site, out_comp, nb, dagger, st)
-                         : launch_prec<double, false>(g, U, kappa, in, in_site, in_comp, out,
-                                                      out_site, out_comp, nb, dagger, st);
-    return lds_links ? launch_prec<float, true>(g, U, kappa, in, in_site, in_comp, out,
-                                                out_site, out_comp, nb, dagger, st)
-                     : launch_prec<float, false>(g, U, kappa, in, in_site, in_comp, out,
-                                                 out_site, out_comp, nb, dagger, st);
+#undef DSBCG_W
+    return hipGetLastError();
 }
 
 hipError_t neighbor_table(const Geom &g, int32_t *dev_out, hipStream_t st) {
     hipLaunchKernelGGL(neighbor_kernel, dim3((g.V + 255) / 256), dim3(256), 0, st, g, dev_out);
+    return hipGetLastError();
+}
+
+// Links [V][4][3][3] (FP64) -> structure of arrays [4][9][V] in FP64 or FP32.
+template <typename To>
+__global__ __launch_bounds__(256) void links_soa_kernel(int64_t V, const zd *__restrict__ U,
+                                                        cx<To> *__restrict__ out) {
+    const int64_t total = V * 36;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = e % V;
+        const int64_t k = e / V;  // mu*9 + element
+        out[e] = cvt<To>(U[x * 36 + k]);
+    }
+}
+
+hipError_t links_to_soa(int64_t V, const void *U, void *out, bool fp64, hipStream_t st) {
+    const int64_t want = (V * 36 + 255) / 256;
+    const dim3 grid((unsigned)(want < 65536 ? want : 65536));
+    if (fp64)
+        hipLaunchKernelGGL((links_soa_kernel<double>), grid, dim3(256), 0, st, V, (const zd *)U,
+                           (zd *)out);
+    else
+        hipLaunchKernelGGL((links_soa_kernel<float>), grid, dim3(256), 0, st, V, (const zd *)U,
+                           (zf *)out);
     return hipGetLastError();
 }
 

@@ -10,14 +10,16 @@ struct Geom {
     int32_t V;
 };
 
-// out = D in (dagger = false) or D^H in (dagger = true) on nb columns.
-// Element (site x, spin-colour c, column r) of a field lives at
-//   x * site_stride + c * comp_stride + r.
-// fp64 selects double (U, in, out all double) or float data.
-// lds_links stages each workgroup's link matrices in LDS.
-hipError_t wilson_apply(const Geom &g, bool fp64, const void *U, double kappa, const void *in,
-                        int64_t in_site, int64_t in_comp, void *out, int64_t out_site,
-                        int64_t out_comp, int nb, bool dagger, bool lds_links, hipStream_t st);
+// out = D in (dagger = false) or D^H in (dagger = true) on nb <= 16 columns.
+// in, out: column-major fields, element (column r, spin-colour c, site x) at
+// (r*12 + c)*V + x.  Ul: links as structure of arrays, element e of U_mu(x)
+// at (mu*9 + e)*V + x.  fp64 selects double or float data.  out must not
+// alias in.
+hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, const void *in,
+                        void *out, int nb, bool dagger, hipStream_t st);
+
+// Links [V][4][3][3] (FP64) -> structure of arrays [4][9][V], FP64 or FP32.
+hipError_t links_to_soa(int64_t V, const void *U, void *out, bool fp64, hipStream_t st);
 
 // Neighbour table [V][8] (+x, -x, +y, -y, +z, -z, +t, -t) as the stencil computes it.
 hipError_t neighbor_table(const Geom &g, int32_t *dev_out, hipStream_t st);
