@@ -143,6 +143,32 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
                 const double *sigma, int32_t s, double tol, const dsbcg_opts *opts,
                 void *X, dsbcg_stats *stats, dsbcg_stream stream);
 
+/* Solve (sigma_j I + A) X_j = B_j for j = 0..s-1, one right-hand-side block
+ * per shift: B is [s][V][4][3][m] (device).  The blocks are stacked and
+ * deflated together (deflated QR of [B_0 | ... | B_{s-1}]) and ONE DSBlockCG
+ * run over that common basis serves every shift, each with its own initial
+ * coefficients (the block form of the paper's method with Z_{j,1} = the
+ * coordinates of B_j).  When the blocks span more than 16 directions the call
+ * falls back to one block solve per shift.  This is the adjoint solve of the
+ * differentiation form: Lambda_j = (sigma_j + A)^{-1} dL/dX_j.  Other
+ * arguments, results and errors as dsbcg_solve. */
+int dsbcg_solve_multi(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
+                      const double *sigma, int32_t s, double tol, const dsbcg_opts *opts,
+                      void *X, dsbcg_stats *stats, dsbcg_stream stream);
+
+/* Backward of X_j = (sigma_j I + D^H D)^{-1} B given X_j and the adjoint
+ * solutions Lambda_j = (sigma_j I + A)^{-1} G_j, G_j = dL/dRe X_j + i dL/dIm X_j
+ * (both [s][V][4][3][m], device).  Since sigma_j I + A is hermitian,
+ *   dL/dB       = sum_j Lambda_j                         (dB: device [V][4][3][m])
+ *   dL/dsigma_j = -Re <Lambda_j, X_j>                     (dsigma: HOST [s])
+ *   dL/dU       = -sum_j [ dRe<D X_j, D Lambda_j> + dRe<D Lambda_j, D X_j> ]/dU
+ * (dU: device [V][4][3][3], convention dRe + i dIm, link-derivative stencil of
+ * dsbcg_link_grad).  Each output pointer may be NULL to skip it.  Synchronises
+ * `stream` when dsigma is requested. */
+int dsbcg_grad(dsbcg_handle h, const void *U, double kappa, const double *sigma, int32_t s,
+               int32_t m, const void *X, const void *Lam, void *dU, void *dB, double *dsigma,
+               dsbcg_stream stream);
+
 /* Link derivative of f(U) = sum_k Re <Phi_k, D[U] Psi_k> summed over the
  * nvec = s*m columns of Phi and Psi ([V][4][3][nvec], device), in the
  * convention dU = df/dRe U + i df/dIm U:

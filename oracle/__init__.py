@@ -19,3 +19,6 @@ from .dsbcg import (dsbcg, deflated_qr, true_relres, NotHPD, Result)
 __all__ = ["apply_D", "apply_A", "apply_D_sites", "apply_A_sites", "neighbors", "gamma",
            "link_grad", "max_threads", "load", "dsbcg", "deflated_qr", "true_relres",
            "NotHPD", "Result"]
+from .grad import adjoint_gradients  # noqa: E402
+
+__all__.append("adjoint_gradients")

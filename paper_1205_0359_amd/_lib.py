@@ -90,6 +90,11 @@ def load():
     lib.dsbcg_solve.argtypes = [P, P, dbl, P, i32, ctypes.POINTER(ctypes.c_double), i32, dbl,
                                 ctypes.POINTER(dsbcg_opts), P, ctypes.POINTER(dsbcg_stats), P]
     lib.dsbcg_solve.restype = ctypes.c_int
+    lib.dsbcg_solve_multi.argtypes = lib.dsbcg_solve.argtypes
+    lib.dsbcg_solve_multi.restype = ctypes.c_int
+    lib.dsbcg_grad.argtypes = [P, P, dbl, ctypes.POINTER(ctypes.c_double), i32, i32, P, P, P, P,
+                               ctypes.POINTER(ctypes.c_double), P]
+    lib.dsbcg_grad.restype = ctypes.c_int
     lib.dsbcg_link_grad.argtypes = [P, dbl, P, P, i32, P, P]
     lib.dsbcg_link_grad.restype = ctypes.c_int
     lib.dsbcg_profile_enable.argtypes = [P, i32]
@@ -227,20 +232,14 @@ def default_opts(**kw) -> dsbcg_opts:
     return o
 
 
-def dsbcg_solve(h: Handle, U, kappa: float, B, sigma, tol: float, X=None, stream=None,
-                raise_not_converged: bool = True, **opts):
-    """Solve (sigma_j I + A) X_j = B for all shifts.
-
-    Returns (X, stats) with X complex128 (s, V, 4, 3, m) on the device and a
-    stats dict (iterations, mvms, estimated and true relative residuals).
-    """
+def _solve(fn, h: Handle, U, kappa, B, sigma, tol, X, stream, raise_not_converged, multi, opts):
     import numpy as np
     torch = _torch()
     m = B.shape[-1]
     sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(-1))
     s = len(sig)
     pU = _dev(U, "U", (h.V, 4, 3, 3))
-    pB = _dev(B, "B", (h.V, 4, 3, m))
+    pB = _dev(B, "B", (s, h.V, 4, 3, m) if multi else (h.V, 4, 3, m))
     if X is None:
         X = torch.empty((s, h.V, 4, 3, m), dtype=torch.complex128, device=B.device)
     pX = _dev(X, "X", (s, h.V, 4, 3, m))
@@ -250,21 +249,61 @@ def dsbcg_solve(h: Handle, U, kappa: float, B, sigma, tol: float, X=None, stream
     st = dsbcg_stats()
     st.est_relres = est.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     st.true_relres = true.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    code = load().dsbcg_solve(h.ptr, pU, float(kappa), pB, int(m),
-                              sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(s),
-                              float(tol), ctypes.byref(o), pX, ctypes.byref(st), _stream(stream))
+    code = fn(h.ptr, pU, float(kappa), pB, int(m), sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+              int(s), float(tol), ctypes.byref(o), pX, ctypes.byref(st), _stream(stream))
     stats = {
         "status": STATUS_NAMES.get(code, code),
         "block_iters": st.block_iters, "rank0": st.rank0, "deflations": st.deflations,
         "reliable_updates": st.reliable_updates, "refine_iters": st.refine_iters,
-        "final_width": st.final_width, "switch_iter": st.switch_iter, "main_relres_max": st.main_relres_max,
-        "mvms": int(st.mvms),
+        "final_width": st.final_width, "switch_iter": st.switch_iter,
+        "main_relres_max": st.main_relres_max, "mvms": int(st.mvms),
         "est_relres": est.reshape(s, m).T.copy(), "true_relres": true.reshape(s, m).T.copy(),
     }
     if code == DSBCG_ERR_NOT_CONVERGED and not raise_not_converged:
         return X, stats
     _check(code)
     return X, stats
+
+
+def dsbcg_solve(h: Handle, U, kappa: float, B, sigma, tol: float, X=None, stream=None,
+                raise_not_converged: bool = True, **opts):
+    """Solve (sigma_j I + A) X_j = B for all shifts.
+
+    Returns (X, stats) with X complex128 (s, V, 4, 3, m) on the device and a
+    stats dict (iterations, mvms, estimated and true relative residuals as
+    (m, s) arrays).
+    """
+    return _solve(load().dsbcg_solve, h, U, kappa, B, sigma, tol, X, stream, raise_not_converged,
+                  False, opts)
+
+
+def dsbcg_solve_multi(h: Handle, U, kappa: float, B, sigma, tol: float, X=None, stream=None,
+                      raise_not_converged: bool = True, **opts):
+    """Solve (sigma_j I + A) X_j = B_j with one block per shift, B of shape (s, V, 4, 3, m)."""
+    return _solve(load().dsbcg_solve_multi, h, U, kappa, B, sigma, tol, X, stream,
+                  raise_not_converged, True, opts)
+
+
+def dsbcg_grad(h: Handle, U, kappa: float, sigma, X, Lam, want_U=True, want_B=True,
+               want_sigma=True, stream=None):
+    """Backward kernels: (dU, dB, dsigma) from X_j and Lambda_j = (sigma_j + A)^{-1} G_j."""
+    import numpy as np
+    torch = _torch()
+    s, V, _, _, m = X.shape
+    sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(-1))
+    pU = _dev(U, "U", (h.V, 4, 3, 3))
+    pX = _dev(X, "X", (s, h.V, 4, 3, m))
+    pL = _dev(Lam, "Lam", (s, h.V, 4, 3, m))
+    dU = torch.empty((h.V, 4, 3, 3), dtype=torch.complex128, device=X.device) if want_U else None
+    dB = torch.empty((h.V, 4, 3, m), dtype=torch.complex128, device=X.device) if want_B else None
+    ds = np.zeros(s) if want_sigma else None
+    _check(load().dsbcg_grad(h.ptr, pU, float(kappa), sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             int(s), int(m), pX, pL,
+                             ctypes.c_void_p(dU.data_ptr()) if dU is not None else None,
+                             ctypes.c_void_p(dB.data_ptr()) if dB is not None else None,
+                             ds.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if ds is not None else None,
+                             _stream(stream)))
+    return dU, dB, ds
 
 
 def dsbcg_link_grad(h: Handle, kappa: float, Phi, Psi, dU=None, stream=None):

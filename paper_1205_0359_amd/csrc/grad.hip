@@ -66,7 +66,8 @@ __device__ inline void grad_dir(const Geom &g, int x, const int c[4], double kap
 
 __global__ __launch_bounds__(256) void link_grad_kernel(Geom g, double kappa, const zd *__restrict__ Phi,
                                                         const zd *__restrict__ Psi, int cols,
-                                                        zd *__restrict__ dU, int accumulate) {
+                                                        zd *__restrict__ dU, int accumulate,
+                                                        double scale) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= 4 * (int64_t)g.V) return;
     const int mu = (int)(t / g.V);
@@ -87,16 +88,16 @@ __global__ __launch_bounds__(256) void link_grad_kernel(Geom g, double kappa, co
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const zd v = mk<double>(-kappa * G[i][j].x, -kappa * G[i][j].y);
+            const zd v = mk<double>(-scale * kappa * G[i][j].x, -scale * kappa * G[i][j].y);
             o[i * 3 + j] = accumulate ? o[i * 3 + j] + v : v;
         }
 }
 
 hipError_t link_grad_apply(const Geom &g, double kappa, const void *Phi, const void *Psi, int cols,
-                           void *dU, bool accumulate, hipStream_t st) {
+                           void *dU, bool accumulate, double scale, hipStream_t st) {
     const int64_t total = 4 * (int64_t)g.V;
     hipLaunchKernelGGL(link_grad_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g,
-                       kappa, (const zd *)Phi, (const zd *)Psi, cols, (zd *)dU, accumulate ? 1 : 0);
+                       kappa, (const zd *)Phi, (const zd *)Psi, cols, (zd *)dU, accumulate ? 1 : 0, scale);
     return hipGetLastError();
 }
 

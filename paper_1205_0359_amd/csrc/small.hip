@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
                 st->Z[j][r * 16 + l] = v;
                 nrm += norm2(v);
             }
-            const double bn = st->bnorm[l];
+            const double bn = st->bnorm[st->colmap[j][l]];
             const double e = (bn > 0.0) ? sqrt(nrm) / bn : 0.0;
             rep->est[j][l] = e;
             if (freeze && ((mask >> l) & 1u) && e <= tol) mask &= ~(1u << l);
@@ -359,18 +359,20 @@ hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double to
 // ---------------------------------------------------------------------------
 // Initial deflated QR of B (classical Gram-Schmidt twice, column order).
 // ---------------------------------------------------------------------------
-__global__ void bnorms_kernel(SmallState *st, StepReport *rep, const zd *__restrict__ G, int m) {
+__global__ void bnorms_kernel(SmallState *st, StepReport *rep, const zd *__restrict__ G, int c0,
+                              int cnt) {
     if (threadIdx.x != 0) return;
-    for (int l = 0; l < m; ++l) {
+    for (int l = 0; l < cnt; ++l) {
         const double v = G[l * 16 + l].x;
         if (!isfinite(v)) rep->flags |= kFlagNonFinite;
-        st->bnorm[l] = sqrt(fmax(v, 0.0));
+        st->bnorm[c0 + l] = sqrt(fmax(v, 0.0));
+        for (int r = 0; r < kS; ++r) st->rho[r * kStack + c0 + l] = mk<double>(0, 0);
     }
-    for (int e = 0; e < 256; ++e) st->rho[e] = mk<double>(0, 0);
 }
 
-hipError_t small_bnorms(SmallState *st, StepReport *rep, const zd *G, int m, hipStream_t stream) {
-    hipLaunchKernelGGL(bnorms_kernel, dim3(1), dim3(64), 0, stream, st, rep, G, m);
+hipError_t small_bnorms(SmallState *st, StepReport *rep, const zd *G, int c0, int cnt,
+                        hipStream_t stream) {
+    hipLaunchKernelGGL(bnorms_kernel, dim3(1), dim3(64), 0, stream, st, rep, G, c0, cnt);
     return hipGetLastError();
 }
 
@@ -391,11 +393,15 @@ __global__ void cgs_decide_kernel(SmallState *st, StepReport *rep, const zd *__r
     for (int r = 0; r < k; ++r) {
         const zd a = c1 ? c1[r * 16] : mk<double>(0, 0);
         const zd bb = c2 ? c2[r * 16] : mk<double>(0, 0);
-        st->rho[r * 16 + l] = a + bb;
+        st->rho[r * kStack + l] = a + bb;
     }
     const double nu = sqrt(fmax(nu2[0].x, 0.0));
-    const bool keep = nu > tau_B * st->bnorm[l];
-    if (keep) st->rho[k * 16 + l] = mk<double>(nu, 0.0);
+    bool keep = nu > tau_B * st->bnorm[l];
+    if (keep && k >= kS) {
+        rep->flags |= kFlagRank;
+        keep = false;
+    }
+    if (keep) st->rho[k * kStack + l] = mk<double>(nu, 0.0);
     st->coef[3][0] = mk<double>(keep ? 1.0 / nu : 0.0, 0.0);
     rep->scalar[0] = nu;
     rep->scalar[1] = keep ? 1.0 : 0.0;
@@ -413,7 +419,7 @@ struct ShiftInit {
 };
 
 __global__ void init_shifts_kernel(SmallState *st, StepReport *rep, int m1, int m, int s,
-                                   ShiftInit sh, int freeze, double tol) {
+                                   ShiftInit sh, int freeze, double tol, int per_shift) {
     if (threadIdx.x != 0) return;
     st->b = m1;
     st->bp = 0;
@@ -423,12 +429,18 @@ __global__ void init_shifts_kernel(SmallState *st, StepReport *rep, int m1, int 
     for (int e = 0; e < 256; ++e) st->beta[e] = mk<double>(0, 0);
     for (int j = 0; j < s; ++j) {
         st->sigma[j] = sh.sigma[j];
-        for (int e = 0; e < 256; ++e) st->Z[j][e] = st->rho[e];
+        for (int e = 0; e < 256; ++e) st->Z[j][e] = mk<double>(0, 0);
         uint32_t mask = 0;
         for (int l = 0; l < m; ++l) {
+            const int c = per_shift ? j * m + l : l;
+            st->colmap[j][l] = c;
             double nrm = 0.0;
-            for (int r = 0; r < m1; ++r) nrm += norm2(st->rho[r * 16 + l]);
-            const double bn = st->bnorm[l];
+            for (int r = 0; r < m1; ++r) {
+                const zd v = st->rho[r * kStack + c];
+                st->Z[j][r * 16 + l] = v;
+                nrm += norm2(v);
+            }
+            const double bn = st->bnorm[c];
             const double e = bn > 0.0 ? sqrt(nrm) / bn : 0.0;
             rep->est[j][l] = e;
             if (bn > 0.0 && !(freeze && e <= tol)) mask |= 1u << l;
@@ -439,11 +451,12 @@ __global__ void init_shifts_kernel(SmallState *st, StepReport *rep, int m1, int 
 }
 
 hipError_t small_init_shifts(SmallState *st, StepReport *rep, int m1, int m, int s,
-                             const double *sigma_host, int freeze, double tol, hipStream_t stream) {
+                             const double *sigma_host, int freeze, double tol, int per_shift,
+                             hipStream_t stream) {
     ShiftInit sh{};
     for (int j = 0; j < s && j < kS; ++j) sh.sigma[j] = sigma_host[j];
     hipLaunchKernelGGL(init_shifts_kernel, dim3(1), dim3(64), 0, stream, st, rep, m1, m, s, sh,
-                       freeze, tol);
+                       freeze, tol, per_shift);
     return hipGetLastError();
 }
 

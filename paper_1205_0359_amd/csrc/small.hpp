@@ -6,7 +6,8 @@
 
 namespace dsbcg {
 
-constexpr int kS = 16;  // largest shift count / block width handled by the small kernels
+constexpr int kS = 16;       // largest shift count / block width handled by the small kernels
+constexpr int kStack = 256;  // largest number of stacked right-hand-side columns
 
 // Matrices are 16 x 16 row-major (leading dimension 16); only the leading
 // rows x cols part is meaningful.
@@ -17,7 +18,8 @@ struct SmallState {
     zd R1[256];          // first-pass Cholesky factor of W^H W, kept rows (bnew x b)
     zd C1[256];          // E_K R_KK^{-1}                       (b x bnew)
     zd Rinv[256];        // E_K (R2 R_KK)^{-1}                   (b x bnew)
-    zd rho[256];         // R factor of the deflated QR of B     (m1 x m)
+    zd rho[kS * kStack]; // R factor of the deflated QR of the stacked right-hand sides,
+                         // row r, stacked column c at r * kStack + c  (m1 x M)
     zd coef[4][256];     // scratch coefficient matrices for the block kernels
     zd L[kS][256];       // per shift: Cholesky factor of Delta_{j,i} (lower, b x b)
     zd Z[kS][256];       // per shift: Z_{j,i} (b x m)
@@ -26,7 +28,8 @@ struct SmallState {
     zf N32[kS][256];     // FP32 copies of N and M for the FP32 block updates
     zf M32[kS][256];
     double sigma[kS];
-    double bnorm[kS];    // ||b_l||
+    double bnorm[kStack];       // norms of the stacked right-hand-side columns
+    int32_t colmap[kS][kS];     // stacked column of right-hand side l of shift j
     double test;         // running estimate of ||T||: max Frobenius norm of alpha_i, beta_i
     int32_t b, bp, m, s;
 };
@@ -42,7 +45,7 @@ struct StepReport {
     double scalar[4];    // [0]: norm of the last CGS remainder, [1]: kept flag of that column
 };
 
-enum { kFlagNotHPD = 1, kFlagQR2 = 2, kFlagNonFinite = 4 };
+enum { kFlagNotHPD = 1, kFlagQR2 = 2, kFlagNonFinite = 4, kFlagRank = 8 };
 
 // alpha_i = herm(raw Gram V_i^H W) into the state, and coef[1] = -alpha_i.
 hipError_t small_prep_alpha(SmallState *st, const zd *alpha_raw, hipStream_t stream);
@@ -64,16 +67,21 @@ hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double to
                         const int32_t *shift_list, int nact, hipStream_t stream);
 
 // Initial deflated QR of B, classical Gram-Schmidt twice per column.
-// small_bnorms: ||b_l|| from the diagonal of B^H B; flags zero / non-finite columns.
-hipError_t small_bnorms(SmallState *st, StepReport *rep, const zd *G, int m, hipStream_t stream);
+// small_bnorms: ||b_l|| for the stacked columns c0 .. c0+cnt-1 from the diagonal of
+// their Gram matrix; flags non-finite columns.
+hipError_t small_bnorms(SmallState *st, StepReport *rep, const zd *G, int c0, int cnt,
+                        hipStream_t stream);
 // coef[slot] = -(column 0 of src) for the first k rows.
 hipError_t small_neg_column(SmallState *st, int slot, const zd *src, int k, hipStream_t stream);
 // Decide on column l: rho[0..k)[l] = c1 + c2; keep if ||w|| > tau_B ||b_l||.
 // Writes coef[3] = 1/||w|| and the decision into rep->scalar.
 hipError_t small_cgs_decide(SmallState *st, StepReport *rep, const zd *c1, const zd *c2,
                             const zd *nu2, int k, int l, double tau_B, hipStream_t stream);
-// Initialise the per-shift state from rho: Z_{j,1} = rho, masks and estimates.
+// Initialise the per-shift state from rho: Z_{j,1} = the columns of rho that
+// belong to shift j (per_shift: stacked column j*m + l, else column l for
+// every shift), masks and estimates.
 hipError_t small_init_shifts(SmallState *st, StepReport *rep, int m1, int m, int s,
-                             const double *sigma_host, int freeze, double tol, hipStream_t stream);
+                             const double *sigma_host, int freeze, double tol, int per_shift,
+                             hipStream_t stream);
 
 }  // namespace dsbcg

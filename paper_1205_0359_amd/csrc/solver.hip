@@ -337,12 +337,13 @@ struct SolveStats {
     double est[kS * kS] = {};
 };
 
-// Initial deflated QR of B (column-major FP64 in h->Bint): classical
-// Gram-Schmidt applied twice, column by column, in column order.  Column l is
-// dropped when its remainder is <= tau_B ||b_l|| (deflation, Sec. 1 and the
-// deflated block Lanczos process of Sec. 3).  Leaves V_1 (FP64, m1 columns)
-// in h->V[0] and rho in the small state.
-int initial_qr(dsbcg_ctx *h, int m, double tau_B, hipStream_t st, int *m1_out) {
+// Initial deflated QR of the right-hand sides (M <= 256 column-major FP64
+// columns in h->Bint): classical Gram-Schmidt applied twice, column by
+// column, in column order.  Column l is dropped when its remainder is
+// <= tau_B ||b_l|| (deflation, Sec. 1 and the deflated block Lanczos process
+// of Sec. 3).  Leaves V_1 (FP64, m1 <= 16 columns) in h->V[0] and rho in the
+// small state; returns DSBCG_ERR_ARG with *m1_out = -1 when the rank exceeds 16.
+int initial_qr(dsbcg_ctx *h, int M, double tau_B, hipStream_t st, int *m1_out) {
     const int64_t n = 12 * (int64_t)h->g.V;
     Ts ts{h, true, st, n};
     SmallState *S = stp(h);
@@ -350,18 +351,19 @@ int initial_qr(dsbcg_ctx *h, int m, double tau_B, hipStream_t st, int *m1_out) {
     zd *Qp = (zd *)h->Q.p;
     zd *Bp = (zd *)h->Bint.p;
     zd *wp = (zd *)h->wbuf.p;
-    // ||b_l|| from the diagonal of B^H B
-    {
+    // ||b_l|| from the diagonals of the Gram matrices of 16-column chunks
+    for (int c0 = 0; c0 < M; c0 += 16) {
+        const int cnt = std::min(16, M - c0);
         TsArgs a = ts_args(n);
         a.K = 1;
-        a.X[0] = Bp; a.bx[0] = m; a.C[0] = nullptr;
-        a.bout = m;
+        a.X[0] = Bp + (int64_t)c0 * n; a.bx[0] = cnt; a.C[0] = nullptr;
+        a.bout = cnt;
         a.gram = 1;
-        CHK(ts.run_reduce(a, m, 0));
-        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_bnorms(S, rep, red_slot(h, 0), m, st));
+        CHK(ts.run_reduce(a, cnt, 0));
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_bnorms(S, rep, red_slot(h, 0), c0, cnt, st));
     }
     int k = 0;
-    for (int l = 0; l < m; ++l) {
+    for (int l = 0; l < M; ++l) {
         const zd *bl = Bp + (int64_t)l * n;
         if (k > 0) {
             // c1 = Q^H b_l
@@ -408,6 +410,10 @@ int initial_qr(dsbcg_ctx *h, int m, double tau_B, hipStream_t st, int *m1_out) {
         CHK(read_report(h, st));
         if (h->rep_host->flags & kFlagNonFinite)
             return fail(DSBCG_ERR_NOT_HPD, "B holds non-finite values");
+        if (h->rep_host->flags & kFlagRank) {
+            *m1_out = -1;
+            return fail(DSBCG_ERR_ARG, "the right-hand sides span more than 16 directions");
+        }
         if (h->rep_host->scalar[1] > 0.5) {
             // Q[:, k] = w / ||w||
             TsArgs a = ts_args(n);
@@ -441,8 +447,9 @@ int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
 // every shift (Sec. 4: relative residual); B and X in the caller's layout, the
 // FP64 structure-of-arrays links in h->Ul64.  With keep_j >= 0 only that shift
 // is evaluated and its residual block is stored in Rkeep (caller's layout).
-int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi, const void *Xapi,
-                   int m, const double *sigma, int s, double *out, int keep_j, void *Rkeep) {
+int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi, int64_t bstride,
+                   const void *Xapi, int m, const double *sigma, int s, double *out, int keep_j,
+                   void *Rkeep) {
     const int64_t n = 12 * (int64_t)h->g.V;
     const size_t blk = (size_t)n * m * sizeof(zd);
     CHK(ensure_common(h));
@@ -451,23 +458,23 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
     CHK(ensure(h->R2, blk));
     CHK(ensure(h->R3, blk));
     Ts ts{h, true, st, n};
-    CHK(copy(h, m, api(Bapi, m), cm(h->R0.p, n, true), false, st));
     std::vector<double> bn(m);
-    {
-        TsArgs a = ts_args(n);
-        a.K = 1;
-        a.X[0] = h->R0.p; a.bx[0] = m; a.C[0] = nullptr;
-        a.bout = m;
-        a.gram = 1;
-        CHK(ts.run_reduce(a, m, 4));
-        std::vector<zd> g(256);
-        HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 4), 256 * sizeof(zd), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        for (int l = 0; l < m; ++l) bn[l] = std::sqrt(std::max(g[l * 16 + l].x, 0.0));
-    }
     std::vector<zd> cf(512, mk<double>(0, 0));
     for (int j = 0; j < s; ++j) {
         if (keep_j >= 0 && j != keep_j) continue;
+        if (j == 0 || bstride != 0 || keep_j >= 0) {
+            CHK(copy(h, m, api((const zd *)Bapi + (int64_t)j * bstride, m), cm(h->R0.p, n, true), false, st));
+            TsArgs a = ts_args(n);
+            a.K = 1;
+            a.X[0] = h->R0.p; a.bx[0] = m; a.C[0] = nullptr;
+            a.bout = m;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, m, 4));
+            std::vector<zd> g(256);
+            HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 4), 256 * sizeof(zd), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int l = 0; l < m; ++l) bn[l] = std::sqrt(std::max(g[l * 16 + l].x, 0.0));
+        }
         CHK(copy(h, m, api((const zd *)Xapi + (int64_t)j * n * m, m), cm(h->R1.p, n, true), false, st));
         CHK(apply_A_cm(h, true, h->Ul64.p, kappa, h->R1.p, h->R2.p, h->R3.p, m, st));
         TsArgs a = ts_args(n);
@@ -517,29 +524,33 @@ struct WorkSet {
 // ru_interval steps and at the end.  Writes the iterates to Xapi
 // ([s][V][4][3][m], FP64).  The FP64 links must be in h->Ul64 (and the FP32
 // links in h->Ul32 for the FP32 form).
-int solve_core(dsbcg_ctx *h, double kappa, const void *B, int m, const double *sigma, int s,
-               double tol, const dsbcg_opts &o, double switch_at, void *Xapi, SolveStats &stt,
-               hipStream_t st) {
+int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m,
+               const double *sigma, int s, double tol, const dsbcg_opts &o, double switch_at,
+               void *Xapi, SolveStats &stt, hipStream_t st) {
     const int64_t V = h->g.V, n = 12 * V;
     const bool form32 = o.precision == DSBCG_FP32_RELIABLE;
+    const int M = bstride ? m * s : m;  // stacked right-hand-side columns
 
     CHK(ensure_common(h));
-    CHK(ensure(h->Bint, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->Q, (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->Bint, (size_t)n * M * sizeof(zd)));
+    CHK(ensure(h->Q, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
     CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
-    CHK(ensure(h->V[0], (size_t)n * m * sizeof(zd)));
+    CHK(ensure(h->V[0], (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
     CHK(ensure(h->X, (size_t)n * m * s * sizeof(zd)));
 
     SmallState *S = stp(h);
     StepReport *rep = repp(h);
     HIPCHK(hipMemsetAsync(rep, 0, sizeof(StepReport), st));
     HIPCHK(hipMemsetAsync(h->X.p, 0, (size_t)n * m * s * sizeof(zd), st));
-    CHK(copy(h, m, api(B, m), cm(h->Bint.p, n, true), false, st));
+    for (int j = 0; j < (bstride ? s : 1); ++j)
+        CHK(copy(h, m, api((const zd *)B + (int64_t)j * bstride, m),
+                 cm((zd *)h->Bint.p + (int64_t)j * m * n, n, true), false, st));
 
     int m1 = 0;
-    CHK(initial_qr(h, m, o.tau_B, st, &m1));
+    CHK(initial_qr(h, M, o.tau_B, st, &m1));
     stt.rank0 = m1;
-    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, st));
+    PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                small_init_shifts(S, rep, m1, m, s, sigma, o.freeze, tol, bstride != 0, st));
     CHK(read_report(h, st));
 
     // widths never exceed m1 after the initial deflation
@@ -860,9 +871,16 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     return DSBCG_OK;
 }
 
-int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
-                const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
-                dsbcg_stats *stats, dsbcg_stream stream) {
+}  // extern "C"
+
+namespace {
+
+// Validated solve of (sigma_j I + A) X_j = B_j, B_j = B + j * bstride
+// (bstride = 0: one B for every shift), followed by the FP64 true residuals
+// and, for shifts that miss tol, FP64 re-solves of their residual blocks.
+int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, int64_t bstride,
+                  int32_t m, const double *sigma, int32_t s, double tol, const dsbcg_opts *opts,
+                  void *X, dsbcg_stats *stats, hipStream_t st) {
     if (!h || !U || !B || !sigma || !X) return fail(DSBCG_ERR_ARG, "NULL argument");
     if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
     if (s < 1 || s > DSBCG_MAX_SHIFTS) return fail(DSBCG_ERR_ARG, "s out of range");
@@ -879,7 +897,6 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
     if (o.tau_W < 0) o.tau_W = 1e-12;
     if (o.max_iters < 1) o.max_iters = 1;
     if (o.switch_at < 0) o.switch_at = std::min(1e-2, 1e5 * tol);
-    hipStream_t st = (hipStream_t)stream;
     const int64_t n = 12 * (int64_t)h->g.V;
 
     CHK(ensure_common(h));
@@ -888,16 +905,30 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
     if (o.precision == DSBCG_FP32_RELIABLE) CHK(prepare_links(h, U, false, st));
 
     SolveStats stt;
-    double stt_main_max = 0.0;
-    int status = solve_core(h, kappa, B, m, sigma, s, tol, o, o.switch_at, X, stt, st);
+    double main_max = 0.0;
+    int status = solve_core(h, kappa, B, bstride, m, sigma, s, tol, o, o.switch_at, X, stt, st);
+    if (status == DSBCG_ERR_ARG && bstride != 0 && stt.rank0 == 0) {
+        // the blocks span more than 16 directions: one block solve per shift
+        stt = SolveStats();
+        status = DSBCG_OK;
+        for (int j = 0; j < s && status == DSBCG_OK; ++j) {
+            SolveStats one;
+            status = solve_core(h, kappa, (const zd *)B + (int64_t)j * bstride, 0, m, &sigma[j], 1,
+                                tol, o, o.switch_at, (zd *)X + (int64_t)j * n * m, one, st);
+            stt.block_iters += one.block_iters;
+            stt.mvms += one.mvms;
+            stt.reliable_updates += one.reliable_updates;
+            stt.rank0 = std::max(stt.rank0, one.rank0);
+            for (int l = 0; l < m; ++l) stt.est[j * m + l] = one.est[l];
+        }
+    }
     if (status != DSBCG_OK && status != DSBCG_ERR_NOT_CONVERGED) return status;
 
-    // FP64 true residuals of every system; re-solve the shifts that miss tol
     std::vector<double> tr((size_t)s * m, 0.0);
     const bool want_true = (stats && stats->true_relres) || o.refine;
     if (want_true && status == DSBCG_OK) {
-        CHK(true_residuals(h, st, kappa, B, X, m, sigma, s, tr.data(), -1, nullptr));
-        for (double v : tr) stt_main_max = std::max(stt_main_max, v);
+        CHK(true_residuals(h, st, kappa, B, bstride, X, m, sigma, s, tr.data(), -1, nullptr));
+        for (double v : tr) main_max = std::max(main_max, v);
         for (int round = 0; o.refine && o.fixed_iters <= 0 && round < 2; ++round) {
             bool any = false;
             for (int j = 0; j < s; ++j) {
@@ -909,7 +940,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
                 CHK(ensure(h->Rres, (size_t)n * m * sizeof(zd)));
                 CHK(ensure(h->Xref, (size_t)n * m * sizeof(zd)));
                 std::vector<double> tmp((size_t)s * m);
-                CHK(true_residuals(h, st, kappa, B, X, m, sigma, s, tmp.data(), j, h->Rres.p));
+                CHK(true_residuals(h, st, kappa, B, bstride, X, m, sigma, s, tmp.data(), j, h->Rres.p));
                 double ratio = 1e300;
                 for (int l = 0; l < m; ++l)
                     if (tr[j * m + l] > 0) ratio = std::min(ratio, 1.0 / tr[j * m + l]);
@@ -919,14 +950,14 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
                 ro.tau_B = 0.1 * tol;
                 SolveStats rs;
                 const double rtol = std::max(0.5 * tol * ratio, 1e-15);
-                int rc = solve_core(h, kappa, h->Rres.p, m, &sigma[j], 1, rtol, ro, 0.0, h->Xref.p, rs, st);
+                int rc = solve_core(h, kappa, h->Rres.p, 0, m, &sigma[j], 1, rtol, ro, 0.0, h->Xref.p, rs, st);
                 if (rc != DSBCG_OK && rc != DSBCG_ERR_NOT_CONVERGED) return rc;
                 stt.refine_iters += rs.block_iters;
                 stt.mvms += rs.mvms;
                 CHK(copy(h, m, api(h->Xref.p, m), api((zd *)X + (int64_t)j * n * m, m), true, st));
             }
             if (!any) break;
-            CHK(true_residuals(h, st, kappa, B, X, m, sigma, s, tr.data(), -1, nullptr));
+            CHK(true_residuals(h, st, kappa, B, bstride, X, m, sigma, s, tr.data(), -1, nullptr));
         }
         double worst = 0.0;
         for (double v : tr) worst = std::max(worst, v);
@@ -945,10 +976,79 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
         stats->refine_iters = stt.refine_iters;
         stats->final_width = stt.final_width;
         stats->switch_iter = stt.switch_iter;
-        stats->main_relres_max = stt_main_max;
+        stats->main_relres_max = main_max;
         stats->mvms = stt.mvms;
     }
     return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
+                const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
+                dsbcg_stats *stats, dsbcg_stream stream) {
+    return solve_checked(h, U, kappa, B, 0, m, sigma, s, tol, opts, X, stats, (hipStream_t)stream);
+}
+
+int dsbcg_solve_multi(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
+                      const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
+                      dsbcg_stats *stats, dsbcg_stream stream) {
+    if (!h) return fail(DSBCG_ERR_ARG, "NULL handle");
+    return solve_checked(h, U, kappa, B, 12 * (int64_t)h->g.V * m, m, sigma, s, tol, opts, X, stats,
+                         (hipStream_t)stream);
+}
+
+int dsbcg_grad(dsbcg_handle h, const void *U, double kappa, const double *sigma, int32_t s, int32_t m,
+               const void *X, const void *Lam, void *dU, void *dB, double *dsigma, dsbcg_stream stream) {
+    if (!h || !U || !sigma || !X || !Lam) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (m < 1 || m > DSBCG_MAX_RHS || s < 1 || s > DSBCG_MAX_SHIFTS)
+        return fail(DSBCG_ERR_ARG, "m or s out of range");
+    if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = 12 * (int64_t)h->g.V;
+    const size_t blk = (size_t)n * m * sizeof(zd);
+    CHK(ensure_common(h));
+    CHK(ensure(h->R0, blk));
+    CHK(ensure(h->R1, blk));
+    CHK(ensure(h->R2, blk));
+    CHK(ensure(h->R3, blk));
+    if (dU) CHK(prepare_links(h, U, true, st));
+    Ts ts{h, true, st, n};
+    for (int j = 0; j < s; ++j) {
+        const zd *Xj = (const zd *)X + (int64_t)j * n * m;
+        const zd *Lj = (const zd *)Lam + (int64_t)j * n * m;
+        // dL/dB = sum_j Lambda_j
+        if (dB) CHK(copy(h, m, api(Lj, m), api(dB, m), j > 0, st));
+        CHK(copy(h, m, api(Xj, m), cm(h->R0.p, n, true), false, st));
+        CHK(copy(h, m, api(Lj, m), cm(h->R1.p, n, true), false, st));
+        if (dsigma) {
+            // dL/dsigma_j = -Re <Lambda_j, X_j>
+            TsArgs a = ts_args(n);
+            a.K = 1;
+            a.X[0] = h->R0.p; a.bx[0] = m; a.C[0] = nullptr;
+            a.bout = m;
+            a.gram = 2; a.L = h->R1.p; a.bl = m;
+            CHK(ts.run_reduce(a, m, 6));
+            std::vector<zd> g(256);
+            HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 6), 256 * sizeof(zd), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            double tr = 0.0;
+            for (int l = 0; l < m; ++l) tr += g[l * 16 + l].x;
+            dsigma[j] = -tr;
+        }
+        if (dU) {
+            // dL/dU = -sum_j [ d Re <D X_j, D Lambda_j> + d Re <D Lambda_j, D X_j> ]
+            CHK(stencil(h, true, h->Ul64.p, kappa, h->R0.p, h->R2.p, m, false, st));   // D X_j
+            CHK(stencil(h, true, h->Ul64.p, kappa, h->R1.p, h->R3.p, m, false, st));   // D Lambda_j
+            PROF_LAUNCH(h, kProfGrad, (double)h->g.V * (4.0 * 12 * m + 36.0 * (j ? 2 : 1)) * 16, st,
+                        link_grad_apply(h->g, kappa, h->R2.p, h->R1.p, m, dU, j > 0, -1.0, st));
+            PROF_LAUNCH(h, kProfGrad, (double)h->g.V * (4.0 * 12 * m + 72.0) * 16, st,
+                        link_grad_apply(h->g, kappa, h->R3.p, h->R0.p, m, dU, true, -1.0, st));
+        }
+    }
+    return DSBCG_OK;
 }
 
 int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *Psi, int32_t nvec,
@@ -971,7 +1071,7 @@ int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *P
         CHK(copy(h, cols, FieldDesc{const_cast<void *>(Psi), kApi, nvec, c0, true},
                  cm(h->Yout.p, n, true), false, st));
         PROF_LAUNCH(h, kProfGrad, (double)V * (2.0 * 12 * cols + 36.0 * (c0 ? 2 : 1)) * 16, st,
-                    link_grad_apply(h->g, kappa, h->Xin.p, h->Yout.p, cols, dU, c0 > 0, st));
+                    link_grad_apply(h->g, kappa, h->Xin.p, h->Yout.p, cols, dU, c0 > 0, 1.0, st));
     }
     return DSBCG_OK;
 }
