@@ -81,6 +81,9 @@ typedef struct {
     int32_t refine;       /* 1: after the main phase, re-solve (FP64) the shifts whose true
                              residual misses tol (default 1) */
     int32_t freeze;       /* 1: stop updating a system once its estimate reaches tol (default 1) */
+    int32_t window;       /* per-shift update window: P_j and X_j are written once every
+                             `window` block steps (0: longest that fits, up to 16; 1: every
+                             step).  The result is the same up to rounding */
     double switch_at;     /* FP32 form: the iteration runs in FP64 until every active estimated
                              relative residual is <= switch_at, then continues the same
                              recurrences with FP32 vectors (default min(1e-2, 1e5 * tol)) */
@@ -184,9 +187,10 @@ int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *P
  * bracketed by two HIP events on the call's stream (this adds a few
  * microseconds per launch); durations and algorithmic bytes (the data each
  * kernel must read and write, not cache traffic) accumulate per kernel class.
- * dsbcg_profile_enable resets the totals.  Classes: 0 Wilson stencil pass
- * (D or D^H), 1 block Gram / combination kernels, 2 per-shift P_j / X_j
- * update, 3 small FP64 algebra and Gram reductions, 4 conversions.
+ * dsbcg_profile_enable resets the totals.  Classes (dsbcg_profile_name):
+ * 0/1 Wilson stencil pass D or D^H in FP64/FP32, 2/3 block Gram / combination
+ * kernels in FP64/FP32, 4/5 windowed per-shift P_j / X_j update in FP64/FP32,
+ * 6 small FP64 algebra and Gram reductions, 7 conversions, 8 link derivative.
  * dsbcg_profile_read waits for the recorded events; any pointer may be NULL. */
 int dsbcg_profile_enable(dsbcg_handle h, int32_t enable);
 int dsbcg_profile_read(dsbcg_handle h, int32_t kclass, double *ms, int64_t *launches,

@@ -45,7 +45,8 @@ class dsbcg_opts(ctypes.Structure):
                 ("fixed_iters", ctypes.c_int32), ("ru_interval", ctypes.c_int32),
                 ("tau_B", ctypes.c_double),
                 ("tau_W", ctypes.c_double), ("refine", ctypes.c_int32),
-                ("freeze", ctypes.c_int32), ("switch_at", ctypes.c_double)]
+                ("freeze", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("switch_at", ctypes.c_double)]
 
 
 class dsbcg_stats(ctypes.Structure):

@@ -315,75 +315,120 @@ hipError_t copy_field(int64_t V, int cols, FieldDesc in, FieldDesc out, bool acc
 }
 
 // ---------------------------------------------------------------------------
-// Per-shift update, one thread per row (coalesced column-major access).  The
-// coefficient matrices are read with wave-uniform addresses; the basis row
-// V_i is read once from HBM and re-read from cache for every further shift.
+// Window update of the per-shift iterates: a workgroup owns 64 rows; the rows
+// of the K window blocks are staged in LDS once and each of the four waves
+// applies them to every fourth shift, so X_j and P_j rows are read and
+// written once per window instead of once per block step.
 // ---------------------------------------------------------------------------
-template <typename R, int BC>
-__global__ __launch_bounds__(256) void shift_kernel(ShiftArgs a) {
-    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (row >= a.nrows) return;
+template <typename R>
+struct WinCols {
+    static constexpr int value = sizeof(R) == 8 ? kWinCols64 : kWinCols32;
+};
+
+template <typename R, int BC, int MC>
+__global__ __launch_bounds__(256) void window_kernel(WinArgs a) {
+    constexpr int kRows = 64;
+    __shared__ cx<R> vt[WinCols<R>::value * kRows];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kRows;
+    const int64_t row = r0 + lane;
+    const bool ok = row < a.nrows;
     const int64_t n = a.nrows;
-    const cx<R> *__restrict__ V = (const cx<R> *)a.V + row;
-    const cx<R> *__restrict__ Nc = (const cx<R> *)a.N;
-    const cx<R> *__restrict__ Mc = (const cx<R> *)a.M;
-    const int b = a.b, bp = a.bp, m = a.m;
-    for (int js = 0; js < a.nshift; ++js) {
+    // stage the window rows: column c of the concatenated window at vt[c * 64 + lane]
+    {
+        int c0 = 0;
+        for (int u = 0; u < a.K; ++u) {
+            const cx<R> *Vu = (const cx<R> *)a.Vw[u];
+            for (int q = wave; q < a.wb[u]; q += 4)
+                vt[(c0 + q) * kRows + lane] = ok ? Vu[(int64_t)q * n + row] : mk<R>(0, 0);
+            c0 += a.wb[u];
+        }
+    }
+    __syncthreads();
+    if (!ok) return;
+    const cx<R> *G = (const cx<R> *)a.G, *Fp = (const cx<R> *)a.Fp;
+    const cx<R> *H = (const cx<R> *)a.H, *F = (const cx<R> *)a.F;
+    for (int js = wave; js < a.nshift; js += 4) {
         const int j = a.shifts[js];
-        const uint32_t mask = a.colmask[j];
-        cx<R> pn[BC];
+        const uint32_t xm = a.xmask[j];
+        const int cnt = a.count[j];
+        const bool wp = a.pmask[j] != 0;
+        cx<R> dx[MC], pn[BC];
 #pragma unroll
-        for (int q = 0; q < BC; ++q)
-            if (q < b) pn[q] = V[q * n];
-        if (!a.first) {
+        for (int q = 0; q < MC; ++q) dx[q] = mk<R>(0, 0);
+#pragma unroll
+        for (int q = 0; q < BC; ++q) pn[q] = mk<R>(0, 0);
+        if (a.bp0 > 0) {
             const cx<R> *po = (const cx<R> *)a.Pold + j * a.pstride + row;
-            const cx<R> *Nj = Nc + j * 256;
-            for (int p = 0; p < bp; ++p) {
-                const cx<R> v = po[p * n];
+            const cx<R> *g = G + j * 256, *fp = Fp + j * 256;
+            for (int p = 0; p < a.bp0; ++p) {
+                const cx<R> v = po[(int64_t)p * n];
 #pragma unroll
-                for (int q = 0; q < BC; ++q)
-                    if (q < b) {
-                        const cx<R> nn = Nj[p * 16 + q];
-                        pn[q].x = fma(-v.x, nn.x, pn[q].x);
-                        pn[q].x = fma(v.y, nn.y, pn[q].x);
-                        pn[q].y = fma(-v.x, nn.y, pn[q].y);
-                        pn[q].y = fma(-v.y, nn.x, pn[q].y);
-                    }
+                for (int q = 0; q < MC; ++q)
+                    if (q < a.m) cmac(dx[q], v, fp[p * 16 + q]);
+                if (wp)
+#pragma unroll
+                    for (int q = 0; q < BC; ++q)
+                        if (q < a.bend) cmac(pn[q], v, g[p * 16 + q]);
             }
         }
-        cx<R> *pw = (cx<R> *)a.Pnew + j * a.pstride + row;
+        int c0 = 0;
+        for (int u = 0; u < cnt; ++u) {
+            const cx<R> *hu = H + ((int64_t)j * kWinMax + u) * 256;
+            const cx<R> *fu = F + ((int64_t)j * kWinMax + u) * 256;
+            for (int p = 0; p < a.wb[u]; ++p) {
+                const cx<R> v = vt[(c0 + p) * kRows + lane];
 #pragma unroll
-        for (int q = 0; q < BC; ++q)
-            if (q < b) pw[q * n] = pn[q];
+                for (int q = 0; q < MC; ++q)
+                    if (q < a.m) cmac(dx[q], v, fu[p * 16 + q]);
+                if (wp)
+#pragma unroll
+                    for (int q = 0; q < BC; ++q)
+                        if (q < a.bend) cmac(pn[q], v, hu[p * 16 + q]);
+            }
+            c0 += a.wb[u];
+        }
         cx<R> *xr = (cx<R> *)a.X + j * a.xstride + row;
-        const cx<R> *Mj = Mc + j * 256;
-        for (int l = 0; l < m; ++l) {
-            if (!((mask >> l) & 1u)) continue;
-            cx<R> x = xr[l * n];
+#pragma unroll
+        for (int q = 0; q < MC; ++q)
+            if (q < a.m && ((xm >> q) & 1u)) xr[(int64_t)q * n] = xr[(int64_t)q * n] + dx[q];
+        if (wp) {
+            cx<R> *pw = (cx<R> *)a.Pnew + j * a.pstride + row;
 #pragma unroll
             for (int q = 0; q < BC; ++q)
-                if (q < b) cmac(x, pn[q], Mj[q * 16 + l]);
-            xr[l * n] = x;
+                if (q < a.bend) pw[(int64_t)q * n] = pn[q];
         }
     }
 }
 
-hipError_t shift_update(bool fp64, const ShiftArgs &a, hipStream_t st) {
-    const dim3 grid((unsigned)((a.nrows + 255) / 256));
-    const int bc = a.b <= 4 ? 4 : a.b <= 8 ? 8 : a.b <= 12 ? 12 : 16;
-#define DSBCG_SHIFT(R, N) hipLaunchKernelGGL((shift_kernel<R, N>), grid, dim3(256), 0, st, a)
-    if (fp64) {
-        if (bc == 4) DSBCG_SHIFT(double, 4);
-        else if (bc == 8) DSBCG_SHIFT(double, 8);
-        else if (bc == 12) DSBCG_SHIFT(double, 12);
-        else DSBCG_SHIFT(double, 16);
-    } else {
-        if (bc == 4) DSBCG_SHIFT(float, 4);
-        else if (bc == 8) DSBCG_SHIFT(float, 8);
-        else if (bc == 12) DSBCG_SHIFT(float, 12);
-        else DSBCG_SHIFT(float, 16);
-    }
-#undef DSBCG_SHIFT
+hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
+    if (a.K < 1 || a.K > kWinMax || a.m < 1 || a.m > 16 || a.bend > 16 || a.bp0 > 16)
+        return hipErrorInvalidValue;
+    int cols = 0;
+    for (int u = 0; u < a.K; ++u) cols += a.wb[u];
+    if (cols > (fp64 ? kWinCols64 : kWinCols32)) return hipErrorInvalidValue;
+    if (a.nrows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.nrows + 63) / 64));
+    const int bc = a.bend <= 4 ? 4 : a.bend <= 8 ? 8 : 16;
+    const int mc = a.m <= 4 ? 4 : a.m <= 8 ? 8 : 16;
+#define DSBCG_WIN(R, B, M) hipLaunchKernelGGL((window_kernel<R, B, M>), grid, dim3(256), 0, st, a)
+#define DSBCG_WIN_M(R, B)                   \
+    do {                                    \
+        if (mc == 4) DSBCG_WIN(R, B, 4);    \
+        else if (mc == 8) DSBCG_WIN(R, B, 8); \
+        else DSBCG_WIN(R, B, 16);           \
+    } while (0)
+#define DSBCG_WIN_B(R)                      \
+    do {                                    \
+        if (bc == 4) DSBCG_WIN_M(R, 4);     \
+        else if (bc == 8) DSBCG_WIN_M(R, 8); \
+        else DSBCG_WIN_M(R, 16);            \
+    } while (0)
+    if (fp64) DSBCG_WIN_B(double);
+    else DSBCG_WIN_B(float);
+#undef DSBCG_WIN_B
+#undef DSBCG_WIN_M
+#undef DSBCG_WIN
     return hipGetLastError();
 }
 

@@ -52,27 +52,36 @@ struct FieldDesc {
 hipError_t copy_field(int64_t V, int cols, FieldDesc in, FieldDesc out, bool accumulate,
                       double scale, hipStream_t st);
 
-// Per-shift update of Sec. 3 in block form, for the listed shifts j:
-//   P_j <- V_i - P_j N_j      (or P_j <- V_i on the first step)
-//   X_j[:, l] += P_j M_j[:, l] for the columns l set in colmask[j]
-// All blocks column-major with column stride nrows.
-struct ShiftArgs {
+// Window update of the per-shift iterates over block steps i0+1 .. i0+K:
+//   X_j += P_{j,i0} Fp_j + sum_u V_u F_{j,u}          (columns in xmask[j])
+//   P_{j,i0+K} = P_{j,i0} G_j + sum_u V_u H_{j,u}      (shifts with pmask set)
+// V_u: the K Lanczos blocks of the window (widths wb[u]), shared by all
+// shifts and staged once per row tile in LDS.  Coefficients are [s][16*16]
+// (G, Fp) and [s][kWin][16*16] (H, F) in the data precision.
+constexpr int kWinMax = 16;
+struct WinArgs {
     int64_t nrows;
-    const void *V;              // b columns
-    int b, bp, m;
-    const void *Pold;           // [s][bp][n]
-    void *Pnew;                 // [s][b][n]
-    int64_t pstride;            // elements between shifts in the P buffers
-    void *X;                    // [s][m][n]
+    int K;
+    int wb[kWinMax];
+    const void *Vw[kWinMax];
+    int bp0;                    // width of P_{j,i0} (0: no P term)
+    const void *Pold;
+    void *Pnew;
+    int bend;                   // width of P_{j,i0+K}
+    int64_t pstride;
+    int m;
+    void *X;
     int64_t xstride;
-    const void *N;              // [s][16*16] coefficients in the data precision
-    const void *M;              // [s][16*16]
-    const int32_t *shifts;      // device list of shift indices
+    const void *G, *Fp, *H, *F; // coefficient arrays (data precision)
+    const int32_t *shifts;
     int nshift;
-    const uint32_t *colmask;    // device [s] active-column bit masks
-    int first;
+    const uint32_t *xmask;      // [s] columns to update
+    const int32_t *count;       // [s] window slots of each shift
+    const int32_t *pmask;       // [s] nonzero: write P_{j,i0+K}
 };
-hipError_t shift_update(bool fp64, const ShiftArgs &a, hipStream_t st);
+// Largest sum of window widths one launch supports (LDS budget).
+constexpr int kWinCols64 = 48, kWinCols32 = 96;
+hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st);
 
 // Checks a field for NaN/Inf: sets *flag (device int) to 1 if any is found.
 hipError_t find_nonfinite(const double *data, int64_t count, int32_t *flag, hipStream_t st);

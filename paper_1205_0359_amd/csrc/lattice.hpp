@@ -26,12 +26,15 @@ __device__ inline void site_coords(const Geom &g, int x, int c[4]) {
     c[3] = x / g.L[2];
 }
 
-// Neighbour of site x (coordinates c) one step along mu, forward or backward.
+// Neighbour of site x (coordinates c) one step along mu, forward or backward
+// (periodic).  Written with selects rather than branches so that the hops of
+// a stencil stay straight-line code.
 __device__ inline int hop(const Geom &g, int x, const int c[4], int mu, bool fwd) {
     int stride = 1;
     for (int d = 0; d < mu; ++d) stride *= g.L[d];
-    if (fwd) return (c[mu] == g.L[mu] - 1) ? x - (g.L[mu] - 1) * stride : x + stride;
-    return (c[mu] == 0) ? x + (g.L[mu] - 1) * stride : x - stride;
+    const int wrap = g.L[mu] * stride;
+    return fwd ? x + stride - (c[mu] == g.L[mu] - 1 ? wrap : 0)
+               : x - stride + (c[mu] == 0 ? wrap : 0);
 }
 
 // Spin indices (a, b) that form the half spinor h_k = p_a + coef * p_b for

@@ -138,7 +138,6 @@ __global__ __launch_bounds__(64) void shift_coeffs_kernel(SmallState *st, StepRe
         for (int e = t; e < bp * b; e += 64) {
             const int r = e / b, c = e - r * b;
             st->N[j][r * 16 + c] = Nn[r * 16 + c];
-            st->N32[j][r * 16 + c] = cvt<float>(Nn[r * 16 + c]);
         }
     }
     // M = Delta^{-1} Z: one column per lane
@@ -155,7 +154,6 @@ __global__ __launch_bounds__(64) void shift_coeffs_kernel(SmallState *st, StepRe
     for (int e = t; e < b * m; e += 64) {
         const int r = e / m, c = e - r * m;
         st->M[j][r * 16 + c] = Zs[r * 16 + c];
-        st->M32[j][r * 16 + c] = cvt<float>(Zs[r * 16 + c]);
     }
 }
 
@@ -164,6 +162,131 @@ hipError_t small_shift_coeffs(SmallState *st, StepReport *rep, const zd *alpha_r
     if (nact <= 0) return hipSuccess;
     hipLaunchKernelGGL(shift_coeffs_kernel, dim3(nact), dim3(64), 0, stream, st, rep, alpha_raw,
                        first, shift_list);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Window recurrences (one 64-lane workgroup per active shift), applied after
+// N_{j,i} and M_{j,i} of step i are known.  With Mh the columns of M_{j,i}
+// still being updated:
+//   first step of a window:  Wg = -N, Wfp = Wg Mh, Wh_0 = I, Wf_0 = Mh
+//   later steps:             Wg <- -Wg N, Wfp += Wg Mh,
+//                            Wh_u <- -Wh_u N, Wf_u += Wh_u Mh  (u < t),
+//                            Wh_t = I, Wf_t = Mh
+// (P_{j,i} = V_i - P_{j,i-1} N_{j,i} and X_j += P_{j,i} Mh unrolled over the window).
+// ---------------------------------------------------------------------------
+__device__ inline void mat_neg_mul(zd *A, const zd *N, int rows, int inner, int cols, zd *tmp) {
+    // A (rows x inner) <- -A N (inner x cols), tmp: scratch of the same size in LDS
+    const int t = threadIdx.x;
+    for (int e = t; e < rows * cols; e += blockDim.x) {
+        const int r = e / cols, c = e - r * cols;
+        zd v = mk<double>(0, 0);
+        for (int k = 0; k < inner; ++k) v = v - A[r * 16 + k] * N[k * 16 + c];
+        tmp[r * 16 + c] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < 256; e += blockDim.x) {
+        const int r = e / 16, c = e - r * 16;
+        A[e] = (r < rows && c < cols) ? tmp[e] : mk<double>(0, 0);
+    }
+    __syncthreads();
+}
+
+__device__ inline void mat_mul_acc(zd *F, const zd *A, const zd *Mh, int rows, int inner, int cols,
+                                   bool overwrite) {
+    // F (rows x cols) (=|+=) A (rows x inner) Mh (inner x cols)
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        const int r = e / 16, c = e - r * 16;
+        zd v = mk<double>(0, 0);
+        if (r < rows && c < cols)
+            for (int k = 0; k < inner; ++k) v = v + A[r * 16 + k] * Mh[k * 16 + c];
+        F[e] = overwrite ? v : F[e] + v;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void window_update_kernel(SmallState *st, StepReport *rep, WindowStep w,
+                                                           const int32_t *__restrict__ list) {
+    __shared__ zd Ns[256], Mh[256], A[256], tmp[256];
+    const int j = list[blockIdx.x];
+    const int t = threadIdx.x;
+    const uint32_t mask = rep->colmask[j];
+    for (int e = t; e < 256; e += 64) {
+        const int r = e / 16, c = e - r * 16;
+        Ns[e] = st->N[j][e];
+        Mh[e] = (r < w.b && c < w.m && ((mask >> c) & 1u)) ? st->M[j][e] : mk<double>(0, 0);
+    }
+    __syncthreads();
+    if (w.bp0 > 0) {
+        // Wg, Wfp
+        for (int e = t; e < 256; e += 64) A[e] = st->Wg[j][e];
+        __syncthreads();
+        if (w.t == 0) {
+            // Wg_{i0} = I (bp0 x bp0), so Wg = -N
+            for (int e = t; e < 256; e += 64) {
+                const int r = e / 16, c = e - r * 16;
+                A[e] = (r < w.bp0 && c < w.b) ? -Ns[e] : mk<double>(0, 0);
+            }
+            __syncthreads();
+        } else {
+            mat_neg_mul(A, Ns, w.bp0, w.bp, w.b, tmp);
+        }
+        for (int e = t; e < 256; e += 64) st->Wg[j][e] = A[e];
+        for (int e = t; e < 256; e += 64) tmp[e] = (w.t == 0) ? mk<double>(0, 0) : st->Wfp[j][e];
+        __syncthreads();
+        mat_mul_acc(tmp, A, Mh, w.bp0, w.b, w.m, false);
+        for (int e = t; e < 256; e += 64) st->Wfp[j][e] = tmp[e];
+        __syncthreads();
+    }
+    for (int u = 0; u < w.t; ++u) {
+        for (int e = t; e < 256; e += 64) A[e] = st->Wh[j][u][e];
+        __syncthreads();
+        mat_neg_mul(A, Ns, w.wb[u], w.bp, w.b, tmp);
+        for (int e = t; e < 256; e += 64) st->Wh[j][u][e] = A[e];
+        for (int e = t; e < 256; e += 64) tmp[e] = st->Wf[j][u][e];
+        __syncthreads();
+        mat_mul_acc(tmp, A, Mh, w.wb[u], w.b, w.m, false);
+        for (int e = t; e < 256; e += 64) st->Wf[j][u][e] = tmp[e];
+        __syncthreads();
+    }
+    for (int e = t; e < 256; e += 64) {
+        const int r = e / 16, c = e - r * 16;
+        st->Wh[j][w.t][e] = (r == c && r < w.b) ? mk<double>(1, 0) : mk<double>(0, 0);
+        st->Wf[j][w.t][e] = Mh[e];
+    }
+    if (t == 0) {
+        st->Wmask[j] = (w.t == 0 ? 0u : st->Wmask[j]) | mask;
+        st->Wcount[j] = w.t + 1;
+    }
+    __syncthreads();
+    // FP32 copies for the FP32 window kernel
+    for (int e = t; e < 256; e += 64) {
+        st->Wg32[j][e] = cvt<float>(st->Wg[j][e]);
+        st->Wfp32[j][e] = cvt<float>(st->Wfp[j][e]);
+    }
+    for (int u = 0; u <= w.t; ++u)
+        for (int e = t; e < 256; e += 64) {
+            st->Wh32[j][u][e] = cvt<float>(st->Wh[j][u][e]);
+            st->Wf32[j][u][e] = cvt<float>(st->Wf[j][u][e]);
+        }
+}
+
+hipError_t small_window_update(SmallState *st, StepReport *rep, WindowStep ws,
+                               const int32_t *shift_list, int nact, hipStream_t stream) {
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(window_update_kernel, dim3(nact), dim3(64), 0, stream, st, rep, ws, shift_list);
+    return hipGetLastError();
+}
+
+__global__ void window_reset_kernel(SmallState *st, int s) {
+    for (int j = threadIdx.x; j < s; j += blockDim.x) {
+        st->Wmask[j] = 0u;
+        st->Wcount[j] = 0;
+    }
+}
+
+hipError_t small_window_reset(SmallState *st, int s, hipStream_t stream) {
+    hipLaunchKernelGGL(window_reset_kernel, dim3(1), dim3(64), 0, stream, st, s);
     return hipGetLastError();
 }
 

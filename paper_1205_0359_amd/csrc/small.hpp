@@ -8,6 +8,7 @@ namespace dsbcg {
 
 constexpr int kS = 16;       // largest shift count / block width handled by the small kernels
 constexpr int kStack = 256;  // largest number of stacked right-hand-side columns
+constexpr int kWin = 16;     // largest number of block steps in one update window
 
 // Matrices are 16 x 16 row-major (leading dimension 16); only the leading
 // rows x cols part is meaningful.
@@ -25,8 +26,19 @@ struct SmallState {
     zd Z[kS][256];       // per shift: Z_{j,i} (b x m)
     zd N[kS][256];       // per shift: N_{j,i} (bp x b)
     zd M[kS][256];       // per shift: M_{j,i} (b x m)
-    zf N32[kS][256];     // FP32 copies of N and M for the FP32 block updates
-    zf M32[kS][256];
+    // Window of block steps i0+1 .. i0+t (per shift): within it
+    //   P_{j,i} = P_{j,i0} Wg_j + sum_u V_{i0+1+u} Wh_{j,u}
+    //   X_j increment = P_{j,i0} Wfp_j + sum_u V_{i0+1+u} Wf_{j,u}
+    zd Wg[kS][256];             // b_{i0} x b_i
+    zd Wfp[kS][256];            // b_{i0} x m
+    zd Wh[kS][kWin][256];       // b_{i0+1+u} x b_i
+    zd Wf[kS][kWin][256];       // b_{i0+1+u} x m
+    zf Wg32[kS][256];
+    zf Wfp32[kS][256];
+    zf Wh32[kS][kWin][256];
+    zf Wf32[kS][kWin][256];
+    uint32_t Wmask[kS];         // columns of X_j touched in the window
+    int32_t Wcount[kS];         // window slots holding coefficients of shift j
     double sigma[kS];
     double bnorm[kStack];       // norms of the stacked right-hand-side columns
     int32_t colmap[kS][kS];     // stacked column of right-hand side l of shift j
@@ -54,6 +66,17 @@ hipError_t small_prep_alpha(SmallState *st, const zd *alpha_raw, hipStream_t str
 // hermitised): Delta_{j,i}, its Cholesky factor, N_{j,i} and M_{j,i}.
 hipError_t small_shift_coeffs(SmallState *st, StepReport *rep, const zd *alpha_raw, int first,
                               const int32_t *shift_list, int nact, hipStream_t stream);
+
+// Window bookkeeping for step i (after small_shift_coeffs): slot t = i - i0 - 1
+// of the window, widths wb[u] of the window blocks, b_{i0} (0 when the window
+// starts at step 1, i.e. there is no stored P), current and previous widths.
+struct WindowStep {
+    int t, bp0, b, bp, m;
+    int wb[kWin];
+};
+hipError_t small_window_update(SmallState *st, StepReport *rep, WindowStep ws,
+                               const int32_t *shift_list, int nact, hipStream_t stream);
+hipError_t small_window_reset(SmallState *st, int s, hipStream_t stream);
 
 // First pass of the deflated CholQR of W: Cholesky of G = W^H W with column
 // dropping (remainder <= tau_W * ||T||_est); also updates ||T||_est from

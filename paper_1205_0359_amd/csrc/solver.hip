@@ -62,16 +62,20 @@ struct DevBuf {
 };
 
 enum ProfClass {
-    kProfStencil = 0,   // one Wilson D or D^H pass
-    kProfBlock,         // tall-skinny combination / Gram kernels of the block step
-    kProfShift,         // fused per-shift P_j / X_j update
-    kProfSmall,         // small FP64 algebra and Gram reductions
+    kProfStencil = 0,   // one Wilson D or D^H pass, FP64 (FP32: + 1)
+    kProfBlock = 2,     // tall-skinny combination / Gram kernels of the block step
+    kProfShift = 4,     // windowed per-shift P_j / X_j update
+    kProfSmall = 6,     // small FP64 algebra and Gram reductions
     kProfConvert,       // layout conversions, widening, accumulation
     kProfGrad,          // link-derivative stencil
     kProfClasses
 };
-const char *const kProfNames[kProfClasses] = {"wilson_stencil", "block_gram_update", "shift_update",
-                                              "small_algebra",  "convert",           "link_grad"};
+const char *const kProfNames[kProfClasses] = {
+    "wilson_stencil.f64", "wilson_stencil.f32", "block_gram_update.f64", "block_gram_update.f32",
+    "shift_update.f64",   "shift_update.f32",   "small_algebra",         "convert",
+    "link_grad"};
+// class of a kernel family in the given data precision
+inline int prof_cls(int family, bool fp64) { return family + (fp64 ? 0 : 1); }
 
 struct ProfRec {
     int cls;
@@ -93,23 +97,28 @@ struct dsbcg_ctx {
     int64_t prof_launches[kProfClasses] = {};
     // workspace
     DevBuf Ul64, Ul32;                                   // structure-of-arrays links
-    DevBuf V[3], T, W, P[2], X;                          // FP64 iteration
-    DevBuf V32[3], T32, W32, P32[2], Xlo;                // FP32 iteration
+    DevBuf V0, T, W, P[2], X;                            // FP64 iteration (V0: V_1)
+    DevBuf T32, W32, P32[2], Xlo;                        // FP32 iteration
     DevBuf Bint, Q, wbuf;                                // deflated QR of B
     DevBuf R0, R1, R2, R3, Rres, Xref;                   // true residuals, refinement
     DevBuf Xin, Yout;                                    // dsbcg_apply_* conversions
-    DevBuf partials, red, list, st, rep;
+    DevBuf partials, red, list, wlist, st, rep;
+    std::vector<DevBuf> Vring, Vring32;                  // window rings of Lanczos blocks
     StepReport *rep_host = nullptr;
     int32_t *list_host = nullptr;
     int nwg_max = 2048;
 
     ~dsbcg_ctx() {
-        DevBuf *all[] = {&Ul64, &Ul32, &V[0], &V[1], &V[2], &T,   &W,    &P[0], &P[1], &X,
-                         &V32[0], &V32[1], &V32[2], &T32, &W32, &P32[0], &P32[1], &Xlo,
+        DevBuf *all[] = {&Ul64, &Ul32, &V0,  &T,   &W,    &P[0], &P[1], &X,
+                         &T32, &W32, &P32[0], &P32[1], &Xlo,
                          &Bint, &Q,    &wbuf, &R0,   &R1,   &R2,  &R3,   &Rres, &Xref, &Xin,
-                         &Yout, &partials, &red, &list, &st, &rep};
+                         &Yout, &partials, &red, &list, &wlist, &st, &rep};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
+        for (auto &b : Vring)
+            if (b.p) (void)hipFree(b.p);
+        for (auto &b : Vring32)
+            if (b.p) (void)hipFree(b.p);
         if (rep_host) (void)hipHostFree(rep_host);
         if (list_host) (void)hipHostFree(list_host);
         for (auto &r : prof_pending) {
@@ -206,13 +215,6 @@ double stencil_bytes(const Geom &g, int nb, size_t esz) {
     return (double)g.V * (2.0 * 12 * nb + 36.0) * (double)esz;
 }
 
-double shift_bytes(const ShiftArgs &a, bool fp64) {
-    // V_i row once; per shift: P_{j,i-1} row, P_{j,i} row, X_j row read and written
-    double cols = a.b;
-    for (int js = 0; js < a.nshift; ++js) cols += (a.first ? 0 : a.bp) + a.b + 2.0 * a.m;
-    return cols * (double)a.nrows * (double)(fp64 ? sizeof(zd) : sizeof(zf));
-}
-
 double copy_bytes(int64_t V, int cols, size_t in_esz, size_t out_esz, bool accumulate) {
     return (double)V * 12 * cols * ((double)in_esz + (accumulate ? 2.0 : 1.0) * (double)out_esz);
 }
@@ -224,7 +226,7 @@ int ensure_common(dsbcg_ctx *h) {
     CHK(ensure(h->st, sizeof(SmallState)));
     CHK(ensure(h->rep, sizeof(StepReport)));
     if (!h->rep_host) HIPCHK(hipHostMalloc((void **)&h->rep_host, sizeof(StepReport), 0));
-    if (!h->list_host) HIPCHK(hipHostMalloc((void **)&h->list_host, 64 * sizeof(int32_t), 0));
+    if (!h->list_host) HIPCHK(hipHostMalloc((void **)&h->list_host, 128 * sizeof(int32_t), 0));
     return DSBCG_OK;
 }
 
@@ -259,7 +261,7 @@ struct Ts {
         if (a.gram == 2) per_row += a.bl;
         const double bytes = per_row * (double)nrows * (fp64 ? sizeof(zd) : sizeof(zf));
         int nwg = 0;
-        PROF_LAUNCH(h, kProfBlock, bytes, st, ts_run(fp64, a, h->nwg_max, &nwg, st));
+        PROF_LAUNCH(h, prof_cls(kProfBlock, fp64), bytes, st, ts_run(fp64, a, h->nwg_max, &nwg, st));
         if (nwg_out) *nwg_out = nwg;
         return DSBCG_OK;
     }
@@ -307,7 +309,7 @@ int validate_geom(const int32_t *L) {
 
 int stencil(dsbcg_ctx *h, bool fp64, const void *Ul, double kappa, const void *X, void *Y, int b,
             bool dagger, hipStream_t st) {
-    PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, b, fp64 ? sizeof(zd) : sizeof(zf)), st,
+    PROF_LAUNCH(h, prof_cls(kProfStencil, fp64), stencil_bytes(h->g, b, fp64 ? sizeof(zd) : sizeof(zf)), st,
                 wilson_apply(h->g, fp64, Ul, kappa, X, Y, b, dagger, st));
     return DSBCG_OK;
 }
@@ -341,7 +343,7 @@ struct SolveStats {
 // columns in h->Bint): classical Gram-Schmidt applied twice, column by
 // column, in column order.  Column l is dropped when its remainder is
 // <= tau_B ||b_l|| (deflation, Sec. 1 and the deflated block Lanczos process
-// of Sec. 3).  Leaves V_1 (FP64, m1 <= 16 columns) in h->V[0] and rho in the
+// of Sec. 3).  Leaves V_1 (FP64, m1 <= 16 columns) in h->V0 and rho in the
 // small state; returns DSBCG_ERR_ARG with *m1_out = -1 when the rank exceeds 16.
 int initial_qr(dsbcg_ctx *h, int M, double tau_B, hipStream_t st, int *m1_out) {
     const int64_t n = 12 * (int64_t)h->g.V;
@@ -426,7 +428,7 @@ int initial_qr(dsbcg_ctx *h, int M, double tau_B, hipStream_t st, int *m1_out) {
         }
     }
     if (k > 0)
-        HIPCHK(hipMemcpyAsync(h->V[0].p, Qp, (size_t)n * k * sizeof(zd), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(h->V0.p, Qp, (size_t)n * k * sizeof(zd), hipMemcpyDeviceToDevice, st));
     *m1_out = k;
     return DSBCG_OK;
 }
@@ -505,18 +507,6 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
     return DSBCG_OK;
 }
 
-// Buffers of one working precision.
-struct WorkSet {
-    void *V[3];
-    void *T, *W;
-    void *P[2];
-    void *X;            // solution accumulator [s][m][n]
-    const void *Ul;     // structure-of-arrays links
-    const void *N, *M;  // per-shift coefficients in this precision
-    bool fp64;
-    size_t esz;
-};
-
 // The DSBlockCG iteration.  FP64 form: every vector in FP64.  FP32 form: the
 // iteration starts in FP64 and continues the same recurrences with FP32
 // vectors once every active estimate is <= switch_at; from then on
@@ -535,7 +525,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     CHK(ensure(h->Bint, (size_t)n * M * sizeof(zd)));
     CHK(ensure(h->Q, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
     CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
-    CHK(ensure(h->V[0], (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
+    CHK(ensure(h->V0, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
     CHK(ensure(h->X, (size_t)n * m * s * sizeof(zd)));
 
     SmallState *S = stp(h);
@@ -555,32 +545,49 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
 
     // widths never exceed m1 after the initial deflation
     const int wmax = std::max(m1, 1);
+    // window lengths: the LDS tile of the window kernel holds kWinCols columns
+    const int kauto64 = std::max(1, std::min(kWinMax, kWinCols64 / wmax));
+    const int kauto32 = std::max(1, std::min(kWinMax, kWinCols32 / wmax));
+    const int K64 = o.window > 0 ? std::min(o.window, kauto64) : kauto64;
+    const int K32 = o.window > 0 ? std::min(o.window, kauto32) : kauto32;
+    const int nring = std::max(K64, form32 ? K32 : 1) + 2;
     const size_t b64 = (size_t)n * wmax * sizeof(zd), b32 = (size_t)n * wmax * sizeof(zf);
-    for (int k = 0; k < 3; ++k) CHK(ensure(h->V[k], std::max(b64, (size_t)n * m * sizeof(zd))));
+    if ((int)h->Vring.size() < nring) h->Vring.resize(nring);
+    if (form32 && (int)h->Vring32.size() < nring) h->Vring32.resize(nring);
+    for (int k = 1; k < nring; ++k) CHK(ensure(h->Vring[k], b64));
+    for (int k = 0; k < (form32 ? nring : 0); ++k) CHK(ensure(h->Vring32[k], b32));
     CHK(ensure(h->T, b64));
     CHK(ensure(h->W, b64));
     CHK(ensure(h->P[0], b64 * s));
     CHK(ensure(h->P[1], b64 * s));
-    WorkSet w64{{h->V[0].p, h->V[1].p, h->V[2].p}, h->T.p, h->W.p, {h->P[0].p, h->P[1].p}, h->X.p,
-                h->Ul64.p, S->N, S->M, true, sizeof(zd)};
-    WorkSet w32{};
+    CHK(ensure(h->wlist, 2 * 64 * sizeof(int32_t)));
+    std::vector<void *> ring64(nring), ring32(nring, nullptr);
+    ring64[0] = h->V0.p;
+    for (int k = 1; k < nring; ++k) ring64[k] = h->Vring[k].p;
+    for (int k = 0; k < (form32 ? nring : 0); ++k) ring32[k] = h->Vring32[k].p;
     if (form32) {
-        for (int k = 0; k < 3; ++k) CHK(ensure(h->V32[k], b32));
         CHK(ensure(h->T32, b32));
         CHK(ensure(h->W32, b32));
         CHK(ensure(h->P32[0], b32 * s));
         CHK(ensure(h->P32[1], b32 * s));
         CHK(ensure(h->Xlo, (size_t)n * m * s * sizeof(zf)));
-        w32 = WorkSet{{h->V32[0].p, h->V32[1].p, h->V32[2].p}, h->T32.p, h->W32.p,
-                      {h->P32[0].p, h->P32[1].p}, h->Xlo.p, h->Ul32.p, S->N32, S->M32, false, sizeof(zf)};
     }
-    WorkSet *ws = &w64;
     bool lo = false;
     int since_flush = 0;
+    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_reset(S, s, st));
+
+    // Lanczos blocks by step: vidx[i] = ring slot of V_i, bw[i] = width
+    std::vector<int> vidx(2, -1), bw(2, 0);
+    std::vector<int> freelist;
+    for (int k = nring - 1; k >= 1; --k) freelist.push_back(k);
+    vidx[1] = 0;
+    bw[1] = m1;
+    auto ring = [&](int i) -> void * { return lo ? ring32[vidx[i]] : ring64[vidx[i]]; };
 
     int b = m1, bp = 0;
-    int cur = 0, prev = 2, next = 1;
-    int pcur = 0;  // P buffer holding P_{j,i-1}
+    int pcur = 0;        // P buffer holding P_{j,i0}
+    int i0 = 0;          // the current window covers steps i0+1 .. i
+    std::vector<int32_t> wset;  // shifts updated in the current window
     int status = DSBCG_OK;
     int iters = 0;
     const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
@@ -598,7 +605,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                 if ((h->rep_host->colmask[j] >> l) & 1u) e = std::max(e, h->rep_host->est[j][l]);
         return e;
     };
-    auto flush = [&](void) -> int {
+    auto flush_lo = [&](void) -> int {
         // X_hi += X_lo, X_lo = 0 (FP64 accumulation of the solution)
         CHK(copy(h, m * s, cm(h->Xlo.p, n, false), cm(h->X.p, n, true), true, st));
         HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
@@ -606,37 +613,113 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         stt.reliable_updates += 1;
         return DSBCG_OK;
     };
+    // Apply the window i0+1 .. i to X_j (and P_j for the shifts still active).
+    auto release = [&](int i) {
+        // V_{i0} .. V_{i-1} are no longer needed once the window ends at step i
+        for (int k = std::max(i0, 1); k < i; ++k)
+            if (vidx[k] >= 0) {
+                freelist.push_back(vidx[k]);
+                vidx[k] = -1;
+            }
+        i0 = i;
+    };
+    auto apply_window = [&](int i) -> int {
+        if (wset.empty() || i <= i0) {
+            release(i);
+            wset = act;
+            return DSBCG_OK;
+        }
+        WinArgs wa;
+        memset(&wa, 0, sizeof(wa));
+        wa.nrows = n;
+        wa.K = i - i0;
+        for (int u = 0; u < wa.K; ++u) {
+            wa.wb[u] = bw[i0 + 1 + u];
+            wa.Vw[u] = ring(i0 + 1 + u);
+        }
+        wa.bp0 = i0 >= 1 ? bw[i0] : 0;
+        wa.Pold = lo ? h->P32[pcur].p : h->P[pcur].p;
+        wa.Pnew = lo ? h->P32[pcur ^ 1].p : h->P[pcur ^ 1].p;
+        wa.bend = bw[i];
+        wa.pstride = n * wmax;
+        wa.m = m;
+        wa.X = lo ? h->Xlo.p : h->X.p;
+        wa.xstride = n * m;
+        wa.G = lo ? (const void *)S->Wg32 : (const void *)S->Wg;
+        wa.Fp = lo ? (const void *)S->Wfp32 : (const void *)S->Wfp;
+        wa.H = lo ? (const void *)S->Wh32 : (const void *)S->Wh;
+        wa.F = lo ? (const void *)S->Wf32 : (const void *)S->Wf;
+        int32_t *wl = h->list_host + 64;  // pinned: window shift list, then P flags
+        std::vector<int32_t> pm(s, 0);
+        for (int j : act) pm[j] = 1;
+        for (size_t q = 0; q < wset.size(); ++q) wl[q] = wset[q];
+        for (int j = 0; j < s; ++j) wl[16 + j] = pm[j];
+        HIPCHK(hipMemcpyAsync(h->wlist.p, wl, 64 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        wa.shifts = (const int32_t *)h->wlist.p;
+        wa.nshift = (int)wset.size();
+        wa.pmask = (const int32_t *)h->wlist.p + 16;
+        wa.xmask = S->Wmask;
+        wa.count = S->Wcount;
+        double cols = 0;
+        for (int u = 0; u < wa.K; ++u) cols += wa.wb[u];
+        cols += (double)wset.size() * (wa.bp0 + wa.bend + 2.0 * m);
+        PROF_LAUNCH(h, prof_cls(kProfShift, !lo), cols * (double)n * (lo ? sizeof(zf) : sizeof(zd)), st,
+                    window_apply(!lo, wa, st));
+        // the next window starts after step i; P_{j,i} now lives in P[pcur ^ 1].
+        // (The pinned list is rewritten only after the next step's report,
+        // which waits for the stream.)
+        pcur ^= 1;
+        release(i);
+        wset = act;
+        if (lo && since_flush >= std::max(1, o.ru_interval)) CHK(flush_lo());
+        return DSBCG_OK;
+    };
     active_list();
+    wset = act;
     bool done = (m1 == 0) || (act.empty() && o.fixed_iters <= 0);
 
     for (int i = 1; !done && i <= steps; ++i) {
         if (form32 && !lo && max_active_est() <= switch_at) {
-            // continue the same recurrences with FP32 vectors
-            CHK(copy(h, b, cm(w64.V[cur], n, true), cm(w32.V[cur], n, false), false, st));
+            // continue the same recurrences with FP32 vectors (the window was
+            // applied at the end of the previous step)
+            CHK(copy(h, b, cm(ring64[vidx[i]], n, true), cm(ring32[vidx[i]], n, false), false, st));
             if (i > 1) {
-                CHK(copy(h, bp, cm(w64.V[prev], n, true), cm(w32.V[prev], n, false), false, st));
+                CHK(copy(h, bp, cm(ring64[vidx[i - 1]], n, true), cm(ring32[vidx[i - 1]], n, false),
+                         false, st));
                 for (int j : act)
-                    CHK(copy(h, bp, cm((zd *)w64.P[pcur] + (int64_t)j * n * wmax, n, true),
-                             cm((zf *)w32.P[pcur] + (int64_t)j * n * wmax, n, false), false, st));
+                    CHK(copy(h, bp, cm((zd *)h->P[pcur].p + (int64_t)j * n * wmax, n, true),
+                             cm((zf *)h->P32[pcur].p + (int64_t)j * n * wmax, n, false), false, st));
             }
             HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
-            ws = &w32;
             lo = true;
             since_flush = 0;
             stt.switch_iter = i;
         }
-        const bool f64 = ws->fp64;
+        const bool f64 = !lo;
+        const int K = lo ? K32 : K64;
         Ts ts{h, f64, st, n};
         iters = i;
         stt.mvms += b;
-        void *Vc = ws->V[cur], *Vp = ws->V[prev], *Vn = ws->V[next];
+        if ((int)vidx.size() < i + 2) {
+            vidx.resize(i + 2, -1);
+            bw.resize(i + 2, 0);
+        }
+        if (freelist.empty()) {
+            status = fail(DSBCG_ERR_HIP, "internal: Lanczos block ring exhausted");
+            break;
+        }
+        vidx[i + 1] = freelist.back();
+        freelist.pop_back();
+        void *Vc = ring(i), *Vp = i > 1 ? ring(i - 1) : ring(i), *Vn = ring(i + 1);
+        void *T = lo ? h->T32.p : h->T.p, *Wb = lo ? h->W32.p : h->W.p;
+        const void *Ul = lo ? h->Ul32.p : h->Ul64.p;
         // W = A V_i
-        CHK(apply_A_cm(h, f64, ws->Ul, kappa, Vc, ws->T, ws->W, b, st));
+        CHK(apply_A_cm(h, f64, Ul, kappa, Vc, T, Wb, b, st));
         // alpha_i = V_i^H (W - V_{i-1} beta_i^H)
         {
             TsArgs a = ts_args(n);
             a.K = (i > 1) ? 2 : 1;
-            a.X[0] = ws->W; a.bx[0] = b; a.C[0] = nullptr;
+            a.X[0] = Wb; a.bx[0] = b; a.C[0] = nullptr;
             a.X[1] = Vp; a.bx[1] = bp; a.C[1] = coef_slot(h, 0);
             a.bout = b;
             a.gram = 2; a.L = Vc; a.bl = b;
@@ -644,42 +727,35 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         }
         // hermitised alpha_i, -alpha_i as a coefficient
         PROF_LAUNCH(h, kProfSmall, 0.0, st, small_prep_alpha(S, red_slot(h, 0), st));
-        // per-shift coefficients and P_j / X_j updates
+        // per-shift coefficients and the window recurrences
         for (size_t q = 0; q < act.size(); ++q) h->list_host[q] = act[q];
         HIPCHK(hipMemcpyAsync(h->list.p, h->list_host, act.size() * sizeof(int32_t) + 4,
                               hipMemcpyHostToDevice, st));
         PROF_LAUNCH(h, kProfSmall, 0.0, st,
                     small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
                                        (int)act.size(), st));
-        if (!act.empty()) {
-            ShiftArgs sa;
-            sa.nrows = n;
-            sa.V = Vc;
-            sa.b = b;
-            sa.bp = bp;
-            sa.m = m;
-            sa.Pold = ws->P[pcur];
-            sa.Pnew = ws->P[pcur ^ 1];
-            sa.pstride = n * wmax;
-            sa.X = ws->X;
-            sa.xstride = n * m;
-            sa.N = ws->N;
-            sa.M = ws->M;
-            sa.shifts = (const int32_t *)h->list.p;
-            sa.nshift = (int)act.size();
-            sa.colmask = rep->colmask;
-            sa.first = (i == 1);
-            PROF_LAUNCH(h, kProfShift, shift_bytes(sa, f64), st, shift_update(f64, sa, st));
+        {
+            WindowStep wsp;
+            memset(&wsp, 0, sizeof(wsp));
+            wsp.t = i - i0 - 1;
+            wsp.bp0 = i0 >= 1 ? bw[i0] : 0;
+            wsp.b = b;
+            wsp.bp = bp;
+            wsp.m = m;
+            bw[i] = b;
+            for (int u = 0; u <= wsp.t; ++u) wsp.wb[u] = bw[i0 + 1 + u];
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        small_window_update(S, rep, wsp, (const int32_t *)h->list.p, (int)act.size(), st));
         }
         // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
         {
             TsArgs a = ts_args(n);
             a.K = (i > 1) ? 3 : 2;
-            a.X[0] = ws->W; a.bx[0] = b; a.C[0] = nullptr;
+            a.X[0] = Wb; a.bx[0] = b; a.C[0] = nullptr;
             a.X[1] = Vc; a.bx[1] = b; a.C[1] = coef_slot(h, 1);
             a.X[2] = Vp; a.bx[2] = bp; a.C[2] = coef_slot(h, 0);
             a.bout = b;
-            a.out = ws->W;
+            a.out = Wb;
             a.gram = 1;
             CHK(ts.run_reduce(a, b, 1));
         }
@@ -691,7 +767,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         {
             TsArgs a = ts_args(n);
             a.K = 1;
-            a.X[0] = ws->W; a.bx[0] = b; a.C[0] = S->C1;
+            a.X[0] = Wb; a.bx[0] = b; a.C[0] = S->C1;
             a.bout = b;
             a.gram = 1;
             CHK(ts.run_reduce(a, b, 2));
@@ -704,12 +780,11 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         {
             TsArgs a = ts_args(n);
             a.K = 1;
-            a.X[0] = ws->W; a.bx[0] = b; a.C[0] = S->Rinv;
+            a.X[0] = Wb; a.bx[0] = b; a.C[0] = S->Rinv;
             a.bout = b;
             a.out = Vn;
             CHK(ts.run(a, nullptr));
         }
-        if (lo && ++since_flush >= std::max(1, o.ru_interval)) CHK(flush());
         CHK(read_report(h, st));
         const StepReport &R = *h->rep_host;
         if (R.flags & kFlagNotHPD) {
@@ -727,17 +802,16 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         active_list();
         if (bnew == 0) done = true;
         if (o.fixed_iters <= 0 && act.empty()) done = true;
-        // rotate the three-block window
-        const int old_prev = prev;
-        prev = cur;
-        cur = next;
-        next = old_prev;
-        pcur ^= 1;
+        if (lo) ++since_flush;
+        const bool switch_next = form32 && !lo && !done && max_active_est() <= switch_at;
+        const bool ru_due = lo && since_flush >= std::max(1, o.ru_interval);
+        if (i - i0 >= K || done || i == steps || switch_next || ru_due) CHK(apply_window(i));
         bp = b;
         b = bnew;
+        bw[i + 1] = bnew;
         stt.final_width = bnew;
     }
-    if (lo) CHK(flush());
+    if (lo) CHK(flush_lo());
     stt.block_iters += iters;
     if (status == DSBCG_OK && !done && o.fixed_iters <= 0)
         status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
@@ -775,6 +849,7 @@ void dsbcg_default_opts(dsbcg_opts *o) {
     o->refine = 1;
     o->freeze = 1;
     o->switch_at = -1.0;  // resolved to min(1e-2, 1e5 * tol)
+    o->window = 0;        // automatic window length
 }
 
 const char *dsbcg_last_error(void) { return g_err.c_str(); }
@@ -893,6 +968,7 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
     if (opts) o = *opts;
     if (o.precision != DSBCG_FP64 && o.precision != DSBCG_FP32_RELIABLE)
         return fail(DSBCG_ERR_ARG, "unknown precision");
+    if (o.window < 0) return fail(DSBCG_ERR_ARG, "window must be >= 0");
     if (o.tau_B < 0) o.tau_B = 0.1 * tol;
     if (o.tau_W < 0) o.tau_W = 1e-12;
     if (o.max_iters < 1) o.max_iters = 1;

@@ -40,7 +40,7 @@ def test_default_opts_and_argument_errors_without_a_device():
 
 def test_opts_struct_matches_header_layout():
     # sizes of the C structs as the header lays them out on x86-64
-    assert ctypes.sizeof(_lib.dsbcg_opts) == 48
+    assert ctypes.sizeof(_lib.dsbcg_opts) == 56
     assert ctypes.sizeof(_lib.dsbcg_stats) == 64
 
 

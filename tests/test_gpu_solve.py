@@ -60,6 +60,40 @@ def test_fixed_iteration_parity_fp64(L, m, sig, k, kind):
     np.testing.assert_allclose(st["est_relres"], ref.est, rtol=1e-8, atol=1e-14)
 
 
+@pytest.mark.parametrize("window", [1, 3, 5])
+def test_window_lengths_fixed_iterations(window):
+    """Per-shift updates applied once per window of block steps (the last
+    window ragged) give the oracle's step-wise iterates."""
+    L, m, sig, k = (4, 4, 4, 6), 6, (1e-3, 3e-2, 0.5), 11
+    announce("solve window", L, m, sig, k, window)
+    kappa = 0.124
+    U, B = _problem(L, m, 805, "haar")
+    n = 12 * int(np.prod(L))
+    ref = oracle.dsbcg(_op(L, U, kappa), B.reshape(n, m), sig, 1e-30, fixed_iters=k)
+    X, st = _gpu_solve(L, U, kappa, B, sig, 1e-30, fixed_iters=k, window=window)
+    for j in range(len(sig)):
+        assert rel_fro(X[j].reshape(n, m), ref.X[j]) <= 1e-10, j
+
+
+def test_window_with_freezing():
+    """Shifts and columns that freeze inside a window: window lengths 1 and
+    automatic agree, and every system meets the tolerance."""
+    L, m = (4, 4, 4, 4), 5
+    sig = (1e-3, 0.05, 0.8, 4.0)
+    announce("solve window freezing", L, m, sig)
+    U, B = _problem(L, m, 806, "smooth")
+    B[..., 2] *= 1e-3  # a column with a much smaller norm converges on its own schedule
+    X1, s1 = _gpu_solve(L, U, 0.125, B, sig, 1e-10, window=1)
+    X0, s0 = _gpu_solve(L, U, 0.125, B, sig, 1e-10)
+    assert s1["block_iters"] == s0["block_iters"]
+    assert s0["true_relres"].max() <= 1e-10 and s1["true_relres"].max() <= 1e-10
+    n = 12 * int(np.prod(L))
+    for j in range(len(sig)):
+        assert rel_fro(X0[j].reshape(n, m), X1[j].reshape(n, m)) <= 1e-11, j
+    with pytest.raises(dsb.DSBCGError):
+        _gpu_solve(L, U, 0.125, B, sig, 1e-10, window=-1)
+
+
 def test_converges_to_dense_solution_4x4x4x4():
     w = inputs.WORKLOADS["haar4^4_m4_s3"]
     announce("solve converge", w.name)
