@@ -45,10 +45,145 @@ def parse():
     p.add_argument("--no-compare", dest="compare", action="store_false")
     p.add_argument("--cpu-baseline", action="store_true", default=True)
     p.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    p.add_argument("--cpu-steps", type=int, default=2,
+    p.add_argument("--cpu-steps", type=int, default=6,
                    help="block steps of the oracle sample")
     p.add_argument("--stencil-calls", type=int, default=100)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="first run a plain 1 GiB device copy (the reference kernel for "
+                        "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    p.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                   help="turn two rocprofv3 --pmc CSV runs (FETCH_SIZE, WRITE_SIZE) of a "
+                        "--calibrate-copy bench into profiles/traffic.json, then exit")
+    p.add_argument("--summarize-stats", metavar="STATS_DIR",
+                   help="print a per-class summary of a rocprofv3 --kernel-trace --stats CSV run, "
+                        "then exit")
+    p.add_argument("--command", default="", help="command line recorded with --ingest-counters / "
+                                                 "--summarize-stats")
     return p.parse_args()
+
+
+COPY_BYTES = 1 << 30
+SOURCES = {"wilson_stencil": ["paper_1205_0359_amd/csrc/stencil.hip",
+                              "paper_1205_0359_amd/csrc/lattice.hpp"],
+           "block_gram_update": ["paper_1205_0359_amd/csrc/blas.hip"],
+           "shift_update": ["paper_1205_0359_amd/csrc/blas.hip"],
+           "small_algebra": ["paper_1205_0359_amd/csrc/small.hip"],
+           "convert": ["paper_1205_0359_amd/csrc/blas.hip", "paper_1205_0359_amd/csrc/stencil.hip"],
+           "link_grad": ["paper_1205_0359_amd/csrc/grad.hip"]}
+
+
+def kernel_class(name: str):
+    """Profiler class of a kernel name as rocprofv3 reports it (None: not this library's)."""
+    prec = "f64" if "<double" in name else "f32"
+    if "wilson_cm_kernel" in name:
+        return "wilson_stencil." + prec
+    if "ts_reg_kernel" in name or "ts_lds_kernel" in name:
+        return "block_gram_update." + prec
+    if "window_kernel<" in name:
+        return "shift_update." + prec
+    if "copy_kernel" in name or "links_soa_kernel" in name:
+        return "convert"
+    if "link_grad_kernel" in name:
+        return "link_grad"
+    if "dsbcg::" in name:
+        return "small_algebra"
+    return None
+
+
+def _csv_rows(root, suffix):
+    import csv
+    rows = []
+    for dirpath, _, files in os.walk(root):
+        for fn in files:
+            if fn.endswith(suffix):
+                with open(os.path.join(dirpath, fn), newline="") as f:
+                    rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {root}")
+    return rows
+
+
+def _per_dispatch(root, counter):
+    """{dispatch id: (kernel name, value)} of one counter, summed over its instances."""
+    out = {}
+    for r in _csv_rows(root, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        name, val = r.get("Kernel_Name", ""), float(r.get("Counter_Value", 0) or 0)
+        prev = out.get(d, (name, 0.0))
+        out[d] = (name, prev[1] + val)
+    return out
+
+
+def ingest_counters(fetch_dir, write_dir, command):
+    fetch, write = _per_dispatch(fetch_dir, "FETCH_SIZE"), _per_dispatch(write_dir, "WRITE_SIZE")
+
+    def copy_kib(table):
+        # the calibration copy: the largest dispatch of a kernel outside this library
+        c = [v for (n, v) in table.values() if kernel_class(n) is None]
+        if not c:
+            raise SystemExit("no calibration copy dispatch found (run the bench with --calibrate-copy)")
+        return max(c)
+
+    f_fac = COPY_BYTES / (1024.0 * copy_kib(fetch))
+    w_fac = COPY_BYTES / (1024.0 * copy_kib(write))
+    acc = {}
+    for table, key in ((fetch, "fetch"), (write, "write")):
+        for name, kib in table.values():
+            cls = kernel_class(name)
+            if cls is None:
+                continue
+            e = acc.setdefault(cls, {"fetch": [], "write": []})
+            e[key].append(kib)
+    rec = {}
+    for cls, e in sorted(acc.items()):
+        nf, nw = len(e["fetch"]), len(e["write"])
+        if not nf or not nw:
+            continue
+        fk, wk = sum(e["fetch"]) / nf, sum(e["write"]) / nw
+        family = cls.split(".")[0]
+        rec[cls] = {"bytes_per_launch": 1024.0 * (fk * f_fac + wk * w_fac),
+                    "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+                    "dispatches": nf, "source_digest": source_digest(SOURCES[family])}
+    rec["_calibration"] = {"copy_bytes": COPY_BYTES, "fetch_factor": f_fac, "write_factor": w_fac,
+                           "command": command}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps(rec, indent=1, sort_keys=True))
+
+
+def summarize_stats(stats_dir, command):
+    rows = _csv_rows(stats_dir, "kernel_stats.csv")
+    cls_tot = {}
+    lines = [f"command: {command}", "",
+             "| kernel | calls | total ms | avg us | class |", "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name, calls = r["Name"], int(r["Calls"])
+        tot, avg = float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3
+        cls = kernel_class(name) or "-"
+        c = cls_tot.setdefault(cls, [0, 0.0])
+        c[0] += calls
+        c[1] += tot
+        short = name if len(name) < 90 else name[:87] + "..."
+        lines.append(f"| `{short}` | {calls} | {tot:.2f} | {avg:.1f} | {cls} |")
+    lines += ["", "| class | calls | total ms | avg us |", "|---|---|---|---|"]
+    for cls, (calls, tot) in sorted(cls_tot.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| {cls} | {calls} | {tot:.2f} | {1e3 * tot / max(calls, 1):.1f} |")
+    print("\n".join(lines))
+
+
+def copy_calibration():
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
 
 
 def source_digest(paths):
@@ -108,6 +243,7 @@ def run_form(dsb, h, dU, dB, w, prec, steps, warmup):
         "max_true_relres": worst,
         "kernels": {k: {"ms_per_solve": v["ms"] / steps,
                         "launches_per_solve": v["launches"] / steps,
+                        "bytes_per_launch": (v["bytes"] / v["launches"]) if v["launches"] else 0.0,
                         "avg_launch_us": (1e3 * v["ms"] / v["launches"]) if v["launches"] else 0.0,
                         "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0}
                     for k, v in prof.items()},
@@ -180,6 +316,12 @@ def cpu_baseline(w, gpu_iters, steps, max_sites=1 << 17):
 
 def main():
     args = parse()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters, args.command)
+        return
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats, args.command)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
               "multi-GPU form in this build", file=sys.stderr)
@@ -189,6 +331,8 @@ def main():
     import paper_1205_0359_amd as dsb
     from paper_1205_0359_amd import inputs
 
+    if args.calibrate_copy:
+        copy_calibration()
     w = inputs.WORKLOADS[args.workload]
     log(f"[bench] generating {w.name} (V={w.V}, m={w.m}, s={len(w.shifts)})")
     t = time.perf_counter()
@@ -221,16 +365,14 @@ def main():
     kern = {k: v for k, v in head["kernels"].items() if v["ms_per_solve"] > 0}
     dom = max(kern, key=lambda k: kern[k]["ms_per_solve"])
     family = dom.split(".")[0]
-    src = {"wilson_stencil": ["paper_1205_0359_amd/csrc/stencil.hip"],
-           "shift_update": ["paper_1205_0359_amd/csrc/blas.hip"],
-           "block_gram_update": ["paper_1205_0359_amd/csrc/blas.hip"],
-           "small_algebra": ["paper_1205_0359_amd/csrc/small.hip"],
-           "convert": ["paper_1205_0359_amd/csrc/blas.hip"]}[family]
+    src = SOURCES[family]
     achieved = kern[dom]["GBps"]
     traffic = stored_traffic(dom, source_digest(src))
+    alg_per_launch = kern[dom]["bytes_per_launch"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic}
+                "traffic": traffic, "algorithmic_bytes_per_launch": alg_per_launch,
+                "avg_launch_us": round(kern[dom]["avg_launch_us"], 2)}
 
     cpu = None
     if args.cpu_baseline:

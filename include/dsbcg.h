@@ -71,8 +71,9 @@ typedef struct {
     int32_t precision;    /* dsbcg_precision */
     int32_t max_iters;    /* block-step limit of the main phase (default 10000) */
     int32_t fixed_iters;  /* > 0: run exactly this many block steps, no convergence stop */
-    int32_t ru_interval;  /* FP32 form: the FP32 part of the iterates is added into the FP64
-                             solution every this many block steps and at the end (default 50) */
+    int32_t ru_interval;  /* FP32 form: the contribution of the FP32 Lanczos blocks is added
+                             into the FP64 solution at least every this many block steps and at
+                             the end (default 50) */
     double tau_B;         /* initial deflation of B: drop column l when its remainder is
                              <= tau_B * ||b_l|| (default 0.1 * tol) */
     double tau_W;         /* in-iteration deflation: drop a new basis column whose remainder is
@@ -81,9 +82,11 @@ typedef struct {
     int32_t refine;       /* 1: after the main phase, re-solve (FP64) the shifts whose true
                              residual misses tol (default 1) */
     int32_t freeze;       /* 1: stop updating a system once its estimate reaches tol (default 1) */
-    int32_t window;       /* per-shift update window: P_j and X_j are written once every
-                             `window` block steps (0: longest that fits, up to 16; 1: every
-                             step).  The result is the same up to rounding */
+    int32_t window;       /* per-shift update window: the Lanczos blocks of up to `window`
+                             block steps are kept and X_j (and P_j, if the iteration goes on)
+                             are formed from them once per window.  0: the longest window
+                             whose blocks fit in half of the free device memory, at most 128;
+                             1: every step.  The result is the same up to rounding */
     double switch_at;     /* FP32 form: the iteration runs in FP64 until every active estimated
                              relative residual is <= switch_at, then continues the same
                              recurrences with FP32 vectors (default min(1e-2, 1e5 * tol)) */
@@ -93,7 +96,8 @@ typedef struct {
     int32_t block_iters;      /* block steps of the main phase */
     int32_t rank0;            /* width of the first Lanczos block after deflating B */
     int32_t deflations;       /* columns dropped during the iteration */
-    int32_t reliable_updates; /* FP32 form: number of reliable updates */
+    int32_t reliable_updates; /* FP32 form: windows of FP32 blocks added into the FP64
+                                 solution */
     int32_t refine_iters;     /* block steps spent in refinement solves */
     int32_t final_width;      /* width of the last Lanczos block */
     int32_t switch_iter;      /* FP32 form: first block step run with FP32 vectors (0: none) */

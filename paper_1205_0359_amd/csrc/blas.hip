@@ -1,99 +1,148 @@
 // Tall-skinny block kernels of the block Lanczos process and of the
 // per-shift recurrences (Sec. 3 of the paper): products V^H W (Gram), block
 // combinations W - V alpha - V' beta^H, basis scalings W R^{-1}, and the
-// P_j / X_j updates.  All of them stream n x b blocks with b <= 16 and are
+// windowed P_j / X_j updates (matrix cores).  All of them stream n x b blocks with b <= 16 and are
 // bound by HBM bandwidth.  Blocks are column-major and one thread owns one
 // row, so a wave reads 64 consecutive elements of a column.  Gram sums are
 // accumulated in FP64 and reduced in a fixed order (bitwise repeatable).
 
 #include "blas.hpp"
 
+#include <algorithm>
+
 namespace dsbcg {
 
 // ---------------------------------------------------------------------------
-// Combination out = sum_k X_k C_k, one thread per row.  Coefficients are
-// rounded to the data precision and read from LDS with wave-uniform
-// addresses.
+// Combination out = sum_k X_k C_k and Gram products, one thread per row.
+// Widths are compile-time (B) so that every load of a row is issued before
+// the arithmetic that uses it; columns past a block's width are read at its
+// last column and meet zero coefficients.  Coefficients are rounded to the
+// data precision and read from LDS with wave-uniform addresses; C_k == NULL
+// means the identity.
 // ---------------------------------------------------------------------------
-template <typename R, int BO>
-__device__ inline void combine_row(const TsArgs &a, const cx<R> (*coef)[kMaxW * kMaxW], int64_t row,
-                                   cx<R> out[BO]) {
+template <typename R, int B>
+__device__ inline void load_coefs(const TsArgs &a, cx<R> *coef) {
+    for (int e = threadIdx.x; e < 3 * B * B; e += blockDim.x) {
+        const int k = e / (B * B), r = e - k * B * B, p = r / B, q = r - p * B;
+        cx<R> v = mk<R>(0, 0);
+        if (k < a.K && p < a.bx[k] && q < a.bout)
+            v = a.C[k] ? cvt<R>(a.C[k][p * 16 + q]) : (p == q ? mk<R>(1, 0) : mk<R>(0, 0));
+        coef[e] = v;
+    }
+}
+
+template <typename R, int B, int K>
+__device__ inline void combine_row(const TsArgs &a, const cx<R> *coef, int64_t row, cx<R> o[B]) {
 #pragma unroll
-    for (int q = 0; q < BO; ++q) out[q] = mk<R>(0, 0);
-    for (int k = 0; k < a.K; ++k) {
-        const cx<R> *X = (const cx<R> *)a.X[k] + row;
-        const int64_t cs = a.cs[k];
-        if (a.C[k] == nullptr) {
+    for (int q = 0; q < B; ++q) o[q] = mk<R>(0, 0);
+    if (B <= 8) {
+        // every input row in flight at once
+        cx<R> x[K][B];
 #pragma unroll
-            for (int q = 0; q < BO; ++q)
-                if (q < a.bout) out[q] = out[q] + X[q * cs];
-        } else {
-            for (int p = 0; p < a.bx[k]; ++p) {
-                const cx<R> x = X[p * cs];
+        for (int k = 0; k < K; ++k) {
+            // inputs k >= a.K have no block (NULL) and zero coefficients
+            if (k < a.K) {
+                const cx<R> *X = (const cx<R> *)a.X[k] + row;
+                const int last = max(a.bx[k] - 1, 0);
 #pragma unroll
-                for (int q = 0; q < BO; ++q)
-                    if (q < a.bout) cmac(out[q], x, coef[k][p * kMaxW + q]);
+                for (int p = 0; p < B; ++p) x[k][p] = X[(int64_t)min(p, last) * a.cs[k]];
+            } else {
+#pragma unroll
+                for (int p = 0; p < B; ++p) x[k][p] = mk<R>(0, 0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int p = 0; p < B; ++p) {
+                // one coefficient row at a time (all of them at once would
+                // need 4 K B^2 registers)
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < B; ++q) cmac(o[q], x[k][p], coef[(k * B + p) * B + q]);
+            }
+    } else {
+        // wide blocks: one input block at a time (only the a.K inputs that exist)
+        const int nk = min(K, a.K);
+#pragma unroll 1
+        for (int k = 0; k < nk; ++k) {
+            const cx<R> *X = (const cx<R> *)a.X[k] + row;
+            const int last = max(a.bx[k] - 1, 0);
+            cx<R> x[B];
+#pragma unroll
+            for (int p = 0; p < B; ++p) x[p] = X[(int64_t)min(p, last) * a.cs[k]];
+#pragma unroll
+            for (int p = 0; p < B; ++p) {
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < B; ++q) cmac(o[q], x[p], coef[(k * B + p) * B + q]);
             }
         }
     }
 }
 
-template <typename R>
-__device__ inline void load_coefs(const TsArgs &a, cx<R> (*coef)[kMaxW * kMaxW]) {
-    for (int k = 0; k < a.K; ++k) {
-        if (a.C[k] == nullptr) continue;
-        for (int e = threadIdx.x; e < a.bx[k] * a.bout; e += blockDim.x) {
-            const int p = e / a.bout, q = e - p * a.bout;
-            coef[k][p * kMaxW + q] = cvt<R>(a.C[k][p * 16 + q]);
-        }
-    }
-}
-
-// Gram with B x B accumulators per thread (bl == bout == B).
-template <typename R, int B>
+// Register Gram: GRAM 0 none, 1 out^H out (upper triangle, mirrored), 2 L^H out;
+// K inputs.
+template <typename R, int B, int K, int GRAM>
 __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
-    __shared__ cx<R> coef[3][kMaxW * kMaxW];
+    __shared__ cx<R> coef[3 * B * B];
     __shared__ zd red[4][B * B];
-    load_coefs<R>(a, coef);
+    load_coefs<R, B>(a, coef);
     __syncthreads();
-    zd G[B][B];
+    constexpr int NG = GRAM == 0 ? 1 : B * B;
+    zd G[NG];
 #pragma unroll
-    for (int p = 0; p < B; ++p)
-#pragma unroll
-        for (int q = 0; q < B; ++q) G[p][q] = mk<double>(0, 0);
+    for (int e = 0; e < NG; ++e) G[e] = mk<double>(0, 0);
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
     const int64_t r1 = min(a.nrows, r0 + a.rows_per_wg);
     cx<R> *out = (cx<R> *)a.out;
+    const int bl = GRAM == 2 ? a.bl : 0;
+#pragma unroll 1
     for (int64_t row = r0 + threadIdx.x; row < r1; row += 256) {
+        cx<R> l[B];
+        if (GRAM == 2) {
+            const cx<R> *Lp = (const cx<R> *)a.L + row;
+#pragma unroll
+            for (int p = 0; p < B; ++p) {
+                const cx<R> v = Lp[(int64_t)min(p, bl - 1) * a.csl];
+                l[p] = p < bl ? v : mk<R>(0, 0);
+            }
+        }
         cx<R> o[B];
-        combine_row<R, B>(a, coef, row, o);
+        combine_row<R, B, K>(a, coef, row, o);
         if (out)
 #pragma unroll
-            for (int q = 0; q < B; ++q) out[q * a.cso + row] = o[q];
-        if (a.gram) {
-            cx<R> l[B];
-            if (a.gram == 2) {
-                const cx<R> *Lp = (const cx<R> *)a.L + row;
+            for (int q = 0; q < B; ++q)
+                if (q < a.bout) out[q * a.cso + row] = o[q];
+        if (GRAM == 1) {
+            zd od[B];
 #pragma unroll
-                for (int p = 0; p < B; ++p) l[p] = Lp[p * a.csl];
-            } else {
-#pragma unroll
-                for (int p = 0; p < B; ++p) l[p] = o[p];
-            }
+            for (int q = 0; q < B; ++q) od[q] = cvt<double>(o[q]);
 #pragma unroll
             for (int p = 0; p < B; ++p)
 #pragma unroll
-                for (int q = 0; q < B; ++q) cmac_conj(G[p][q], cvt<double>(l[p]), cvt<double>(o[q]));
+                for (int q = p; q < B; ++q) cmac_conj(G[p * B + q], od[p], od[q]);
+        } else if (GRAM == 2) {
+            zd od[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) od[q] = cvt<double>(o[q]);
+#pragma unroll
+            for (int p = 0; p < B; ++p) {
+                const zd lp = cvt<double>(l[p]);
+#pragma unroll
+                for (int q = 0; q < B; ++q) cmac_conj(G[p * B + q], lp, od[q]);
+            }
         }
     }
-    if (!a.gram) return;
+    if (GRAM == 0) return;
     // wave reduction by butterflies, then across the four waves
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int p = 0; p < B; ++p)
 #pragma unroll
         for (int q = 0; q < B; ++q) {
-            zd v = G[p][q];
+            if (GRAM == 1 && q < p) continue;
+            zd v = G[p * B + q];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 v.x += __shfl_xor(v.x, off, 64);
@@ -103,16 +152,18 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
         }
     __syncthreads();
     if (threadIdx.x < B * B) {
-        const int p = threadIdx.x / B, q = threadIdx.x - p * B;
-        zd s = red[0][threadIdx.x];
-        s = s + red[1][threadIdx.x];
-        s = s + red[2][threadIdx.x];
-        s = s + red[3][threadIdx.x];
-        a.partials[(int64_t)blockIdx.x * 256 + p * 16 + q] = s;
+        int p = threadIdx.x / B, q = threadIdx.x - p * B;
+        const bool mirror = GRAM == 1 && q < p;
+        const int e = mirror ? q * B + p : p * B + q;
+        zd s = red[0][e];
+        s = s + red[1][e];
+        s = s + red[2][e];
+        s = s + red[3][e];
+        a.partials[(int64_t)blockIdx.x * 256 + p * 16 + q] = mirror ? conj(s) : s;
     }
 }
 
-// General widths: a tile of rows (one per thread) is staged in LDS
+// Wider blocks (B = 16): a tile of rows (one per thread) is staged in LDS
 // (column-major) and the Gram is accumulated by 2 x 2 blocks of pairs; with
 // 128 threads two halves of the tile are summed separately.
 template <typename R>
@@ -122,12 +173,13 @@ struct TileRows {
 
 template <typename R>
 __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
+    constexpr int B = kMaxW;
     constexpr int kTileRows = TileRows<R>::value;
-    __shared__ cx<R> coef[3][kMaxW * kMaxW];
-    __shared__ cx<R> so[kMaxW * kTileRows];
-    __shared__ cx<R> sl[kMaxW * kTileRows];
+    __shared__ cx<R> coef[3 * B * B];
+    __shared__ cx<R> so[B * kTileRows];
+    __shared__ cx<R> sl[B * kTileRows];
     __shared__ zd red[4][64];
-    load_coefs<R>(a, coef);
+    load_coefs<R, B>(a, coef);
     const int t = threadIdx.x;
     const int bl = (a.gram == 1) ? a.bout : a.bl;
     const int nbq = (a.bout + 1) / 2, nbp = (bl + 1) / 2;
@@ -142,34 +194,39 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
     cx<R> *out = (cx<R> *)a.out;
     __syncthreads();
     for (int64_t t0 = r0; t0 < r1; t0 += kTileRows) {
+        __asm__ volatile("" ::: "memory");
         const int64_t row = t0 + t;
         const bool ok = row < r1;
         if (ok) {
-            cx<R> o[kMaxW];
-            combine_row<R, kMaxW>(a, coef, row, o);
-            for (int q = 0; q < a.bout; ++q) {
-                if (out) out[q * a.cso + row] = o[q];
+            cx<R> o[B];
+            combine_row<R, B, 3>(a, coef, row, o);
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                if (out && q < a.bout) out[q * a.cso + row] = o[q];
                 so[q * kTileRows + t] = o[q];
             }
             if (a.gram == 2) {
                 const cx<R> *Lp = (const cx<R> *)a.L + row;
-                for (int p = 0; p < a.bl; ++p) sl[p * kTileRows + t] = Lp[p * a.csl];
+#pragma unroll
+                for (int p = 0; p < B; ++p) {
+                    const cx<R> v = Lp[(int64_t)min(p, a.bl - 1) * a.csl];
+                    sl[p * kTileRows + t] = p < a.bl ? v : mk<R>(0, 0);
+                }
             }
         } else {
-            for (int q = 0; q < a.bout; ++q) so[q * kTileRows + t] = mk<R>(0, 0);
+            for (int q = 0; q < B; ++q) so[q * kTileRows + t] = mk<R>(0, 0);
             if (a.gram == 2)
-                for (int p = 0; p < a.bl; ++p) sl[p * kTileRows + t] = mk<R>(0, 0);
+                for (int p = 0; p < B; ++p) sl[p * kTileRows + t] = mk<R>(0, 0);
         }
         __syncthreads();
         if (a.gram && blk < nblk) {
             const cx<R> *L = (a.gram == 1) ? so : sl;
             const int p0 = 2 * bp, q0 = 2 * bq;
-            const bool p1ok = p0 + 1 < bl, q1ok = q0 + 1 < a.bout;
             for (int r = half * 64; r < half * 64 + 64 && r < kTileRows; ++r) {
                 const zd l0 = cvt<double>(L[p0 * kTileRows + r]);
-                const zd l1 = p1ok ? cvt<double>(L[(p0 + 1) * kTileRows + r]) : mk<double>(0, 0);
+                const zd l1 = cvt<double>(L[(p0 + 1) * kTileRows + r]);
                 const zd y0 = cvt<double>(so[q0 * kTileRows + r]);
-                const zd y1 = q1ok ? cvt<double>(so[(q0 + 1) * kTileRows + r]) : mk<double>(0, 0);
+                const zd y1 = cvt<double>(so[(q0 + 1) * kTileRows + r]);
                 cmac_conj(G[0][0], l0, y0);
                 cmac_conj(G[0][1], l0, y1);
                 cmac_conj(G[1][0], l1, y0);
@@ -196,9 +253,48 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
     }
 }
 
+template <typename R, int B, int K>
+void ts_launch_reg(const TsArgs &a, int nwg, hipStream_t st) {
+    if (a.gram == 1)
+        hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 1>), dim3(nwg), dim3(256), 0, st, a);
+    else if (a.gram == 2)
+        hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 2>), dim3(nwg), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 0>), dim3(nwg), dim3(256), 0, st, a);
+}
+
+template <typename R, int B>
+void ts_launch_k(const TsArgs &a, int nwg, hipStream_t st) {
+    if (a.K == 1) ts_launch_reg<R, B, 1>(a, nwg, st);
+    else if (a.K == 2) ts_launch_reg<R, B, 2>(a, nwg, st);
+    else ts_launch_reg<R, B, 3>(a, nwg, st);
+}
+
+template <typename R>
+void ts_launch(const TsArgs &a, int w, int nwg, hipStream_t st) {
+    switch (w) {
+        case 1: ts_launch_k<R, 1>(a, nwg, st); break;
+        case 2: ts_launch_k<R, 2>(a, nwg, st); break;
+        case 3: ts_launch_k<R, 3>(a, nwg, st); break;
+        case 4: ts_launch_k<R, 4>(a, nwg, st); break;
+        case 5: ts_launch_k<R, 5>(a, nwg, st); break;
+        case 6: ts_launch_k<R, 6>(a, nwg, st); break;
+        default:
+            hipLaunchKernelGGL(ts_lds_kernel<R>, dim3(nwg), dim3(TileRows<R>::value), 0, st, a);
+            break;
+    }
+}
+
 hipError_t ts_run(bool fp64, TsArgs a, int max_wg, int *nwg_out, hipStream_t st) {
-    const int bl = (a.gram == 1) ? a.bout : a.bl;
-    const bool reg = a.gram != 2 ? (a.bout <= 6) : (a.bl == a.bout && a.bout <= 6);
+    if (a.K < 1 || a.K > 3 || a.bout < 1 || a.bout > kMaxW) return hipErrorInvalidValue;
+    for (int k = 0; k < a.K; ++k)
+        if (a.bx[k] < 0 || a.bx[k] > kMaxW) return hipErrorInvalidValue;
+    if (a.gram == 2 && (a.bl < 1 || a.bl > kMaxW)) return hipErrorInvalidValue;
+    // register kernel: every input, output and L width within w <= 6
+    int w = a.bout;
+    for (int k = 0; k < a.K; ++k) w = std::max(w, a.bx[k]);
+    if (a.gram == 2) w = std::max(w, a.bl);
+    const bool reg = w <= 6;
     const int tile = reg ? 256 : (fp64 ? TileRows<double>::value : TileRows<float>::value);
     int64_t tiles = (a.nrows + tile - 1) / tile;
     int nwg = (int)(tiles < max_wg ? tiles : max_wg);
@@ -207,24 +303,8 @@ hipError_t ts_run(bool fp64, TsArgs a, int max_wg, int *nwg_out, hipStream_t st)
     a.rows_per_wg = per * tile;
     nwg = (int)((a.nrows + a.rows_per_wg - 1) / a.rows_per_wg);
     if (nwg < 1) nwg = 1;
-    (void)bl;
-    if (reg) {
-#define DSBCG_TS(R, B) hipLaunchKernelGGL((ts_reg_kernel<R, B>), dim3(nwg), dim3(256), 0, st, a)
-        switch (a.bout) {
-            case 1: if (fp64) DSBCG_TS(double, 1); else DSBCG_TS(float, 1); break;
-            case 2: if (fp64) DSBCG_TS(double, 2); else DSBCG_TS(float, 2); break;
-            case 3: if (fp64) DSBCG_TS(double, 3); else DSBCG_TS(float, 3); break;
-            case 4: if (fp64) DSBCG_TS(double, 4); else DSBCG_TS(float, 4); break;
-            case 5: if (fp64) DSBCG_TS(double, 5); else DSBCG_TS(float, 5); break;
-            default: if (fp64) DSBCG_TS(double, 6); else DSBCG_TS(float, 6); break;
-        }
-#undef DSBCG_TS
-    } else {
-        if (fp64)
-            hipLaunchKernelGGL(ts_lds_kernel<double>, dim3(nwg), dim3(TileRows<double>::value), 0, st, a);
-        else
-            hipLaunchKernelGGL(ts_lds_kernel<float>, dim3(nwg), dim3(TileRows<float>::value), 0, st, a);
-    }
+    if (fp64) ts_launch<double>(a, reg ? w : 16, nwg, st);
+    else ts_launch<float>(a, reg ? w : 16, nwg, st);
     if (nwg_out) *nwg_out = nwg;
     return hipGetLastError();
 }
@@ -315,119 +395,169 @@ hipError_t copy_field(int64_t V, int cols, FieldDesc in, FieldDesc out, bool acc
 }
 
 // ---------------------------------------------------------------------------
-// Window update of the per-shift iterates: a workgroup owns 64 rows; the rows
-// of the K window blocks are staged in LDS once and each of the four waves
-// applies them to every fourth shift, so X_j and P_j rows are read and
-// written once per window instead of once per block step.
+// Window update on the matrix cores.  For shift j the window contraction is
+//   [out_X | out_P] (rows x (m + bend)) = [P_{j,i0} | V_window] (rows x K_in) * C_j
+// in complex arithmetic.  It runs as a real product with 16x16x4 MFMAs in the
+// transposed orientation: the A operand is the coefficient table (output
+// real columns x 4 input reals = one pair of complex inputs), the B operand
+// is the data (4 input reals x 16 rows).  The table orders the output reals
+// so that lane group g = lane / 16 ends with (re, im) of the complex
+// outputs 8 mt + 2 g and 8 mt + 2 g + 1 of one data row in its four
+// accumulators; each lane group then stores 16 consecutive rows.
+//
+// A workgroup owns 16 * TILES consecutive rows and has one wave per shift of
+// the window; the window columns are staged chunk by chunk in LDS and read
+// by every wave, the P_{j,i0} columns are read by their own wave only.
 // ---------------------------------------------------------------------------
 template <typename R>
-struct WinCols {
-    static constexpr int value = sizeof(R) == 8 ? kWinCols64 : kWinCols32;
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mac(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mac(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
 };
 
-template <typename R, int BC, int MC>
-__global__ __launch_bounds__(256) void window_kernel(WinArgs a) {
-    constexpr int kRows = 64;
-    __shared__ cx<R> vt[WinCols<R>::value * kRows];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * kRows;
-    const int64_t row = r0 + lane;
-    const bool ok = row < a.nrows;
+template <typename R>
+struct WinChunk {
+    static constexpr int value = sizeof(R) == 8 ? 32 : 64;  // window columns per LDS chunk
+};
+
+template <typename R, int NMT, int TILES>
+__global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
+    constexpr int CH = WinChunk<R>::value;
+    constexpr int RW = 16 * TILES;  // rows per workgroup
+    typedef typename Mfma<R>::v4 v4;
+    __shared__ cx<R> vt[CH * RW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int64_t n = a.nrows;
-    // stage the window rows: column c of the concatenated window at vt[c * 64 + lane]
-    {
-        int c0 = 0;
-        for (int u = 0; u < a.K; ++u) {
-            const cx<R> *Vu = (const cx<R> *)a.Vw[u];
-            for (int q = wave; q < a.wb[u]; q += 4)
-                vt[(c0 + q) * kRows + lane] = ok ? Vu[(int64_t)q * n + row] : mk<R>(0, 0);
-            c0 += a.wb[u];
+    const int64_t r0 = (int64_t)blockIdx.x * RW;
+    const bool active = wave < a.nshift;
+    const int j = active ? a.shifts[wave] : 0;
+    const R *tab = (const R *)a.table + (size_t)wave * a.npairs * NMT * 64 + lane;
+    const int rl = lane & 15;           // row within a 16-row tile
+    const int part = (lane >> 4) & 1;   // real (0) or imaginary (1) part of the input
+    const int sel = lane >> 5;          // input column of the pair
+
+    v4 acc[TILES][NMT];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) acc[t][mt] = v4{0, 0, 0, 0};
+
+    // inputs from P_{j,i0}, per wave
+    if (active && a.bp0 > 0) {
+        const R *P = (const R *)a.Pold + (size_t)2 * j * a.pstride;
+        for (int pp = 0; pp < a.pairs_p; ++pp) {
+            const int p = 2 * pp + sel;
+            R d[TILES];
+#pragma unroll
+            for (int t = 0; t < TILES; ++t) {
+                const int64_t row = r0 + t * 16 + rl;
+                d[t] = (p < a.bp0 && row < n) ? P[2 * ((int64_t)p * n + row) + part] : (R)0;
+            }
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) {
+                const R cf = tab[(pp * NMT + mt) * 64];
+#pragma unroll
+                for (int t = 0; t < TILES; ++t) acc[t][mt] = Mfma<R>::mac(cf, d[t], acc[t][mt]);
+            }
         }
     }
-    __syncthreads();
-    if (!ok) return;
-    const cx<R> *G = (const cx<R> *)a.G, *Fp = (const cx<R> *)a.Fp;
-    const cx<R> *H = (const cx<R> *)a.H, *F = (const cx<R> *)a.F;
-    for (int js = wave; js < a.nshift; js += 4) {
-        const int j = a.shifts[js];
-        const uint32_t xm = a.xmask[j];
-        const int cnt = a.count[j];
-        const bool wp = a.pmask[j] != 0;
-        cx<R> dx[MC], pn[BC];
+    // window columns, staged in LDS (columns past the end and rows past n are zero)
+    for (int c0 = 0; c0 < a.ncolv; c0 += CH) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < CH * RW; e += blockDim.x) {
+            const int cc = e / RW, r = e - cc * RW;
+            const int c = c0 + cc;
+            const int64_t row = r0 + r;
+            cx<R> v = mk<R>(0, 0);
+            if (c < a.ncolv && row < n) v = ((const cx<R> *)a.colptr[c])[row];
+            vt[e] = v;
+        }
+        __syncthreads();
+        if (!active) continue;
+        const int npp = (min(CH, a.ncolv - c0) + 1) >> 1;
+        const R *tc = tab + (size_t)(a.pairs_p + (c0 >> 1)) * NMT * 64;
+        for (int pp = 0; pp < npp; ++pp) {
+            const R *src = (const R *)&vt[(2 * pp + sel) * RW + rl] + part;
+            R d[TILES];
 #pragma unroll
-        for (int q = 0; q < MC; ++q) dx[q] = mk<R>(0, 0);
+            for (int t = 0; t < TILES; ++t) d[t] = src[2 * t * 16];
 #pragma unroll
-        for (int q = 0; q < BC; ++q) pn[q] = mk<R>(0, 0);
-        if (a.bp0 > 0) {
-            const cx<R> *po = (const cx<R> *)a.Pold + j * a.pstride + row;
-            const cx<R> *g = G + j * 256, *fp = Fp + j * 256;
-            for (int p = 0; p < a.bp0; ++p) {
-                const cx<R> v = po[(int64_t)p * n];
+            for (int mt = 0; mt < NMT; ++mt) {
+                const R cf = tc[(pp * NMT + mt) * 64];
 #pragma unroll
-                for (int q = 0; q < MC; ++q)
-                    if (q < a.m) cmac(dx[q], v, fp[p * 16 + q]);
-                if (wp)
-#pragma unroll
-                    for (int q = 0; q < BC; ++q)
-                        if (q < a.bend) cmac(pn[q], v, g[p * 16 + q]);
+                for (int t = 0; t < TILES; ++t) acc[t][mt] = Mfma<R>::mac(cf, d[t], acc[t][mt]);
             }
         }
-        int c0 = 0;
-        for (int u = 0; u < cnt; ++u) {
-            const cx<R> *hu = H + ((int64_t)j * kWinMax + u) * 256;
-            const cx<R> *fu = F + ((int64_t)j * kWinMax + u) * 256;
-            for (int p = 0; p < a.wb[u]; ++p) {
-                const cx<R> v = vt[(c0 + p) * kRows + lane];
+    }
+    if (!active) return;
+    // lane holds rows r0 + 16 t + rl, complex outputs q = 8 mt + 2 g and q + 1
+    const int g = lane >> 4;
+    const uint32_t xm = a.xmask[j];
+    const bool wp = a.pmask[j] != 0;
+    zd *X = a.X + (size_t)j * a.xstride;
+    cx<R> *Pn = (cx<R> *)a.Pnew + (size_t)j * a.pstride;
 #pragma unroll
-                for (int q = 0; q < MC; ++q)
-                    if (q < a.m) cmac(dx[q], v, fu[p * 16 + q]);
-                if (wp)
+    for (int t = 0; t < TILES; ++t) {
+        const int64_t row = r0 + t * 16 + rl;
+        if (row >= n) continue;
 #pragma unroll
-                    for (int q = 0; q < BC; ++q)
-                        if (q < a.bend) cmac(pn[q], v, hu[p * 16 + q]);
+        for (int mt = 0; mt < NMT; ++mt) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = mt * 8 + 2 * g + h;
+                const R re = acc[t][mt][2 * h], im = acc[t][mt][2 * h + 1];
+                if (q < a.m) {
+                    if ((xm >> q) & 1u) {
+                        zd *x = X + (int64_t)q * n + row;
+                        *x = mk<double>(x->x + (double)re, x->y + (double)im);
+                    }
+                } else if (wp && q - a.m < a.bend) {
+                    Pn[(int64_t)(q - a.m) * n + row] = mk<R>(re, im);
+                }
             }
-            c0 += a.wb[u];
-        }
-        cx<R> *xr = (cx<R> *)a.X + j * a.xstride + row;
-#pragma unroll
-        for (int q = 0; q < MC; ++q)
-            if (q < a.m && ((xm >> q) & 1u)) xr[(int64_t)q * n] = xr[(int64_t)q * n] + dx[q];
-        if (wp) {
-            cx<R> *pw = (cx<R> *)a.Pnew + j * a.pstride + row;
-#pragma unroll
-            for (int q = 0; q < BC; ++q)
-                if (q < a.bend) pw[(int64_t)q * n] = pn[q];
         }
     }
 }
 
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
-    if (a.K < 1 || a.K > kWinMax || a.m < 1 || a.m > 16 || a.bend > 16 || a.bp0 > 16)
+    if (a.nshift < 1 || a.nshift > 16 || a.m < 1 || a.m > 16 || a.bend < 0 || a.bend > 16 ||
+        a.bp0 < 0 || a.bp0 > 16 || a.ncolv < 0 || a.nmt < 1 || a.nmt > 4 ||
+        a.nmt * 8 < a.m + a.bend || a.pairs_p != (a.bp0 + 1) / 2 ||
+        a.npairs != a.pairs_p + (a.ncolv + 1) / 2)
         return hipErrorInvalidValue;
-    int cols = 0;
-    for (int u = 0; u < a.K; ++u) cols += a.wb[u];
-    if (cols > (fp64 ? kWinCols64 : kWinCols32)) return hipErrorInvalidValue;
     if (a.nrows <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.nrows + 63) / 64));
-    const int bc = a.bend <= 4 ? 4 : a.bend <= 8 ? 8 : 16;
-    const int mc = a.m <= 4 ? 4 : a.m <= 8 ? 8 : 16;
-#define DSBCG_WIN(R, B, M) hipLaunchKernelGGL((window_kernel<R, B, M>), grid, dim3(256), 0, st, a)
-#define DSBCG_WIN_M(R, B)                   \
-    do {                                    \
-        if (mc == 4) DSBCG_WIN(R, B, 4);    \
-        else if (mc == 8) DSBCG_WIN(R, B, 8); \
-        else DSBCG_WIN(R, B, 16);           \
+    const dim3 block(64 * a.nshift);
+    // four 16-row tiles per wave while the accumulators fit, else two
+    const bool four = fp64 ? a.nmt <= 2 : a.nmt <= 4;
+    const int rw = four ? 64 : 32;
+    const dim3 grid((unsigned)((a.nrows + rw - 1) / rw));
+#define DSBCG_WIN(R, M, T) hipLaunchKernelGGL((window_kernel<R, M, T>), grid, block, 0, st, a)
+#define DSBCG_WIN_R(R)                                       \
+    do {                                                     \
+        if (four) {                                          \
+            if (a.nmt == 1) DSBCG_WIN(R, 1, 4);              \
+            else if (a.nmt == 2) DSBCG_WIN(R, 2, 4);         \
+            else if (a.nmt == 3) DSBCG_WIN(R, 3, 4);         \
+            else DSBCG_WIN(R, 4, 4);                         \
+        } else {                                             \
+            if (a.nmt == 3) DSBCG_WIN(R, 3, 2);              \
+            else DSBCG_WIN(R, 4, 2);                         \
+        }                                                    \
     } while (0)
-#define DSBCG_WIN_B(R)                      \
-    do {                                    \
-        if (bc == 4) DSBCG_WIN_M(R, 4);     \
-        else if (bc == 8) DSBCG_WIN_M(R, 8); \
-        else DSBCG_WIN_M(R, 16);            \
-    } while (0)
-    if (fp64) DSBCG_WIN_B(double);
-    else DSBCG_WIN_B(float);
-#undef DSBCG_WIN_B
-#undef DSBCG_WIN_M
+    if (fp64) DSBCG_WIN_R(double);
+    else DSBCG_WIN_R(float);
+#undef DSBCG_WIN_R
 #undef DSBCG_WIN
     return hipGetLastError();
 }

@@ -52,35 +52,32 @@ struct FieldDesc {
 hipError_t copy_field(int64_t V, int cols, FieldDesc in, FieldDesc out, bool accumulate,
                       double scale, hipStream_t st);
 
-// Window update of the per-shift iterates over block steps i0+1 .. i0+K:
+// Window update of the per-shift iterates over the block steps of a window:
 //   X_j += P_{j,i0} Fp_j + sum_u V_u F_{j,u}          (columns in xmask[j])
-//   P_{j,i0+K} = P_{j,i0} G_j + sum_u V_u H_{j,u}      (shifts with pmask set)
-// V_u: the K Lanczos blocks of the window (widths wb[u]), shared by all
-// shifts and staged once per row tile in LDS.  Coefficients are [s][16*16]
-// (G, Fp) and [s][kWin][16*16] (H, F) in the data precision.
-constexpr int kWinMax = 16;
+//   P_{j,end} = P_{j,i0} G_j + sum_u V_u H_{j,u}      (shifts with pmask set)
+// as one matrix-core contraction per shift: the inputs [P_{j,i0} | V_window]
+// (complex columns taken in pairs) times the coefficient table built by
+// small_window_table.  The window columns are shared by all shifts and are
+// staged chunk by chunk in LDS; X is FP64 in both precisions.
 struct WinArgs {
     int64_t nrows;
-    int K;
-    int wb[kWinMax];
-    const void *Vw[kWinMax];
+    int ncolv;                  // window columns (sum of the block widths)
+    const void *const *colptr;  // device array [ncolv]: first element of each window column
     int bp0;                    // width of P_{j,i0} (0: no P term)
     const void *Pold;
     void *Pnew;
-    int bend;                   // width of P_{j,i0+K}
-    int64_t pstride;
+    int bend;                   // width of P_{j,end}
+    int64_t pstride;            // elements between shifts in the P buffers
     int m;
-    void *X;
+    zd *X;                      // [s][m][nrows] FP64
     int64_t xstride;
-    const void *G, *Fp, *H, *F; // coefficient arrays (data precision)
-    const int32_t *shifts;
-    int nshift;
-    const uint32_t *xmask;      // [s] columns to update
-    const int32_t *count;       // [s] window slots of each shift
-    const int32_t *pmask;       // [s] nonzero: write P_{j,i0+K}
+    const void *table;          // [nshift][npairs][nmt][64] in the data precision
+    int npairs, pairs_p, nmt;
+    const int32_t *shifts;      // device [nshift]: shift of each window slot
+    int nshift;                 // <= 16
+    const uint32_t *xmask;      // [s] columns of X_j to update
+    const int32_t *pmask;       // [s] nonzero: write P_{j,end}
 };
-// Largest sum of window widths one launch supports (LDS budget).
-constexpr int kWinCols64 = 48, kWinCols32 = 96;
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st);
 
 // Checks a field for NaN/Inf: sets *flag (device int) to 1 if any is found.

@@ -166,8 +166,7 @@ hipError_t small_shift_coeffs(SmallState *st, StepReport *rep, const zd *alpha_r
 }
 
 // ---------------------------------------------------------------------------
-// Window recurrences (one 64-lane workgroup per active shift), applied after
-// N_{j,i} and M_{j,i} of step i are known.  With Mh the columns of M_{j,i}
+// Window recurrences, applied after N_{j,i} and M_{j,i} of step i are known.  With Mh the columns of M_{j,i}
 // still being updated:
 //   first step of a window:  Wg = -N, Wfp = Wg Mh, Wh_0 = I, Wf_0 = Mh
 //   later steps:             Wg <- -Wg N, Wfp += Wg Mh,
@@ -205,88 +204,176 @@ __device__ inline void mat_mul_acc(zd *F, const zd *A, const zd *Mh, int rows, i
     __syncthreads();
 }
 
-__global__ __launch_bounds__(64) void window_update_kernel(SmallState *st, StepReport *rep, WindowStep w,
+size_t wincoef_bytes() {
+    return sizeof(zd) * (2 * kS * 256 + 2 * (size_t)kS * kWinMax * 256) + sizeof(uint32_t) * kS +
+           sizeof(int32_t) * kS;
+}
+
+WinCoef wincoef_at(void *base) {
+    WinCoef w;
+    zd *p = (zd *)base;
+    w.Wg = p;
+    w.Wfp = p + kS * 256;
+    w.Wh = p + 2 * kS * 256;
+    w.Wf = w.Wh + (size_t)kS * kWinMax * 256;
+    w.Wmask = (uint32_t *)(w.Wf + (size_t)kS * kWinMax * 256);
+    w.Wcount = (int32_t *)(w.Wmask + kS);
+    return w;
+}
+
+// One block per (active shift, window slot); the slots are independent once
+// N_{j,i} and M_{j,i} are known.  blockIdx.y = u < t: Wh_u <- -Wh_u N,
+// Wf_u += Wh_u Mh; u == t: Wh_t = I, Wf_t = Mh; u == t + 1: the P_{j,i0}
+// part (Wg, Wfp).
+__global__ __launch_bounds__(64) void window_update_kernel(const SmallState *st, const StepReport *rep,
+                                                           WinCoef wc, WindowStep w,
                                                            const int32_t *__restrict__ list) {
     __shared__ zd Ns[256], Mh[256], A[256], tmp[256];
     const int j = list[blockIdx.x];
+    const int u = blockIdx.y;
     const int t = threadIdx.x;
     const uint32_t mask = rep->colmask[j];
+    if (u == w.t + 1 && w.bp0 == 0) return;
     for (int e = t; e < 256; e += 64) {
         const int r = e / 16, c = e - r * 16;
         Ns[e] = st->N[j][e];
         Mh[e] = (r < w.b && c < w.m && ((mask >> c) & 1u)) ? st->M[j][e] : mk<double>(0, 0);
     }
     __syncthreads();
-    if (w.bp0 > 0) {
-        // Wg, Wfp
-        for (int e = t; e < 256; e += 64) A[e] = st->Wg[j][e];
-        __syncthreads();
+    if (u == w.t + 1) {
+        zd *G = wc.Wg + j * 256, *Fp = wc.Wfp + j * 256;
         if (w.t == 0) {
-            // Wg_{i0} = I (bp0 x bp0), so Wg = -N
+            // Wg is the identity (b_{i0} x b_{i0}) at the window start, so Wg = -N
             for (int e = t; e < 256; e += 64) {
                 const int r = e / 16, c = e - r * 16;
                 A[e] = (r < w.bp0 && c < w.b) ? -Ns[e] : mk<double>(0, 0);
             }
             __syncthreads();
         } else {
+            for (int e = t; e < 256; e += 64) A[e] = G[e];
+            __syncthreads();
             mat_neg_mul(A, Ns, w.bp0, w.bp, w.b, tmp);
         }
-        for (int e = t; e < 256; e += 64) st->Wg[j][e] = A[e];
-        for (int e = t; e < 256; e += 64) tmp[e] = (w.t == 0) ? mk<double>(0, 0) : st->Wfp[j][e];
+        for (int e = t; e < 256; e += 64) {
+            G[e] = A[e];
+            tmp[e] = (w.t == 0) ? mk<double>(0, 0) : Fp[e];
+        }
         __syncthreads();
         mat_mul_acc(tmp, A, Mh, w.bp0, w.b, w.m, false);
-        for (int e = t; e < 256; e += 64) st->Wfp[j][e] = tmp[e];
-        __syncthreads();
+        for (int e = t; e < 256; e += 64) Fp[e] = tmp[e];
+        return;
     }
-    for (int u = 0; u < w.t; ++u) {
-        for (int e = t; e < 256; e += 64) A[e] = st->Wh[j][u][e];
-        __syncthreads();
-        mat_neg_mul(A, Ns, w.wb[u], w.bp, w.b, tmp);
-        for (int e = t; e < 256; e += 64) st->Wh[j][u][e] = A[e];
-        for (int e = t; e < 256; e += 64) tmp[e] = st->Wf[j][u][e];
-        __syncthreads();
-        mat_mul_acc(tmp, A, Mh, w.wb[u], w.b, w.m, false);
-        for (int e = t; e < 256; e += 64) st->Wf[j][u][e] = tmp[e];
-        __syncthreads();
+    zd *H = wc.Wh + ((size_t)j * kWinMax + u) * 256, *F = wc.Wf + ((size_t)j * kWinMax + u) * 256;
+    if (u == w.t) {
+        for (int e = t; e < 256; e += 64) {
+            const int r = e / 16, c = e - r * 16;
+            H[e] = (r == c && r < w.b) ? mk<double>(1, 0) : mk<double>(0, 0);
+            F[e] = Mh[e];
+        }
+        if (t == 0) {
+            wc.Wmask[j] = (w.t == 0 ? 0u : wc.Wmask[j]) | mask;
+            wc.Wcount[j] = w.t + 1;
+        }
+        return;
     }
+    // rows of slot u beyond its width are zero, so all kS rows can be carried
+    for (int e = t; e < 256; e += 64) A[e] = H[e];
+    __syncthreads();
+    mat_neg_mul(A, Ns, kS, w.bp, w.b, tmp);
     for (int e = t; e < 256; e += 64) {
-        const int r = e / 16, c = e - r * 16;
-        st->Wh[j][w.t][e] = (r == c && r < w.b) ? mk<double>(1, 0) : mk<double>(0, 0);
-        st->Wf[j][w.t][e] = Mh[e];
-    }
-    if (t == 0) {
-        st->Wmask[j] = (w.t == 0 ? 0u : st->Wmask[j]) | mask;
-        st->Wcount[j] = w.t + 1;
+        H[e] = A[e];
+        tmp[e] = F[e];
     }
     __syncthreads();
-    // FP32 copies for the FP32 window kernel
-    for (int e = t; e < 256; e += 64) {
-        st->Wg32[j][e] = cvt<float>(st->Wg[j][e]);
-        st->Wfp32[j][e] = cvt<float>(st->Wfp[j][e]);
-    }
-    for (int u = 0; u <= w.t; ++u)
-        for (int e = t; e < 256; e += 64) {
-            st->Wh32[j][u][e] = cvt<float>(st->Wh[j][u][e]);
-            st->Wf32[j][u][e] = cvt<float>(st->Wf[j][u][e]);
-        }
+    mat_mul_acc(tmp, A, Mh, kS, w.b, w.m, false);
+    for (int e = t; e < 256; e += 64) F[e] = tmp[e];
 }
 
-hipError_t small_window_update(SmallState *st, StepReport *rep, WindowStep ws,
+hipError_t small_window_update(const SmallState *st, const StepReport *rep, WinCoef wc, WindowStep ws,
                                const int32_t *shift_list, int nact, hipStream_t stream) {
     if (nact <= 0) return hipSuccess;
-    hipLaunchKernelGGL(window_update_kernel, dim3(nact), dim3(64), 0, stream, st, rep, ws, shift_list);
+    if (ws.t < 0 || ws.t >= kWinMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(window_update_kernel, dim3(nact, ws.t + 2), dim3(64), 0, stream, st, rep, wc, ws,
+                       shift_list);
     return hipGetLastError();
 }
 
-__global__ void window_reset_kernel(SmallState *st, int s) {
-    for (int j = threadIdx.x; j < s; j += blockDim.x) {
-        st->Wmask[j] = 0u;
-        st->Wcount[j] = 0;
+__global__ void window_reset_kernel(WinCoef wc) {
+    for (int j = threadIdx.x; j < kS; j += blockDim.x) {
+        wc.Wmask[j] = 0u;
+        wc.Wcount[j] = 0;
     }
 }
 
-hipError_t small_window_reset(SmallState *st, int s, hipStream_t stream) {
-    hipLaunchKernelGGL(window_reset_kernel, dim3(1), dim3(64), 0, stream, st, s);
+hipError_t small_window_reset(WinCoef wc, hipStream_t stream) {
+    hipLaunchKernelGGL(window_reset_kernel, dim3(1), dim3(64), 0, stream, wc);
+    return hipGetLastError();
+}
+
+// One block of 64 lanes per (window shift, input pair, output tile): the
+// lanes hold the matrix-core A operand, entry (output row i, input real
+// index k) at lane i + 16 k.  With c the complex coefficient of input p
+// in output q (out_q += in_p c):
+//   Re out += Re in Re c - Im in Im c,   Im out += Re in Im c + Im in Re c.
+template <typename R>
+__global__ __launch_bounds__(64) void window_table_kernel(WinCoef wc, WindowTable wt,
+                                                          const int32_t *__restrict__ shifts,
+                                                          const int32_t *__restrict__ pmask, R *table) {
+    const int js = blockIdx.x, pair = blockIdx.y, mt = blockIdx.z;
+    const int lane = threadIdx.x;
+    const int j = shifts[js];
+    const int i = lane & 15, k = lane >> 4;
+    // Output real column i of the tile: complex output q and its part po,
+    // chosen so that each lane of the product ends with (re, im) of two
+    // consecutive outputs in its four accumulators.  The f32 instruction
+    // leaves rows 4 g + r of the result in lane group g, register r; the
+    // f64 instruction leaves rows g + 4 r there.
+    int ql, po;
+    if (sizeof(R) == 8) {
+        ql = 2 * (i & 3) + ((i >> 2) >> 1);
+        po = (i >> 2) & 1;
+    } else {
+        ql = i >> 1;
+        po = i & 1;
+    }
+    const int q = mt * 8 + ql;
+    const int pin = k & 1;               // real/imaginary part of the input
+    zd c = mk<double>(0, 0);
+    const bool xout = q < wt.m;
+    const bool pout = !xout && q - wt.m < wt.bend && pmask[j] != 0;
+    if (xout || pout) {
+        const int qq = xout ? q : q - wt.m;
+        if (pair < wt.pairs_p) {
+            const int p = 2 * pair + (k >> 1);
+            if (p < wt.bp0) c = (xout ? wc.Wfp : wc.Wg)[j * 256 + p * 16 + qq];
+        } else {
+            const int col = 2 * (pair - wt.pairs_p) + (k >> 1);
+            if (col < wt.ncolv) {
+                // window slot u of this column and its first column c0
+                int u = 0, c0 = 0;
+                while (u < wt.K - 1 && col >= c0 + wt.wb[u]) c0 += wt.wb[u++];
+                if (u < wc.Wcount[j]) {
+                    const zd *src = (xout ? wc.Wf : wc.Wh) + ((size_t)j * kWinMax + u) * 256;
+                    c = src[(col - c0) * 16 + qq];
+                }
+            }
+        }
+    }
+    const double v = (po == 0) ? (pin == 0 ? c.x : -c.y) : (pin == 0 ? c.y : c.x);
+    table[(((size_t)js * wt.npairs + pair) * wt.nmt + mt) * 64 + lane] = (R)v;
+}
+
+hipError_t small_window_table(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
+                              const int32_t *pmask, bool fp64, void *table, hipStream_t stream) {
+    if (wt.nshift <= 0 || wt.npairs <= 0) return hipSuccess;
+    if (wt.K < 1 || wt.K > kWinMax || wt.nmt < 1 || wt.nmt > 4) return hipErrorInvalidValue;
+    const dim3 grid(wt.nshift, wt.npairs, wt.nmt);
+    if (fp64)
+        hipLaunchKernelGGL(window_table_kernel<double>, grid, dim3(64), 0, stream, wc, wt, shifts, pmask,
+                           (double *)table);
+    else
+        hipLaunchKernelGGL(window_table_kernel<float>, grid, dim3(64), 0, stream, wc, wt, shifts, pmask,
+                           (float *)table);
     return hipGetLastError();
 }
 

@@ -8,7 +8,6 @@ namespace dsbcg {
 
 constexpr int kS = 16;       // largest shift count / block width handled by the small kernels
 constexpr int kStack = 256;  // largest number of stacked right-hand-side columns
-constexpr int kWin = 16;     // largest number of block steps in one update window
 
 // Matrices are 16 x 16 row-major (leading dimension 16); only the leading
 // rows x cols part is meaningful.
@@ -26,19 +25,6 @@ struct SmallState {
     zd Z[kS][256];       // per shift: Z_{j,i} (b x m)
     zd N[kS][256];       // per shift: N_{j,i} (bp x b)
     zd M[kS][256];       // per shift: M_{j,i} (b x m)
-    // Window of block steps i0+1 .. i0+t (per shift): within it
-    //   P_{j,i} = P_{j,i0} Wg_j + sum_u V_{i0+1+u} Wh_{j,u}
-    //   X_j increment = P_{j,i0} Wfp_j + sum_u V_{i0+1+u} Wf_{j,u}
-    zd Wg[kS][256];             // b_{i0} x b_i
-    zd Wfp[kS][256];            // b_{i0} x m
-    zd Wh[kS][kWin][256];       // b_{i0+1+u} x b_i
-    zd Wf[kS][kWin][256];       // b_{i0+1+u} x m
-    zf Wg32[kS][256];
-    zf Wfp32[kS][256];
-    zf Wh32[kS][kWin][256];
-    zf Wf32[kS][kWin][256];
-    uint32_t Wmask[kS];         // columns of X_j touched in the window
-    int32_t Wcount[kS];         // window slots holding coefficients of shift j
     double sigma[kS];
     double bnorm[kStack];       // norms of the stacked right-hand-side columns
     int32_t colmap[kS][kS];     // stacked column of right-hand side l of shift j
@@ -67,16 +53,52 @@ hipError_t small_prep_alpha(SmallState *st, const zd *alpha_raw, hipStream_t str
 hipError_t small_shift_coeffs(SmallState *st, StepReport *rep, const zd *alpha_raw, int first,
                               const int32_t *shift_list, int nact, hipStream_t stream);
 
-// Window bookkeeping for step i (after small_shift_coeffs): slot t = i - i0 - 1
-// of the window, widths wb[u] of the window blocks, b_{i0} (0 when the window
-// starts at step 1, i.e. there is no stored P), current and previous widths.
+// Window of block steps i0+1 .. i0+t.  Within it, per shift j,
+//   P_{j,i} = P_{j,i0} Wg_j + sum_u V_{i0+1+u} Wh_{j,u}
+//   X_j increment = P_{j,i0} Wfp_j + sum_u V_{i0+1+u} Wf_{j,u}
+// (16 x 16 row-major FP64 blocks; rows of Wh_{j,u}, Wf_{j,u} beyond the width
+// of V_{i0+1+u} are zero).  Device arrays, allocated by the caller.
+constexpr int kWinMax = 128;  // largest window length in block steps
+struct WinCoef {
+    zd *Wg;          // [kS][256]   b_{i0} x b_i
+    zd *Wfp;         // [kS][256]   b_{i0} x m
+    zd *Wh;          // [kS][kWinMax][256]
+    zd *Wf;          // [kS][kWinMax][256]
+    uint32_t *Wmask; // [kS] columns of X_j updated in the window
+    int32_t *Wcount; // [kS] window slots holding coefficients of shift j
+};
+size_t wincoef_bytes();
+WinCoef wincoef_at(void *base);
+
+// Window bookkeeping for step i (after small_shift_coeffs): slot t = i - i0 - 1,
+// b_{i0} (0 when the window starts at step 1, i.e. there is no stored P),
+// current and previous widths, m.
 struct WindowStep {
     int t, bp0, b, bp, m;
-    int wb[kWin];
 };
-hipError_t small_window_update(SmallState *st, StepReport *rep, WindowStep ws,
+hipError_t small_window_update(const SmallState *st, const StepReport *rep, WinCoef wc, WindowStep ws,
                                const int32_t *shift_list, int nact, hipStream_t stream);
-hipError_t small_window_reset(SmallState *st, int s, hipStream_t stream);
+hipError_t small_window_reset(WinCoef wc, hipStream_t stream);
+
+// Coefficient table of the window contraction in the data precision, in the
+// lane order of the 16x16x4 matrix-core product (see window_apply):
+// table[js][pair][mt][lane], lane = i + 16 k, for output row i of tile mt
+// (a real or imaginary part of complex output 8 mt + 0..7: X column if
+// < m, else P column - m) and input real index k of the pair (real or
+// imaginary part of complex input 2 pair + k / 2: the P_{j,i0} columns
+// first, then the window columns).
+struct WindowTable {
+    int nshift;     // shifts of the window (order of `shifts`)
+    int bp0, m, bend;
+    int pairs_p;    // ceil(bp0 / 2)
+    int ncolv;      // window columns (sum of the widths)
+    int npairs;     // pairs_p + ceil(ncolv / 2)
+    int nmt;        // 16-column output tiles: ceil(2 (m + bend) / 16)
+    int K;          // window slots
+    int wb[kWinMax];// widths of the window blocks
+};
+hipError_t small_window_table(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
+                              const int32_t *pmask, bool fp64, void *table, hipStream_t stream);
 
 // First pass of the deflated CholQR of W: Cholesky of G = W^H W with column
 // dropping (remainder <= tau_W * ||T||_est); also updates ||T||_est from

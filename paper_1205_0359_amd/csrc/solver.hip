@@ -98,7 +98,8 @@ struct dsbcg_ctx {
     // workspace
     DevBuf Ul64, Ul32;                                   // structure-of-arrays links
     DevBuf V0, T, W, P[2], X;                            // FP64 iteration (V0: V_1)
-    DevBuf T32, W32, P32[2], Xlo;                        // FP32 iteration
+    DevBuf T32, W32, P32[2];                             // FP32 iteration
+    DevBuf wcoef, wtable, colptr;                        // window coefficients, MFMA table, columns
     DevBuf Bint, Q, wbuf;                                // deflated QR of B
     DevBuf R0, R1, R2, R3, Rres, Xref;                   // true residuals, refinement
     DevBuf Xin, Yout;                                    // dsbcg_apply_* conversions
@@ -110,7 +111,7 @@ struct dsbcg_ctx {
 
     ~dsbcg_ctx() {
         DevBuf *all[] = {&Ul64, &Ul32, &V0,  &T,   &W,    &P[0], &P[1], &X,
-                         &T32, &W32, &P32[0], &P32[1], &Xlo,
+                         &T32, &W32, &P32[0], &P32[1], &wcoef, &wtable, &colptr,
                          &Bint, &Q,    &wbuf, &R0,   &R1,   &R2,  &R3,   &Rres, &Xref, &Xin,
                          &Yout, &partials, &red, &list, &wlist, &st, &rep};
         for (DevBuf *b : all)
@@ -545,41 +546,64 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
 
     // widths never exceed m1 after the initial deflation
     const int wmax = std::max(m1, 1);
-    // window lengths: the LDS tile of the window kernel holds kWinCols columns
-    const int kauto64 = std::max(1, std::min(kWinMax, kWinCols64 / wmax));
-    const int kauto32 = std::max(1, std::min(kWinMax, kWinCols32 / wmax));
-    const int K64 = o.window > 0 ? std::min(o.window, kauto64) : kauto64;
-    const int K32 = o.window > 0 ? std::min(o.window, kauto32) : kauto32;
-    const int nring = std::max(K64, form32 ? K32 : 1) + 2;
+    const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
     const size_t b64 = (size_t)n * wmax * sizeof(zd), b32 = (size_t)n * wmax * sizeof(zf);
-    if ((int)h->Vring.size() < nring) h->Vring.resize(nring);
-    if (form32 && (int)h->Vring32.size() < nring) h->Vring32.resize(nring);
-    for (int k = 1; k < nring; ++k) CHK(ensure(h->Vring[k], b64));
-    for (int k = 0; k < (form32 ? nring : 0); ++k) CHK(ensure(h->Vring32[k], b32));
     CHK(ensure(h->T, b64));
     CHK(ensure(h->W, b64));
     CHK(ensure(h->P[0], b64 * s));
     CHK(ensure(h->P[1], b64 * s));
-    CHK(ensure(h->wlist, 2 * 64 * sizeof(int32_t)));
-    std::vector<void *> ring64(nring), ring32(nring, nullptr);
-    ring64[0] = h->V0.p;
-    for (int k = 1; k < nring; ++k) ring64[k] = h->Vring[k].p;
-    for (int k = 0; k < (form32 ? nring : 0); ++k) ring32[k] = h->Vring32[k].p;
     if (form32) {
         CHK(ensure(h->T32, b32));
         CHK(ensure(h->W32, b32));
         CHK(ensure(h->P32[0], b32 * s));
         CHK(ensure(h->P32[1], b32 * s));
-        CHK(ensure(h->Xlo, (size_t)n * m * s * sizeof(zf)));
     }
+    CHK(ensure(h->wcoef, wincoef_bytes()));
+    CHK(ensure(h->wlist, 64 * sizeof(int32_t)));
+    const WinCoef WC = wincoef_at(h->wcoef.p);
+
+    // Window length K: the Lanczos blocks of up to K steps are kept and the
+    // per-shift iterates are formed from them once per window.  Half of the
+    // free device memory (counting the rings this handle already holds) is
+    // the budget; the FP32 phase also flushes into the FP64 solution at
+    // least every ru_interval steps.
+    int K64 = 1, K32 = 1;
+    {
+        size_t freeb = 0, totalb = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &totalb));
+        double held = 0.0;
+        for (const DevBuf &r : h->Vring) held += (double)r.bytes;
+        for (const DevBuf &r : h->Vring32) held += (double)r.bytes;
+        const double budget = 0.5 * ((double)freeb + held);
+        const double per_step = (double)b64 + (form32 ? (double)b32 : 0.0);
+        const double kfit = std::floor(budget / per_step) - 2.0;
+        int K = (int)std::min<double>((double)kWinMax, kfit);
+        if (o.window > 0) K = std::min(K, o.window);
+        K = std::min(K, steps);
+        if (K < 1) return fail(DSBCG_ERR_OOM, "not enough device memory for the Lanczos blocks of a window");
+        K64 = K;
+        K32 = std::min(K, std::max(1, o.ru_interval));
+    }
+    const int nring64 = K64 + 2, nring32 = form32 ? K32 + 2 : 0;
+    if ((int)h->Vring.size() < nring64) h->Vring.resize(nring64);
+    if ((int)h->Vring32.size() < nring32) h->Vring32.resize(nring32);
+    for (int k = 1; k < nring64; ++k) CHK(ensure(h->Vring[k], b64));
+    for (int k = 0; k < nring32; ++k) CHK(ensure(h->Vring32[k], b32));
+    std::vector<void *> ring64(nring64), ring32(nring32);
+    ring64[0] = h->V0.p;
+    for (int k = 1; k < nring64; ++k) ring64[k] = h->Vring[k].p;
+    for (int k = 0; k < nring32; ++k) ring32[k] = h->Vring32[k].p;
+    // coefficient table and window column pointers, sized for the longest window
+    const int npairs_max = (wmax + 1) / 2 + (std::max(K64, K32) * wmax + 1) / 2;
+    CHK(ensure(h->wtable, (size_t)s * npairs_max * 4 * 64 * sizeof(double)));
+    CHK(ensure(h->colptr, (size_t)std::max(K64, K32) * wmax * sizeof(void *)));
     bool lo = false;
-    int since_flush = 0;
-    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_reset(S, s, st));
+    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_reset(WC, st));
 
     // Lanczos blocks by step: vidx[i] = ring slot of V_i, bw[i] = width
     std::vector<int> vidx(2, -1), bw(2, 0);
     std::vector<int> freelist;
-    for (int k = nring - 1; k >= 1; --k) freelist.push_back(k);
+    for (int k = nring64 - 1; k >= 1; --k) freelist.push_back(k);
     vidx[1] = 0;
     bw[1] = m1;
     auto ring = [&](int i) -> void * { return lo ? ring32[vidx[i]] : ring64[vidx[i]]; };
@@ -590,8 +614,8 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     std::vector<int32_t> wset;  // shifts updated in the current window
     int status = DSBCG_OK;
     int iters = 0;
-    const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
     std::vector<int32_t> act;
+    std::vector<void *> colptr_host;
 
     auto active_list = [&](void) {
         act.clear();
@@ -605,15 +629,6 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                 if ((h->rep_host->colmask[j] >> l) & 1u) e = std::max(e, h->rep_host->est[j][l]);
         return e;
     };
-    auto flush_lo = [&](void) -> int {
-        // X_hi += X_lo, X_lo = 0 (FP64 accumulation of the solution)
-        CHK(copy(h, m * s, cm(h->Xlo.p, n, false), cm(h->X.p, n, true), true, st));
-        HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
-        since_flush = 0;
-        stt.reliable_updates += 1;
-        return DSBCG_OK;
-    };
-    // Apply the window i0+1 .. i to X_j (and P_j for the shifts still active).
     auto release = [&](int i) {
         // V_{i0} .. V_{i-1} are no longer needed once the window ends at step i
         for (int k = std::max(i0, 1); k < i; ++k)
@@ -623,55 +638,76 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             }
         i0 = i;
     };
-    auto apply_window = [&](int i) -> int {
+    // Apply the window i0+1 .. i to X_j, and form P_{j,i} for the shifts
+    // still active when the iteration goes on (need_p).
+    auto apply_window = [&](int i, bool need_p) -> int {
         if (wset.empty() || i <= i0) {
             release(i);
             wset = act;
             return DSBCG_OK;
         }
-        WinArgs wa;
-        memset(&wa, 0, sizeof(wa));
-        wa.nrows = n;
-        wa.K = i - i0;
-        for (int u = 0; u < wa.K; ++u) {
-            wa.wb[u] = bw[i0 + 1 + u];
-            wa.Vw[u] = ring(i0 + 1 + u);
+        const size_t esz = lo ? sizeof(zf) : sizeof(zd);
+        WindowTable wt;
+        memset(&wt, 0, sizeof(wt));
+        wt.nshift = (int)wset.size();
+        wt.bp0 = i0 >= 1 ? bw[i0] : 0;
+        wt.m = m;
+        wt.K = i - i0;
+        colptr_host.clear();
+        for (int u = 0; u < wt.K; ++u) {
+            const int w = bw[i0 + 1 + u];
+            wt.wb[u] = w;
+            for (int c = 0; c < w; ++c)
+                colptr_host.push_back((char *)ring(i0 + 1 + u) + (size_t)c * n * esz);
         }
-        wa.bp0 = i0 >= 1 ? bw[i0] : 0;
-        wa.Pold = lo ? h->P32[pcur].p : h->P[pcur].p;
-        wa.Pnew = lo ? h->P32[pcur ^ 1].p : h->P[pcur ^ 1].p;
-        wa.bend = bw[i];
-        wa.pstride = n * wmax;
-        wa.m = m;
-        wa.X = lo ? h->Xlo.p : h->X.p;
-        wa.xstride = n * m;
-        wa.G = lo ? (const void *)S->Wg32 : (const void *)S->Wg;
-        wa.Fp = lo ? (const void *)S->Wfp32 : (const void *)S->Wfp;
-        wa.H = lo ? (const void *)S->Wh32 : (const void *)S->Wh;
-        wa.F = lo ? (const void *)S->Wf32 : (const void *)S->Wf;
-        int32_t *wl = h->list_host + 64;  // pinned: window shift list, then P flags
+        wt.ncolv = (int)colptr_host.size();
         std::vector<int32_t> pm(s, 0);
-        for (int j : act) pm[j] = 1;
+        if (need_p)
+            for (int j : act) pm[j] = 1;
+        wt.bend = (need_p && !act.empty()) ? bw[i] : 0;
+        wt.pairs_p = (wt.bp0 + 1) / 2;
+        wt.npairs = wt.pairs_p + (wt.ncolv + 1) / 2;
+        wt.nmt = (m + wt.bend + 7) / 8;
+        int32_t *wl = h->list_host + 64;  // pinned: window shift list, then P flags
         for (size_t q = 0; q < wset.size(); ++q) wl[q] = wset[q];
         for (int j = 0; j < s; ++j) wl[16 + j] = pm[j];
         HIPCHK(hipMemcpyAsync(h->wlist.p, wl, 64 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        wa.shifts = (const int32_t *)h->wlist.p;
-        wa.nshift = (int)wset.size();
-        wa.pmask = (const int32_t *)h->wlist.p + 16;
-        wa.xmask = S->Wmask;
-        wa.count = S->Wcount;
-        double cols = 0;
-        for (int u = 0; u < wa.K; ++u) cols += wa.wb[u];
-        cols += (double)wset.size() * (wa.bp0 + wa.bend + 2.0 * m);
-        PROF_LAUNCH(h, prof_cls(kProfShift, !lo), cols * (double)n * (lo ? sizeof(zf) : sizeof(zd)), st,
-                    window_apply(!lo, wa, st));
-        // the next window starts after step i; P_{j,i} now lives in P[pcur ^ 1].
-        // (The pinned list is rewritten only after the next step's report,
-        // which waits for the stream.)
+        if (wt.ncolv > 0)
+            HIPCHK(hipMemcpyAsync(h->colptr.p, colptr_host.data(), colptr_host.size() * sizeof(void *),
+                                  hipMemcpyHostToDevice, st));
+        const int32_t *dshift = (const int32_t *)h->wlist.p, *dpm = dshift + 16;
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_window_table(WC, wt, dshift, dpm, !lo, h->wtable.p, st));
+        WinArgs wa;
+        memset(&wa, 0, sizeof(wa));
+        wa.nrows = n;
+        wa.ncolv = wt.ncolv;
+        wa.colptr = (const void *const *)h->colptr.p;
+        wa.bp0 = wt.bp0;
+        wa.Pold = lo ? h->P32[pcur].p : h->P[pcur].p;
+        wa.Pnew = lo ? h->P32[pcur ^ 1].p : h->P[pcur ^ 1].p;
+        wa.bend = wt.bend;
+        wa.pstride = n * wmax;
+        wa.m = m;
+        wa.X = (zd *)h->X.p;
+        wa.xstride = n * m;
+        wa.table = h->wtable.p;
+        wa.npairs = wt.npairs;
+        wa.pairs_p = wt.pairs_p;
+        wa.nmt = wt.nmt;
+        wa.shifts = dshift;
+        wa.nshift = wt.nshift;
+        wa.xmask = WC.Wmask;
+        wa.pmask = dpm;
+        const double bytes = (double)n * ((double)esz * (wt.ncolv + wt.nshift * (wt.bp0 + wt.bend)) +
+                                          2.0 * sizeof(zd) * m * wt.nshift);
+        PROF_LAUNCH(h, prof_cls(kProfShift, !lo), bytes, st, window_apply(!lo, wa, st));
+        // the host buffers are rewritten only after the next step's report,
+        // which waits for the stream
         pcur ^= 1;
         release(i);
         wset = act;
-        if (lo && since_flush >= std::max(1, o.ru_interval)) CHK(flush_lo());
+        if (lo) stt.reliable_updates += 1;
         return DSBCG_OK;
     };
     active_list();
@@ -680,19 +716,23 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
 
     for (int i = 1; !done && i <= steps; ++i) {
         if (form32 && !lo && max_active_est() <= switch_at) {
-            // continue the same recurrences with FP32 vectors (the window was
-            // applied at the end of the previous step)
-            CHK(copy(h, b, cm(ring64[vidx[i]], n, true), cm(ring32[vidx[i]], n, false), false, st));
+            // continue the same recurrences with FP32 vectors (the window
+            // ended with the previous step): V_{i-1}, V_i and P_{j,i-1} move
+            // to the FP32 ring and buffers
+            freelist.clear();
+            for (int k = nring32 - 1; k >= 2; --k) freelist.push_back(k);
+            CHK(copy(h, b, cm(ring64[vidx[i]], n, true), cm(ring32[1], n, false), false, st));
+            vidx[i] = 1;
             if (i > 1) {
-                CHK(copy(h, bp, cm(ring64[vidx[i - 1]], n, true), cm(ring32[vidx[i - 1]], n, false),
-                         false, st));
+                CHK(copy(h, bp, cm(ring64[vidx[i - 1]], n, true), cm(ring32[0], n, false), false, st));
+                vidx[i - 1] = 0;
                 for (int j : act)
                     CHK(copy(h, bp, cm((zd *)h->P[pcur].p + (int64_t)j * n * wmax, n, true),
                              cm((zf *)h->P32[pcur].p + (int64_t)j * n * wmax, n, false), false, st));
+            } else {
+                freelist.push_back(0);
             }
-            HIPCHK(hipMemsetAsync(h->Xlo.p, 0, (size_t)n * m * s * sizeof(zf), st));
             lo = true;
-            since_flush = 0;
             stt.switch_iter = i;
         }
         const bool f64 = !lo;
@@ -713,7 +753,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         void *Vc = ring(i), *Vp = i > 1 ? ring(i - 1) : ring(i), *Vn = ring(i + 1);
         void *T = lo ? h->T32.p : h->T.p, *Wb = lo ? h->W32.p : h->W.p;
         const void *Ul = lo ? h->Ul32.p : h->Ul64.p;
-        // W = A V_i
+    // W = A V_i
         CHK(apply_A_cm(h, f64, Ul, kappa, Vc, T, Wb, b, st));
         // alpha_i = V_i^H (W - V_{i-1} beta_i^H)
         {
@@ -736,16 +776,14 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                                        (int)act.size(), st));
         {
             WindowStep wsp;
-            memset(&wsp, 0, sizeof(wsp));
             wsp.t = i - i0 - 1;
             wsp.bp0 = i0 >= 1 ? bw[i0] : 0;
             wsp.b = b;
             wsp.bp = bp;
             wsp.m = m;
             bw[i] = b;
-            for (int u = 0; u <= wsp.t; ++u) wsp.wb[u] = bw[i0 + 1 + u];
             PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                        small_window_update(S, rep, wsp, (const int32_t *)h->list.p, (int)act.size(), st));
+                        small_window_update(S, rep, WC, wsp, (const int32_t *)h->list.p, (int)act.size(), st));
         }
         // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
         {
@@ -802,16 +840,13 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         active_list();
         if (bnew == 0) done = true;
         if (o.fixed_iters <= 0 && act.empty()) done = true;
-        if (lo) ++since_flush;
         const bool switch_next = form32 && !lo && !done && max_active_est() <= switch_at;
-        const bool ru_due = lo && since_flush >= std::max(1, o.ru_interval);
-        if (i - i0 >= K || done || i == steps || switch_next || ru_due) CHK(apply_window(i));
+        if (i - i0 >= K || done || i == steps || switch_next) CHK(apply_window(i, !done && i < steps));
         bp = b;
         b = bnew;
         bw[i + 1] = bnew;
         stt.final_width = bnew;
     }
-    if (lo) CHK(flush_lo());
     stt.block_iters += iters;
     if (status == DSBCG_OK && !done && o.fixed_iters <= 0)
         status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
