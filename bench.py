@@ -120,11 +120,12 @@ def ingest_counters(fetch_dir, write_dir, command):
     fetch, write = _per_dispatch(fetch_dir, "FETCH_SIZE"), _per_dispatch(write_dir, "WRITE_SIZE")
 
     def copy_kib(table):
-        # the calibration copy: the largest dispatch of a kernel outside this library
-        c = [v for (n, v) in table.values() if kernel_class(n) is None]
+        # the calibration copy: the runtime's buffer-copy kernel, the first one
+        # of the run (bench.py --calibrate-copy launches it before any other copy)
+        c = sorted((int(d), v) for d, (n, v) in table.items() if "copyBuffer" in n)
         if not c:
             raise SystemExit("no calibration copy dispatch found (run the bench with --calibrate-copy)")
-        return max(c)
+        return c[0][1]
 
     f_fac = COPY_BYTES / (1024.0 * copy_kib(fetch))
     w_fac = COPY_BYTES / (1024.0 * copy_kib(write))
