@@ -85,7 +85,8 @@ typedef struct {
     int32_t window;       /* per-shift update window: the Lanczos blocks of up to `window`
                              block steps are kept and X_j (and P_j, if the iteration goes on)
                              are formed from them once per window.  0: the longest window
-                             whose blocks fit in half of the free device memory, at most 128;
+                             whose blocks fit in three quarters of the free device memory less
+                             4 GiB, at most 128;
                              1: every step.  The result is the same up to rounding */
     double switch_at;     /* FP32 form: the iteration runs in FP64 until every active estimated
                              relative residual is <= switch_at, then continues the same

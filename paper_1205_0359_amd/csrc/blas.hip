@@ -81,8 +81,8 @@ __device__ inline void combine_row(const TsArgs &a, const cx<R> *coef, int64_t r
     }
 }
 
-// Register Gram: GRAM 0 none, 1 out^H out (upper triangle, mirrored), 2 L^H out;
-// K inputs.
+// Register Gram: GRAM 0 none, 1 out^H out (upper triangle, mirrored), 2 L^H out,
+// 3 the diagonal of out^H out only (column norms); K inputs.
 template <typename R, int B, int K, int GRAM>
 __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
     __shared__ cx<R> coef[3 * B * B];
@@ -122,6 +122,9 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
             for (int p = 0; p < B; ++p)
 #pragma unroll
                 for (int q = p; q < B; ++q) cmac_conj(G[p * B + q], od[p], od[q]);
+        } else if (GRAM == 3) {
+#pragma unroll
+            for (int q = 0; q < B; ++q) G[q * B + q].x += norm2(cvt<double>(o[q]));
         } else if (GRAM == 2) {
             zd od[B];
 #pragma unroll
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
     for (int p = 0; p < B; ++p)
 #pragma unroll
         for (int q = 0; q < B; ++q) {
-            if (GRAM == 1 && q < p) continue;
+            if ((GRAM == 1 && q < p) || (GRAM == 3 && q != p)) continue;
             zd v = G[p * B + q];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
@@ -155,10 +158,13 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
         int p = threadIdx.x / B, q = threadIdx.x - p * B;
         const bool mirror = GRAM == 1 && q < p;
         const int e = mirror ? q * B + p : p * B + q;
-        zd s = red[0][e];
-        s = s + red[1][e];
-        s = s + red[2][e];
-        s = s + red[3][e];
+        zd s = mk<double>(0, 0);
+        if (GRAM != 3 || p == q) {
+            s = red[0][e];
+            s = s + red[1][e];
+            s = s + red[2][e];
+            s = s + red[3][e];
+        }
         a.partials[(int64_t)blockIdx.x * 256 + p * 16 + q] = mirror ? conj(s) : s;
     }
 }
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
     __shared__ zd red[4][64];
     load_coefs<R, B>(a, coef);
     const int t = threadIdx.x;
-    const int bl = (a.gram == 1) ? a.bout : a.bl;
+    const int bl = (a.gram == 2) ? a.bl : a.bout;  // gram 3 (diagonal) runs as gram 1
     const int nbq = (a.bout + 1) / 2, nbp = (bl + 1) / 2;
     const int nblk = nbp * nbq;
     const int blk = t & 63, half = t >> 6;
@@ -220,7 +226,7 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
         }
         __syncthreads();
         if (a.gram && blk < nblk) {
-            const cx<R> *L = (a.gram == 1) ? so : sl;
+            const cx<R> *L = (a.gram == 2) ? sl : so;
             const int p0 = 2 * bp, q0 = 2 * bq;
             for (int r = half * 64; r < half * 64 + 64 && r < kTileRows; ++r) {
                 const zd l0 = cvt<double>(L[p0 * kTileRows + r]);
@@ -255,10 +261,19 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
 
 template <typename R, int B, int K>
 void ts_launch_reg(const TsArgs &a, int nwg, hipStream_t st) {
-    if (a.gram == 1)
-        hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 1>), dim3(nwg), dim3(256), 0, st, a);
-    else if (a.gram == 2)
-        hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 2>), dim3(nwg), dim3(256), 0, st, a);
+    // widths 7 and 8 only without a full Gram (register budget)
+    if constexpr (B <= 6) {
+        if (a.gram == 1) {
+            hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 1>), dim3(nwg), dim3(256), 0, st, a);
+            return;
+        }
+        if (a.gram == 2) {
+            hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 2>), dim3(nwg), dim3(256), 0, st, a);
+            return;
+        }
+    }
+    if (a.gram == 3)
+        hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 3>), dim3(nwg), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 0>), dim3(nwg), dim3(256), 0, st, a);
 }
@@ -279,6 +294,8 @@ void ts_launch(const TsArgs &a, int w, int nwg, hipStream_t st) {
         case 4: ts_launch_k<R, 4>(a, nwg, st); break;
         case 5: ts_launch_k<R, 5>(a, nwg, st); break;
         case 6: ts_launch_k<R, 6>(a, nwg, st); break;
+        case 7: ts_launch_k<R, 7>(a, nwg, st); break;
+        case 8: ts_launch_k<R, 8>(a, nwg, st); break;
         default:
             hipLaunchKernelGGL(ts_lds_kernel<R>, dim3(nwg), dim3(TileRows<R>::value), 0, st, a);
             break;
@@ -290,11 +307,12 @@ hipError_t ts_run(bool fp64, TsArgs a, int max_wg, int *nwg_out, hipStream_t st)
     for (int k = 0; k < a.K; ++k)
         if (a.bx[k] < 0 || a.bx[k] > kMaxW) return hipErrorInvalidValue;
     if (a.gram == 2 && (a.bl < 1 || a.bl > kMaxW)) return hipErrorInvalidValue;
-    // register kernel: every input, output and L width within w <= 6
+    // register kernel: every input, output and L width within w <= 6, or
+    // w <= 8 without a full Gram
     int w = a.bout;
     for (int k = 0; k < a.K; ++k) w = std::max(w, a.bx[k]);
     if (a.gram == 2) w = std::max(w, a.bl);
-    const bool reg = w <= 6;
+    const bool reg = w <= 6 || (w <= 8 && (a.gram == 0 || a.gram == 3));
     const int tile = reg ? 256 : (fp64 ? TileRows<double>::value : TileRows<float>::value);
     int64_t tiles = (a.nrows + tile - 1) / tile;
     int nwg = (int)(tiles < max_wg ? tiles : max_wg);
@@ -372,8 +390,86 @@ __global__ __launch_bounds__(256) void copy_kernel(int64_t V, int cols, const cx
     }
 }
 
+// Layout change (column-major <-> [V][12][ld]) through an LDS tile of 32
+// sites x 12 components x up to 8 columns: the tile is read in the input's
+// contiguous order and written in the output's, so both sides are coalesced.
+constexpr int kTpSites = 32, kTpCols = 8;
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void transpose_kernel(int64_t V, int cols, const cx<Ti> *__restrict__ in,
+                                                        Strides si, int in_cm, cx<To> *__restrict__ out,
+                                                        Strides so, int accumulate, double scale) {
+    // [site][comp][col], one padding element per site against bank conflicts
+    constexpr int kSiteStride = 12 * kTpCols + 1;
+    __shared__ cx<double> tile[kTpSites * kSiteStride];
+    const int64_t x0 = (int64_t)blockIdx.x * kTpSites;
+    const int ns = (int)min((int64_t)kTpSites, V - x0);
+    for (int r0 = 0; r0 < cols; r0 += kTpCols) {
+        const int nc = min(kTpCols, cols - r0);
+        const int nel = ns * 12 * nc;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+            int x, c, r;
+            if (in_cm) {  // sites fastest
+                x = e % ns;
+                const int k = e / ns;
+                c = k % 12;
+                r = k / 12;
+            } else {      // columns fastest
+                r = e % nc;
+                const int k = e / nc;
+                c = k % 12;
+                x = k / 12;
+            }
+            const cx<double> v = cvt<double>(in[si.base + (x0 + x) * si.site + c * si.comp + (r0 + r) * si.col]);
+            tile[x * kSiteStride + c * kTpCols + r] = mk<double>(scale * v.x, scale * v.y);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+            int x, c, r;
+            if (in_cm) {  // output [V][12][ld]: columns fastest
+                r = e % nc;
+                const int k = e / nc;
+                c = k % 12;
+                x = k / 12;
+            } else {      // output column-major: sites fastest
+                x = e % ns;
+                const int k = e / ns;
+                c = k % 12;
+                r = k / 12;
+            }
+            const cx<double> v = tile[x * kSiteStride + c * kTpCols + r];
+            cx<To> *o = out + so.base + (x0 + x) * so.site + c * so.comp + (r0 + r) * so.col;
+            if (accumulate) {
+                const cx<double> w = cvt<double>(*o);
+                *o = cvt<To>(mk<double>(w.x + v.x, w.y + v.y));
+            } else {
+                *o = cvt<To>(v);
+            }
+        }
+    }
+}
+
 hipError_t copy_field(int64_t V, int cols, FieldDesc in, FieldDesc out, bool accumulate,
                       double scale, hipStream_t st) {
+    if (in.layout != out.layout) {
+        const Strides si = strides_of(in, V), so = strides_of(out, V);
+        const dim3 grid((unsigned)((V + kTpSites - 1) / kTpSites));
+        const int icm = in.layout == kCM, acc = accumulate ? 1 : 0;
+#define DSBCG_TP(TI, TO)                                                                       \
+    hipLaunchKernelGGL((transpose_kernel<TI, TO>), grid, dim3(256), 0, st, V, cols,            \
+                       (const cx<TI> *)in.p, si, icm, (cx<TO> *)out.p, so, acc, scale)
+        if (in.fp64 && out.fp64)
+            DSBCG_TP(double, double);
+        else if (in.fp64)
+            DSBCG_TP(double, float);
+        else if (out.fp64)
+            DSBCG_TP(float, double);
+        else
+            DSBCG_TP(float, float);
+#undef DSBCG_TP
+        return hipGetLastError();
+    }
     const int64_t total = V * 12 * cols;
     const int64_t want = (total + 255) / 256;
     const dim3 grid((unsigned)(want < 65536 ? (want > 0 ? want : 1) : 65536));

@@ -22,7 +22,8 @@ struct TsArgs {
     int bout;
     void *out;               // optional store of the combination
     int64_t cso;
-    int gram;                // 0: none, 1: partial out^H out, 2: partial L^H out
+    int gram;                // 0: none, 1: partial out^H out, 2: partial L^H out,
+                             // 3: diagonal of out^H out only
     const void *L;
     int64_t csl;
     int bl;

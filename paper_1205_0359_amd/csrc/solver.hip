@@ -361,7 +361,7 @@ int initial_qr(dsbcg_ctx *h, int M, double tau_B, hipStream_t st, int *m1_out) {
         a.K = 1;
         a.X[0] = Bp + (int64_t)c0 * n; a.bx[0] = cnt; a.C[0] = nullptr;
         a.bout = cnt;
-        a.gram = 1;
+        a.gram = 3;  // column norms only
         CHK(ts.run_reduce(a, cnt, 0));
         PROF_LAUNCH(h, kProfSmall, 0.0, st, small_bnorms(S, rep, red_slot(h, 0), c0, cnt, st));
     }
@@ -450,9 +450,11 @@ int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
 // every shift (Sec. 4: relative residual); B and X in the caller's layout, the
 // FP64 structure-of-arrays links in h->Ul64.  With keep_j >= 0 only that shift
 // is evaluated and its residual block is stored in Rkeep (caller's layout).
+// Xcm, if not NULL, holds the same iterates column-major ([s][m][n]) and is
+// read instead of Xapi.
 int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi, int64_t bstride,
                    const void *Xapi, int m, const double *sigma, int s, double *out, int keep_j,
-                   void *Rkeep) {
+                   void *Rkeep, const zd *Xcm = nullptr) {
     const int64_t n = 12 * (int64_t)h->g.V;
     const size_t blk = (size_t)n * m * sizeof(zd);
     CHK(ensure_common(h));
@@ -471,22 +473,26 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
             a.K = 1;
             a.X[0] = h->R0.p; a.bx[0] = m; a.C[0] = nullptr;
             a.bout = m;
-            a.gram = 1;
+            a.gram = 3;  // column norms only
             CHK(ts.run_reduce(a, m, 4));
             std::vector<zd> g(256);
             HIPCHK(hipMemcpyAsync(g.data(), red_slot(h, 4), 256 * sizeof(zd), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             for (int l = 0; l < m; ++l) bn[l] = std::sqrt(std::max(g[l * 16 + l].x, 0.0));
         }
-        CHK(copy(h, m, api((const zd *)Xapi + (int64_t)j * n * m, m), cm(h->R1.p, n, true), false, st));
-        CHK(apply_A_cm(h, true, h->Ul64.p, kappa, h->R1.p, h->R2.p, h->R3.p, m, st));
+        const void *xj = h->R1.p;
+        if (Xcm)
+            xj = Xcm + (int64_t)j * n * m;
+        else
+            CHK(copy(h, m, api((const zd *)Xapi + (int64_t)j * n * m, m), cm(h->R1.p, n, true), false, st));
+        CHK(apply_A_cm(h, true, h->Ul64.p, kappa, xj, h->R2.p, h->R3.p, m, st));
         TsArgs a = ts_args(n);
         a.K = 3;
         a.X[0] = h->R0.p; a.bx[0] = m; a.C[0] = nullptr;
-        a.X[1] = h->R1.p; a.bx[1] = m; a.C[1] = coef_slot(h, 2);
+        a.X[1] = xj; a.bx[1] = m; a.C[1] = coef_slot(h, 2);
         a.X[2] = h->R3.p; a.bx[2] = m; a.C[2] = coef_slot(h, 3);
         a.bout = m;
-        a.gram = 1;
+        a.gram = 3;  // column norms only
         if (keep_j >= 0) a.out = h->R2.p;
         // coefficient matrices -sigma_j I and -I
         for (int l = 0; l < m; ++l) {
@@ -563,10 +569,10 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     const WinCoef WC = wincoef_at(h->wcoef.p);
 
     // Window length K: the Lanczos blocks of up to K steps are kept and the
-    // per-shift iterates are formed from them once per window.  Half of the
-    // free device memory (counting the rings this handle already holds) is
-    // the budget; the FP32 phase also flushes into the FP64 solution at
-    // least every ru_interval steps.
+    // per-shift iterates are formed from them once per window.  Three
+    // quarters of the free device memory (counting the rings this handle
+    // already holds), less 4 GiB, is the budget; the FP32 phase also flushes
+    // into the FP64 solution at least every ru_interval steps.
     int K64 = 1, K32 = 1;
     {
         size_t freeb = 0, totalb = 0;
@@ -574,7 +580,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         double held = 0.0;
         for (const DevBuf &r : h->Vring) held += (double)r.bytes;
         for (const DevBuf &r : h->Vring32) held += (double)r.bytes;
-        const double budget = 0.5 * ((double)freeb + held);
+        const double budget = 0.75 * ((double)freeb + held) - 4.0 * (1 << 30);
         const double per_step = (double)b64 + (form32 ? (double)b32 : 0.0);
         const double kfit = std::floor(budget / per_step) - 2.0;
         int K = (int)std::min<double>((double)kWinMax, kfit);
@@ -1018,8 +1024,10 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
     SolveStats stt;
     double main_max = 0.0;
     int status = solve_core(h, kappa, B, bstride, m, sigma, s, tol, o, o.switch_at, X, stt, st);
+    bool fallback = false;
     if (status == DSBCG_ERR_ARG && bstride != 0 && stt.rank0 == 0) {
         // the blocks span more than 16 directions: one block solve per shift
+        fallback = true;
         stt = SolveStats();
         status = DSBCG_OK;
         for (int j = 0; j < s && status == DSBCG_OK; ++j) {
@@ -1038,7 +1046,10 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
     std::vector<double> tr((size_t)s * m, 0.0);
     const bool want_true = (stats && stats->true_relres) || o.refine;
     if (want_true && status == DSBCG_OK) {
-        CHK(true_residuals(h, st, kappa, B, bstride, X, m, sigma, s, tr.data(), -1, nullptr));
+        // the iterates are still column-major in h->X after one block solve
+        // over all shifts (not after the per-shift fallback)
+        const zd *xcm = !fallback ? (const zd *)h->X.p : nullptr;
+        CHK(true_residuals(h, st, kappa, B, bstride, X, m, sigma, s, tr.data(), -1, nullptr, xcm));
         for (double v : tr) main_max = std::max(main_max, v);
         for (int round = 0; o.refine && o.fixed_iters <= 0 && round < 2; ++round) {
             bool any = false;
