@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=6,
                    help="block steps of the oracle sample")
     p.add_argument("--stencil-calls", type=int, default=100)
+    p.add_argument("--grad", action="store_true", default=True,
+                   help="also time forward + backward of the differentiable solve (16^4)")
+    p.add_argument("--no-grad", dest="grad", action="store_false")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run a plain 1 GiB device copy (the reference kernel for "
                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -273,6 +276,41 @@ def stencil_rate(dsb, h, dU, w, b, prec, calls):
             "layout": "[V][4][3][b] (API)"}
 
 
+def grad_rate(dsb, prec, reps=3):
+    """Forward + backward of the differentiable solve on the 16^4 differentiation
+    workload: L = sum_j a_j Re tr(B^H X_j) with a_j in [0.1, 1] (seeded), gradients
+    for U, B and sigma; X_j recomputed in the backward pass."""
+    import numpy as np
+    import torch
+    from paper_1205_0359_amd import autograd, inputs
+    w = inputs.WORKLOADS["smooth16^4_m4_s6_grad"]
+    U, B = w.make()
+    alpha = torch.from_numpy(inputs.rng_for(w.wid, 2).uniform(0.1, 1.0, len(w.shifts))).to("cuda")
+    h = dsb.Handle(w.L)
+    dU = torch.from_numpy(U).to("cuda").requires_grad_(True)
+    dB = torch.from_numpy(B).to("cuda").requires_grad_(True)
+    sig = torch.tensor(w.shifts, dtype=torch.float64, requires_grad=True)
+    p = dsb.DSBCG_FP32_RELIABLE if prec == "fp32" else dsb.DSBCG_FP64
+    fw, bw = [], []
+    for k in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = autograd.solve(dU, dB, sig, h, w.kappa, w.tol, precision=p, recompute=True)
+        loss = (alpha.view(-1, 1, 1, 1, 1) * (dB.conj().unsqueeze(0) * X).real).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if k:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+        dU.grad = dB.grad = sig.grad = None
+    return {"workload": w.name, "form": prec, "ms_forward": round(1e3 * float(np.median(fw)), 3),
+            "ms_backward": round(1e3 * float(np.median(bw)), 3),
+            "note": "backward = adjoint block solve + X_j recompute + dL/dU, dL/dB, dL/dsigma kernels"}
+
+
 def cpu_baseline(w, gpu_iters, steps, max_sites=1 << 17):
     """The oracle on the host cores, on a bounded sample of the workload.
 
@@ -375,6 +413,11 @@ def main():
                 "traffic": traffic, "algorithmic_bytes_per_launch": alg_per_launch,
                 "avg_launch_us": round(kern[dom]["avg_launch_us"], 2)}
 
+    grad = None
+    if args.grad:
+        log("[bench] differentiation form")
+        grad = [grad_rate(dsb, f) for f in ("fp64", "fp32")]
+
     cpu = None
     if args.cpu_baseline:
         log("[bench] CPU oracle sample")
@@ -400,6 +443,7 @@ def main():
         "stencil": stencil,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "grad": grad,
         "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()},
     }
     print(json.dumps(line), flush=True)

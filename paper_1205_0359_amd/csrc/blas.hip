@@ -522,14 +522,16 @@ struct Mfma<double> {
     }
 };
 
-template <typename R>
+// window columns per LDS chunk: 32 KiB of staged rows
+template <typename R, int TILES>
 struct WinChunk {
-    static constexpr int value = sizeof(R) == 8 ? 32 : 64;  // window columns per LDS chunk
+    static constexpr int value = 32768 / (16 * TILES * (int)sizeof(cx<R>));
 };
 
 template <typename R, int NMT, int TILES>
 __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
-    constexpr int CH = WinChunk<R>::value;
+    constexpr int CH = WinChunk<R, TILES>::value;
+    static_assert(CH % 2 == 0, "chunks hold whole input pairs");
     constexpr int RW = 16 * TILES;  // rows per workgroup
     typedef typename Mfma<R>::v4 v4;
     __shared__ cx<R> vt[CH * RW];
@@ -583,17 +585,25 @@ __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
         if (!active) continue;
         const int npp = (min(CH, a.ncolv - c0) + 1) >> 1;
         const R *tc = tab + (size_t)(a.pairs_p + (c0 >> 1)) * NMT * 64;
+        // coefficients of the next pair are loaded while this pair multiplies
+        R cf[NMT];
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) cf[mt] = tc[mt * 64];
         for (int pp = 0; pp < npp; ++pp) {
             const R *src = (const R *)&vt[(2 * pp + sel) * RW + rl] + part;
             R d[TILES];
 #pragma unroll
             for (int t = 0; t < TILES; ++t) d[t] = src[2 * t * 16];
+            R cn[NMT];
+            const int pn = pp + 1 < npp ? pp + 1 : pp;
 #pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) {
-                const R cf = tc[(pp * NMT + mt) * 64];
+            for (int mt = 0; mt < NMT; ++mt) cn[mt] = tc[(pn * NMT + mt) * 64];
 #pragma unroll
-                for (int t = 0; t < TILES; ++t) acc[t][mt] = Mfma<R>::mac(cf, d[t], acc[t][mt]);
-            }
+            for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+                for (int t = 0; t < TILES; ++t) acc[t][mt] = Mfma<R>::mac(cf[mt], d[t], acc[t][mt]);
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) cf[mt] = cn[mt];
         }
     }
     if (!active) return;
@@ -614,10 +624,11 @@ __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
                 const int q = mt * 8 + 2 * g + h;
                 const R re = acc[t][mt][2 * h], im = acc[t][mt][2 * h + 1];
                 if (q < a.m) {
-                    if ((xm >> q) & 1u) {
-                        zd *x = X + (int64_t)q * n + row;
+                    zd *x = X + (int64_t)q * n + row;
+                    if (a.xinit)  // first window: X_j = increment (zero where never updated)
+                        *x = mk<double>((double)re, (double)im);
+                    else if ((xm >> q) & 1u)
                         *x = mk<double>(x->x + (double)re, x->y + (double)im);
-                    }
                 } else if (wp && q - a.m < a.bend) {
                     Pn[(int64_t)(q - a.m) * n + row] = mk<R>(re, im);
                 }
@@ -634,26 +645,21 @@ hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
         return hipErrorInvalidValue;
     if (a.nrows <= 0) return hipSuccess;
     const dim3 block(64 * a.nshift);
-    // four 16-row tiles per wave while the accumulators fit, else two
-    const bool four = fp64 ? a.nmt <= 2 : a.nmt <= 4;
-    const int rw = four ? 64 : 32;
-    const dim3 grid((unsigned)((a.nrows + rw - 1) / rw));
+    // 16-row tiles per wave: as many as the accumulators allow (8, 4 or 2)
+    const int tiles = fp64 ? (a.nmt <= 2 ? 4 : 2) : (a.nmt <= 2 ? 8 : 4);
+    const dim3 grid((unsigned)((a.nrows + 16 * tiles - 1) / (16 * tiles)));
 #define DSBCG_WIN(R, M, T) hipLaunchKernelGGL((window_kernel<R, M, T>), grid, block, 0, st, a)
-#define DSBCG_WIN_R(R)                                       \
-    do {                                                     \
-        if (four) {                                          \
-            if (a.nmt == 1) DSBCG_WIN(R, 1, 4);              \
-            else if (a.nmt == 2) DSBCG_WIN(R, 2, 4);         \
-            else if (a.nmt == 3) DSBCG_WIN(R, 3, 4);         \
-            else DSBCG_WIN(R, 4, 4);                         \
-        } else {                                             \
-            if (a.nmt == 3) DSBCG_WIN(R, 3, 2);              \
-            else DSBCG_WIN(R, 4, 2);                         \
-        }                                                    \
-    } while (0)
-    if (fp64) DSBCG_WIN_R(double);
-    else DSBCG_WIN_R(float);
-#undef DSBCG_WIN_R
+    if (fp64) {
+        if (a.nmt == 1) DSBCG_WIN(double, 1, 4);
+        else if (a.nmt == 2) DSBCG_WIN(double, 2, 4);
+        else if (a.nmt == 3) DSBCG_WIN(double, 3, 2);
+        else DSBCG_WIN(double, 4, 2);
+    } else {
+        if (a.nmt == 1) DSBCG_WIN(float, 1, 8);
+        else if (a.nmt == 2) DSBCG_WIN(float, 2, 8);
+        else if (a.nmt == 3) DSBCG_WIN(float, 3, 4);
+        else DSBCG_WIN(float, 4, 4);
+    }
 #undef DSBCG_WIN
     return hipGetLastError();
 }

@@ -78,6 +78,8 @@ struct WinArgs {
     int nshift;                 // <= 16
     const uint32_t *xmask;      // [s] columns of X_j to update
     const int32_t *pmask;       // [s] nonzero: write P_{j,end}
+    int xinit;                  // nonzero: X_j of the window's shifts is overwritten (every
+                                // column; the coefficients of columns never updated are zero)
 };
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st);
 

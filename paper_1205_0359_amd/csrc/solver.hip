@@ -538,7 +538,6 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     SmallState *S = stp(h);
     StepReport *rep = repp(h);
     HIPCHK(hipMemsetAsync(rep, 0, sizeof(StepReport), st));
-    HIPCHK(hipMemsetAsync(h->X.p, 0, (size_t)n * m * s * sizeof(zd), st));
     for (int j = 0; j < (bstride ? s : 1); ++j)
         CHK(copy(h, m, api((const zd *)B + (int64_t)j * bstride, m),
                  cm((zd *)h->Bint.p + (int64_t)j * m * n, n, true), false, st));
@@ -622,6 +621,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     int iters = 0;
     std::vector<int32_t> act;
     std::vector<void *> colptr_host;
+    bool xfresh = true;  // X has not been written yet in this solve
 
     auto active_list = [&](void) {
         act.clear();
@@ -704,6 +704,16 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         wa.shifts = dshift;
         wa.nshift = wt.nshift;
         wa.xmask = WC.Wmask;
+        // the first window writes X_j of its shifts; the others start from zero
+        wa.xinit = xfresh ? 1 : 0;
+        if (xfresh) {
+            std::vector<char> in_w(s, 0);
+            for (int j : wset) in_w[j] = 1;
+            for (int j = 0; j < s; ++j)
+                if (!in_w[j])
+                    HIPCHK(hipMemsetAsync((zd *)h->X.p + (int64_t)j * n * m, 0, (size_t)n * m * sizeof(zd), st));
+            xfresh = false;
+        }
         wa.pmask = dpm;
         const double bytes = (double)n * ((double)esz * (wt.ncolv + wt.nshift * (wt.bp0 + wt.bend)) +
                                           2.0 * sizeof(zd) * m * wt.nshift);
@@ -853,6 +863,8 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         bw[i + 1] = bnew;
         stt.final_width = bnew;
     }
+    if (xfresh)  // no window was applied (no step, or nothing to update)
+        HIPCHK(hipMemsetAsync(h->X.p, 0, (size_t)n * m * s * sizeof(zd), st));
     stt.block_iters += iters;
     if (status == DSBCG_OK && !done && o.fixed_iters <= 0)
         status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
