@@ -84,7 +84,7 @@ def kernel_class(name: str):
         return "block_gram_update." + prec
     if "window_kernel<" in name:
         return "shift_update." + prec
-    if "copy_kernel" in name or "links_soa_kernel" in name:
+    if "copy_kernel" in name or "links_soa_kernel" in name or "transpose_kernel" in name:
         return "convert"
     if "link_grad_kernel" in name:
         return "link_grad"
