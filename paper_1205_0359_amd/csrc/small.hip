@@ -352,8 +352,9 @@ __global__ __launch_bounds__(64) void window_table_kernel(WinCoef wc, WindowTabl
                 // window slot u of this column and its first column c0
                 int u = 0, c0 = 0;
                 while (u < wt.K - 1 && col >= c0 + wt.wb[u]) c0 += wt.wb[u++];
-                if (u < wc.Wcount[j]) {
-                    const zd *src = (xout ? wc.Wf : wc.Wh) + ((size_t)j * kWinMax + u) * 256;
+                const int slot = wt.slot0 + u;
+                if (slot < wc.Wcount[j]) {
+                    const zd *src = (xout ? wc.Wf : wc.Wh) + ((size_t)j * kWinMax + slot) * 256;
                     c = src[(col - c0) * 16 + qq];
                 }
             }
@@ -366,7 +367,8 @@ __global__ __launch_bounds__(64) void window_table_kernel(WinCoef wc, WindowTabl
 hipError_t small_window_table(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
                               const int32_t *pmask, bool fp64, void *table, hipStream_t stream) {
     if (wt.nshift <= 0 || wt.npairs <= 0) return hipSuccess;
-    if (wt.K < 1 || wt.K > kWinMax || wt.nmt < 1 || wt.nmt > 4) return hipErrorInvalidValue;
+    if (wt.K < 1 || wt.slot0 < 0 || wt.slot0 + wt.K > kWinMax || wt.nmt < 1 || wt.nmt > 4)
+        return hipErrorInvalidValue;
     const dim3 grid(wt.nshift, wt.npairs, wt.nmt);
     if (fp64)
         hipLaunchKernelGGL(window_table_kernel<double>, grid, dim3(64), 0, stream, wc, wt, shifts, pmask,

@@ -94,8 +94,9 @@ struct WindowTable {
     int ncolv;      // window columns (sum of the widths)
     int npairs;     // pairs_p + ceil(ncolv / 2)
     int nmt;        // 16-column output tiles: ceil(2 (m + bend) / 16)
-    int K;          // window slots
-    int wb[kWinMax];// widths of the window blocks
+    int K;          // window slots of this table (a contiguous part of the window)
+    int slot0;      // window slot of the first of them
+    int wb[kWinMax];// widths of those blocks
 };
 hipError_t small_window_table(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
                               const int32_t *pmask, bool fp64, void *table, hipStream_t stream);

@@ -598,20 +598,25 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     ring64[0] = h->V0.p;
     for (int k = 1; k < nring64; ++k) ring64[k] = h->Vring[k].p;
     for (int k = 0; k < nring32; ++k) ring32[k] = h->Vring32[k].p;
-    // coefficient table and window column pointers, sized for the longest window
-    const int npairs_max = (wmax + 1) / 2 + (std::max(K64, K32) * wmax + 1) / 2;
-    CHK(ensure(h->wtable, (size_t)s * npairs_max * 4 * 64 * sizeof(double)));
-    CHK(ensure(h->colptr, (size_t)std::max(K64, K32) * wmax * sizeof(void *)));
+    // coefficient tables and window column pointers, sized for the longest
+    // window (FP64 part and FP32 part each get their own region)
+    const int kwin = std::min((int)kWinMax, K64 + (form32 ? K32 : 0));
+    const int npairs_max = (wmax + 1) / 2 + (kwin * wmax + 1) / 2 + 1;
+    CHK(ensure(h->wtable, (size_t)2 * s * npairs_max * 4 * 64 * sizeof(double)));
+    CHK(ensure(h->colptr, (size_t)(kwin * wmax + 2) * sizeof(void *)));
     bool lo = false;
     PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_reset(WC, st));
 
-    // Lanczos blocks by step: vidx[i] = ring slot of V_i, bw[i] = width
-    std::vector<int> vidx(2, -1), bw(2, 0);
-    std::vector<int> freelist;
-    for (int k = nring64 - 1; k >= 1; --k) freelist.push_back(k);
-    vidx[1] = 0;
+    // Lanczos blocks by step: v64[i] / v32[i] = slot of V_i in the FP64 / FP32
+    // ring (-1: none), bw[i] = width.  After the switch to FP32 vectors the
+    // window's FP64 blocks stay in their ring until the window ends.
+    std::vector<int> v64(2, -1), v32(2, -1), bw(2, 0);
+    std::vector<int> free64, free32;
+    for (int k = nring64 - 1; k >= 1; --k) free64.push_back(k);
+    v64[1] = 0;
     bw[1] = m1;
-    auto ring = [&](int i) -> void * { return lo ? ring32[vidx[i]] : ring64[vidx[i]]; };
+    auto ring = [&](int i) -> void * { return lo ? ring32[v32[i]] : ring64[v64[i]]; };
+    int sw = 0;  // first step of the current window run with FP32 vectors (0: none)
 
     int b = m1, bp = 0;
     int pcur = 0;        // P buffer holding P_{j,i0}
@@ -637,93 +642,132 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     };
     auto release = [&](int i) {
         // V_{i0} .. V_{i-1} are no longer needed once the window ends at step i
-        for (int k = std::max(i0, 1); k < i; ++k)
-            if (vidx[k] >= 0) {
-                freelist.push_back(vidx[k]);
-                vidx[k] = -1;
+        for (int k = std::max(i0, 1); k < i; ++k) {
+            if (v64[k] >= 0) {
+                free64.push_back(v64[k]);
+                v64[k] = -1;
             }
+            if (v32[k] >= 0) {
+                free32.push_back(v32[k]);
+                v32[k] = -1;
+            }
+        }
         i0 = i;
+        sw = 0;
     };
     // Apply the window i0+1 .. i to X_j, and form P_{j,i} for the shifts
-    // still active when the iteration goes on (need_p).
+    // still active when the iteration goes on (need_p).  A window that spans
+    // the switch to FP32 vectors runs as two contractions: blocks up to sw in
+    // FP64 (with the P_{j,i0} term), the later ones in FP32; their P parts
+    // are added in FP32.
     auto apply_window = [&](int i, bool need_p) -> int {
         if (wset.empty() || i <= i0) {
             release(i);
             wset = act;
             return DSBCG_OK;
         }
-        const size_t esz = lo ? sizeof(zf) : sizeof(zd);
-        WindowTable wt;
-        memset(&wt, 0, sizeof(wt));
-        wt.nshift = (int)wset.size();
-        wt.bp0 = i0 >= 1 ? bw[i0] : 0;
-        wt.m = m;
-        wt.K = i - i0;
-        colptr_host.clear();
-        for (int u = 0; u < wt.K; ++u) {
-            const int w = bw[i0 + 1 + u];
-            wt.wb[u] = w;
-            for (int c = 0; c < w; ++c)
-                colptr_host.push_back((char *)ring(i0 + 1 + u) + (size_t)c * n * esz);
-        }
-        wt.ncolv = (int)colptr_host.size();
         std::vector<int32_t> pm(s, 0);
         if (need_p)
             for (int j : act) pm[j] = 1;
-        wt.bend = (need_p && !act.empty()) ? bw[i] : 0;
-        wt.pairs_p = (wt.bp0 + 1) / 2;
-        wt.npairs = wt.pairs_p + (wt.ncolv + 1) / 2;
-        wt.nmt = (m + wt.bend + 7) / 8;
+        const int bend = (need_p && !act.empty()) ? bw[i] : 0;
         int32_t *wl = h->list_host + 64;  // pinned: window shift list, then P flags
         for (size_t q = 0; q < wset.size(); ++q) wl[q] = wset[q];
         for (int j = 0; j < s; ++j) wl[16 + j] = pm[j];
         HIPCHK(hipMemcpyAsync(h->wlist.p, wl, 64 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        if (wt.ncolv > 0)
-            HIPCHK(hipMemcpyAsync(h->colptr.p, colptr_host.data(), colptr_host.size() * sizeof(void *),
-                                  hipMemcpyHostToDevice, st));
         const int32_t *dshift = (const int32_t *)h->wlist.p, *dpm = dshift + 16;
-        PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                    small_window_table(WC, wt, dshift, dpm, !lo, h->wtable.p, st));
-        WinArgs wa;
-        memset(&wa, 0, sizeof(wa));
-        wa.nrows = n;
-        wa.ncolv = wt.ncolv;
-        wa.colptr = (const void *const *)h->colptr.p;
-        wa.bp0 = wt.bp0;
-        wa.Pold = lo ? h->P32[pcur].p : h->P[pcur].p;
-        wa.Pnew = lo ? h->P32[pcur ^ 1].p : h->P[pcur ^ 1].p;
-        wa.bend = wt.bend;
-        wa.pstride = n * wmax;
-        wa.m = m;
-        wa.X = (zd *)h->X.p;
-        wa.xstride = n * m;
-        wa.table = h->wtable.p;
-        wa.npairs = wt.npairs;
-        wa.pairs_p = wt.pairs_p;
-        wa.nmt = wt.nmt;
-        wa.shifts = dshift;
-        wa.nshift = wt.nshift;
-        wa.xmask = WC.Wmask;
-        // the first window writes X_j of its shifts; the others start from zero
-        wa.xinit = xfresh ? 1 : 0;
         if (xfresh) {
+            // the first window writes X_j of its shifts; the others start from zero
             std::vector<char> in_w(s, 0);
             for (int j : wset) in_w[j] = 1;
             for (int j = 0; j < s; ++j)
                 if (!in_w[j])
                     HIPCHK(hipMemsetAsync((zd *)h->X.p + (int64_t)j * n * m, 0, (size_t)n * m * sizeof(zd), st));
-            xfresh = false;
         }
-        wa.pmask = dpm;
-        const double bytes = (double)n * ((double)esz * (wt.ncolv + wt.nshift * (wt.bp0 + wt.bend)) +
-                                          2.0 * sizeof(zd) * m * wt.nshift);
-        PROF_LAUNCH(h, prof_cls(kProfShift, !lo), bytes, st, window_apply(!lo, wa, st));
+        // segments: [first step, last step, precision]
+        struct Seg { int a, b; bool f64; };
+        std::vector<Seg> seg;
+        if (sw > 0) {
+            seg.push_back({i0 + 1, std::min(sw, i), true});
+            if (i > sw) seg.push_back({sw + 1, i, false});
+        } else {
+            seg.push_back({i0 + 1, i, !lo});
+        }
+        // both segments' pointers are copied from one host array: reserve it
+        // so the first copy's source is not moved by the second segment
+        colptr_host.clear();
+        colptr_host.reserve((size_t)(i - i0) * wmax);
+        size_t tab_off = 0;  // elements (doubles) into the table buffer
+        const int pnew = pcur ^ 1;
+        for (size_t sg = 0; sg < seg.size(); ++sg) {
+            const Seg &g = seg[sg];
+            const bool f64s = g.f64;
+            const size_t esz = f64s ? sizeof(zd) : sizeof(zf);
+            WindowTable wt;
+            memset(&wt, 0, sizeof(wt));
+            wt.nshift = (int)wset.size();
+            wt.bp0 = (sg == 0 && i0 >= 1) ? bw[i0] : 0;
+            wt.m = m;
+            wt.K = g.b - g.a + 1;
+            wt.slot0 = g.a - i0 - 1;
+            const size_t cp0 = colptr_host.size();
+            for (int u = 0; u < wt.K; ++u) {
+                const int step = g.a + u;
+                const int w = bw[step];
+                wt.wb[u] = w;
+                void *base = f64s ? ring64[v64[step]] : ring32[v32[step]];
+                for (int c = 0; c < w; ++c) colptr_host.push_back((char *)base + (size_t)c * n * esz);
+            }
+            wt.ncolv = (int)(colptr_host.size() - cp0);
+            wt.bend = bend;
+            wt.pairs_p = (wt.bp0 + 1) / 2;
+            wt.npairs = wt.pairs_p + (wt.ncolv + 1) / 2;
+            wt.nmt = (m + wt.bend + 7) / 8;
+            void **dcol = (void **)h->colptr.p + cp0;
+            if (wt.ncolv > 0)
+                HIPCHK(hipMemcpyAsync(dcol, colptr_host.data() + cp0, (size_t)wt.ncolv * sizeof(void *),
+                                      hipMemcpyHostToDevice, st));
+            double *tab = (double *)h->wtable.p + tab_off;
+            tab_off += (size_t)wt.nshift * wt.npairs * wt.nmt * 64;
+            PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_table(WC, wt, dshift, dpm, f64s, tab, st));
+            WinArgs wa;
+            memset(&wa, 0, sizeof(wa));
+            wa.nrows = n;
+            wa.ncolv = wt.ncolv;
+            wa.colptr = (const void *const *)dcol;
+            wa.bp0 = wt.bp0;
+            // P_{j,i0} is in the precision the window started in
+            wa.Pold = f64s ? h->P[pcur].p : h->P32[pcur].p;
+            wa.Pnew = f64s ? h->P[pnew].p : h->P32[pnew].p;
+            wa.bend = wt.bend;
+            wa.pstride = n * wmax;
+            wa.m = m;
+            wa.X = (zd *)h->X.p;
+            wa.xstride = n * m;
+            wa.table = tab;
+            wa.npairs = wt.npairs;
+            wa.pairs_p = wt.pairs_p;
+            wa.nmt = wt.nmt;
+            wa.shifts = dshift;
+            wa.nshift = wt.nshift;
+            wa.xmask = WC.Wmask;
+            wa.pmask = dpm;
+            wa.xinit = (xfresh && sg == 0) ? 1 : 0;
+            const double bytes = (double)n * ((double)esz * (wt.ncolv + wt.nshift * (wt.bp0 + wt.bend)) +
+                                              (wa.xinit ? 1.0 : 2.0) * sizeof(zd) * m * wt.nshift);
+            PROF_LAUNCH(h, prof_cls(kProfShift, f64s), bytes, st, window_apply(f64s, wa, st));
+            if (!f64s) stt.reliable_updates += 1;
+        }
+        xfresh = false;
+        if (sw > 0 && bend > 0)
+            // the iteration goes on in FP32: P_{j,i} = FP64 part (+ FP32 part), kept in FP32
+            for (int j : act)
+                CHK(copy(h, bend, cm((zd *)h->P[pnew].p + (int64_t)j * n * wmax, n, true),
+                         cm((zf *)h->P32[pnew].p + (int64_t)j * n * wmax, n, false), seg.size() == 2, st));
         // the host buffers are rewritten only after the next step's report,
         // which waits for the stream
-        pcur ^= 1;
+        pcur = pnew;
         release(i);
         wset = act;
-        if (lo) stt.reliable_updates += 1;
         return DSBCG_OK;
     };
     active_list();
@@ -732,40 +776,46 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
 
     for (int i = 1; !done && i <= steps; ++i) {
         if (form32 && !lo && max_active_est() <= switch_at) {
-            // continue the same recurrences with FP32 vectors (the window
-            // ended with the previous step): V_{i-1}, V_i and P_{j,i-1} move
-            // to the FP32 ring and buffers
-            freelist.clear();
-            for (int k = nring32 - 1; k >= 2; --k) freelist.push_back(k);
-            CHK(copy(h, b, cm(ring64[vidx[i]], n, true), cm(ring32[1], n, false), false, st));
-            vidx[i] = 1;
+            // continue the same recurrences with FP32 vectors: V_{i-1} and V_i
+            // get FP32 copies.  An open window keeps its FP64 blocks and goes
+            // on (its P_{j,i0} stays FP64); a window that ended with the
+            // previous step hands over P_{j,i-1} in FP32.
+            free32.clear();
+            for (int k = nring32 - 1; k >= 2; --k) free32.push_back(k);
+            CHK(copy(h, b, cm(ring64[v64[i]], n, true), cm(ring32[1], n, false), false, st));
+            v32[i] = 1;
             if (i > 1) {
-                CHK(copy(h, bp, cm(ring64[vidx[i - 1]], n, true), cm(ring32[0], n, false), false, st));
-                vidx[i - 1] = 0;
+                CHK(copy(h, bp, cm(ring64[v64[i - 1]], n, true), cm(ring32[0], n, false), false, st));
+                v32[i - 1] = 0;
+            } else {
+                free32.push_back(0);
+            }
+            if (i0 < i - 1) {
+                sw = i;
+            } else if (i > 1) {
                 for (int j : act)
                     CHK(copy(h, bp, cm((zd *)h->P[pcur].p + (int64_t)j * n * wmax, n, true),
                              cm((zf *)h->P32[pcur].p + (int64_t)j * n * wmax, n, false), false, st));
-            } else {
-                freelist.push_back(0);
             }
             lo = true;
             stt.switch_iter = i;
         }
         const bool f64 = !lo;
-        const int K = lo ? K32 : K64;
         Ts ts{h, f64, st, n};
         iters = i;
         stt.mvms += b;
-        if ((int)vidx.size() < i + 2) {
-            vidx.resize(i + 2, -1);
+        if ((int)v64.size() < i + 2) {
+            v64.resize(i + 2, -1);
+            v32.resize(i + 2, -1);
             bw.resize(i + 2, 0);
         }
-        if (freelist.empty()) {
+        std::vector<int> &fl = lo ? free32 : free64;
+        if (fl.empty()) {
             status = fail(DSBCG_ERR_HIP, "internal: Lanczos block ring exhausted");
             break;
         }
-        vidx[i + 1] = freelist.back();
-        freelist.pop_back();
+        (lo ? v32 : v64)[i + 1] = fl.back();
+        fl.pop_back();
         void *Vc = ring(i), *Vp = i > 1 ? ring(i - 1) : ring(i), *Vn = ring(i + 1);
         void *T = lo ? h->T32.p : h->T.p, *Wb = lo ? h->W32.p : h->W.p;
         const void *Ul = lo ? h->Ul32.p : h->Ul64.p;
@@ -856,8 +906,9 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         active_list();
         if (bnew == 0) done = true;
         if (o.fixed_iters <= 0 && act.empty()) done = true;
-        const bool switch_next = form32 && !lo && !done && max_active_est() <= switch_at;
-        if (i - i0 >= K || done || i == steps || switch_next) CHK(apply_window(i, !done && i < steps));
+        // the window ends when a ring is full, at the slot limit, or at the end
+        const bool full = lo ? (i - std::max(i0, sw > 0 ? sw - 1 : i0) >= K32) : (i - i0 >= K64);
+        if (full || i - i0 >= kwin || done || i == steps) CHK(apply_window(i, !done && i < steps));
         bp = b;
         b = bnew;
         bw[i + 1] = bnew;
