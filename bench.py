@@ -51,6 +51,9 @@ def parse():
     p.add_argument("--grad", action="store_true", default=True,
                    help="also time forward + backward of the differentiable solve (16^4)")
     p.add_argument("--no-grad", dest="grad", action="store_false")
+    p.add_argument("--rational", action="store_true", default=True,
+                   help="also time the FP64 partial-fraction form on the same workload")
+    p.add_argument("--no-rational", dest="rational", action="store_false")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run a plain 1 GiB device copy (the reference kernel for "
                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -254,6 +257,44 @@ def run_form(dsb, h, dU, dB, w, prec, steps, warmup):
     }, X
 
 
+def rational_rate(dsb, h, dU, dB, w, steps, warmup):
+    """The partial-fraction form Y = c0 B + sum_j c_j (sigma_j + A)^{-1} B in FP64
+    on the same workload (the per-shift solutions are never formed), with
+    seeded coefficients c_j in [0.1, 1] and c0 = 1."""
+    import numpy as np
+    import torch
+    from paper_1205_0359_amd import inputs
+    coef = inputs.rng_for(w.wid, 4).uniform(0.1, 1.0, len(w.shifts))
+    Y = None
+    for k in range(warmup):
+        log(f"[bench] warmup partial-fraction fp64 {k + 1}/{warmup}")
+        Y, st = dsb.dsbcg_solve_rational(h, dU, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y)
+    torch.cuda.synchronize()
+    dsb.dsbcg_profile_enable(h, True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        Y, st = dsb.dsbcg_solve_rational(h, dU, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y)
+        log(f"[bench] partial-fraction fp64 step {k + 1}/{steps}: {st['block_iters']} block steps, "
+            f"max est relres {st['est_relres'].max():.2e}")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    prof = dsb.dsbcg_profile_read(h)
+    dsb.dsbcg_profile_enable(h, False)
+    del Y
+    torch.cuda.empty_cache()
+    return {
+        "form": "fp64 partial fraction (X_j not formed; estimates only)",
+        "coefficients": "c_j ~ U[0.1, 1] (seeded), c0 = 1",
+        "systems_per_s": w.m * len(w.shifts) * steps / sec,
+        "ms_per_solve": 1e3 * sec / steps,
+        "block_iters": st["block_iters"],
+        "max_est_relres": float(st["est_relres"].max()),
+        "kernels": {k: {"ms_per_solve": v["ms"] / steps, "launches_per_solve": v["launches"] / steps,
+                        "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0}
+                    for k, v in prof.items() if v["ms"] > 0},
+    }
+
+
 def stencil_rate(dsb, h, dU, w, b, prec, calls):
     """D^H D on b columns through dsbcg_apply_A; HIP-event kernel timing."""
     import torch
@@ -397,6 +438,10 @@ def main():
             results[prec] = {"unavailable": str(e)}
     head = results[args.precision]
 
+    rational = None
+    if args.rational:
+        rational = rational_rate(dsb, h, dU, dB, w, args.steps, args.warmup)
+
     # the stencil on the solve's block width
     stencil = stencil_rate(dsb, h, dU, w, head["rank0"], args.precision, args.stencil_calls)
 
@@ -444,6 +489,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "grad": grad,
+        "partial_fraction": rational,
         "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()},
     }
     print(json.dumps(line), flush=True)

@@ -151,6 +151,30 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
                 const double *sigma, int32_t s, double tol, const dsbcg_opts *opts,
                 void *X, dsbcg_stats *stats, dsbcg_stream stream);
 
+/* Partial-fraction form (Sec. 1: the rational approximation of a matrix power
+ * that the rational hybrid Monte Carlo algorithm needs, written as a partial
+ * fraction expansion, is what gives rise to the shifted systems):
+ *
+ *     Y = c0 B + sum_j coef_j (sigma_j I + A)^{-1} B
+ *
+ * coef: HOST array of s real coefficients; c0 a real scalar; Y: device output
+ * [V][4][3][m], fully written, must not alias B.  Other arguments as
+ * dsbcg_solve; every system (l, j) is iterated to the same tol.
+ *   DSBCG_FP64: the per-shift X_j are never formed.  The window contraction
+ *     accumulates sum_j coef_j X_j directly into Y (one output block instead
+ *     of s), and no s*V*12*m workspace is held.  Convergence is judged by the
+ *     estimated residuals of the method (Sec. 3): stats->true_relres is filled
+ *     with -1 (not formed) and main_relres_max is -1.
+ *   DSBCG_FP32_RELIABLE: the checked solve of dsbcg_solve (FP64 true
+ *     residuals, FP64 re-solve of shifts that miss tol) into a workspace of
+ *     s*V*12*m complex128, then the sum.
+ * A frozen or converged system contributes its final iterate.  Returns with
+ * `stream` synchronised; errors as dsbcg_solve (ERR_NOT_CONVERGED leaves the
+ * sum of the current iterates in Y). */
+int dsbcg_solve_rational(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
+                         const double *sigma, const double *coef, int32_t s, double c0, double tol,
+                         const dsbcg_opts *opts, void *Y, dsbcg_stats *stats, dsbcg_stream stream);
+
 /* Solve (sigma_j I + A) X_j = B_j for j = 0..s-1, one right-hand-side block
  * per shift: B is [s][V][4][3][m] (device).  The blocks are stacked and
  * deflated together (deflated QR of [B_0 | ... | B_{s-1}]) and ONE DSBlockCG

@@ -14,11 +14,11 @@ Every function is pinned by CPU tests against facts fixed outside the oracle
 """
 from .wilson import (apply_D, apply_A, apply_D_sites, apply_A_sites, neighbors, gamma,
                      link_grad, max_threads, load)
-from .dsbcg import (dsbcg, deflated_qr, true_relres, NotHPD, Result)
+from .dsbcg import (dsbcg, deflated_qr, true_relres, partial_fraction, NotHPD, Result)
 
 __all__ = ["apply_D", "apply_A", "apply_D_sites", "apply_A_sites", "neighbors", "gamma",
            "link_grad", "max_threads", "load", "dsbcg", "deflated_qr", "true_relres",
-           "NotHPD", "Result"]
+           "partial_fraction", "NotHPD", "Result"]
 from .grad import adjoint_gradients  # noqa: E402
 
 __all__.append("adjoint_gradients")

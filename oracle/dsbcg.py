@@ -235,3 +235,18 @@ def true_relres(apply_A, B: np.ndarray, sigma, X: np.ndarray) -> np.ndarray:
         R = B - sigma[j] * X[j] - apply_A(X[j])
         out[:, j] = np.linalg.norm(R, axis=0) / safe
     return out
+
+
+def partial_fraction(B: np.ndarray, X: np.ndarray, coef, c0: float) -> np.ndarray:
+    """Y = c0 B + sum_j coef_j X_j with X_j = (sigma_j I + A)^{-1} B.
+
+    The partial-fraction form of a rational function of A applied to B (Sec. 1:
+    the rational approximation that the rational hybrid Monte Carlo algorithm
+    uses for a power of A, written as a partial fraction expansion, is the
+    source of the shifted systems).  B: (n, m); X: (s, n, m).
+    """
+    Y = c0 * np.asarray(B, dtype=np.complex128)
+    for j, c in enumerate(coef):
+        Y = Y + c * X[j]
+    return Y
+

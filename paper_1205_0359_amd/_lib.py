@@ -93,6 +93,10 @@ def load():
     lib.dsbcg_solve.restype = ctypes.c_int
     lib.dsbcg_solve_multi.argtypes = lib.dsbcg_solve.argtypes
     lib.dsbcg_solve_multi.restype = ctypes.c_int
+    lib.dsbcg_solve_rational.argtypes = [P, P, dbl, P, i32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double), i32, dbl, dbl,
+                                         ctypes.POINTER(dsbcg_opts), P, ctypes.POINTER(dsbcg_stats), P]
+    lib.dsbcg_solve_rational.restype = ctypes.c_int
     lib.dsbcg_grad.argtypes = [P, P, dbl, ctypes.POINTER(ctypes.c_double), i32, i32, P, P, P, P,
                                ctypes.POINTER(ctypes.c_double), P]
     lib.dsbcg_grad.restype = ctypes.c_int
@@ -233,6 +237,27 @@ def default_opts(**kw) -> dsbcg_opts:
     return o
 
 
+def _new_stats(s, m):
+    import numpy as np
+    est = np.zeros(s * m)
+    true = np.zeros(s * m)
+    st = dsbcg_stats()
+    st.est_relres = est.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st.true_relres = true.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return st, est, true
+
+
+def _stats_dict(code, st, est, true, s, m):
+    return {
+        "status": STATUS_NAMES.get(code, code),
+        "block_iters": st.block_iters, "rank0": st.rank0, "deflations": st.deflations,
+        "reliable_updates": st.reliable_updates, "refine_iters": st.refine_iters,
+        "final_width": st.final_width, "switch_iter": st.switch_iter,
+        "main_relres_max": st.main_relres_max, "mvms": int(st.mvms),
+        "est_relres": est.reshape(s, m).T.copy(), "true_relres": true.reshape(s, m).T.copy(),
+    }
+
+
 def _solve(fn, h: Handle, U, kappa, B, sigma, tol, X, stream, raise_not_converged, multi, opts):
     import numpy as np
     torch = _torch()
@@ -245,21 +270,10 @@ def _solve(fn, h: Handle, U, kappa, B, sigma, tol, X, stream, raise_not_converge
         X = torch.empty((s, h.V, 4, 3, m), dtype=torch.complex128, device=B.device)
     pX = _dev(X, "X", (s, h.V, 4, 3, m))
     o = default_opts(**opts)
-    est = np.zeros(s * m)
-    true = np.zeros(s * m)
-    st = dsbcg_stats()
-    st.est_relres = est.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    st.true_relres = true.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st, est, true = _new_stats(s, m)
     code = fn(h.ptr, pU, float(kappa), pB, int(m), sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
               int(s), float(tol), ctypes.byref(o), pX, ctypes.byref(st), _stream(stream))
-    stats = {
-        "status": STATUS_NAMES.get(code, code),
-        "block_iters": st.block_iters, "rank0": st.rank0, "deflations": st.deflations,
-        "reliable_updates": st.reliable_updates, "refine_iters": st.refine_iters,
-        "final_width": st.final_width, "switch_iter": st.switch_iter,
-        "main_relres_max": st.main_relres_max, "mvms": int(st.mvms),
-        "est_relres": est.reshape(s, m).T.copy(), "true_relres": true.reshape(s, m).T.copy(),
-    }
+    stats = _stats_dict(code, st, est, true, s, m)
     if code == DSBCG_ERR_NOT_CONVERGED and not raise_not_converged:
         return X, stats
     _check(code)
@@ -283,6 +297,40 @@ def dsbcg_solve_multi(h: Handle, U, kappa: float, B, sigma, tol: float, X=None, 
     """Solve (sigma_j I + A) X_j = B_j with one block per shift, B of shape (s, V, 4, 3, m)."""
     return _solve(load().dsbcg_solve_multi, h, U, kappa, B, sigma, tol, X, stream,
                   raise_not_converged, True, opts)
+
+
+def dsbcg_solve_rational(h: Handle, U, kappa: float, B, sigma, coef, c0: float, tol: float, Y=None,
+                         stream=None, raise_not_converged: bool = True, **opts):
+    """Partial-fraction sum Y = c0 B + sum_j coef_j (sigma_j I + A)^{-1} B.
+
+    Returns (Y, stats) with Y complex128 (V, 4, 3, m) on the device.  In the
+    FP64 form the per-shift solutions are never formed and stats
+    "true_relres" holds -1 (not computed).
+    """
+    import numpy as np
+    torch = _torch()
+    m = B.shape[-1]
+    sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(-1))
+    cf = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).reshape(-1))
+    s = len(sig)
+    if len(cf) != s:
+        raise ValueError("coef and sigma differ in length")
+    pU = _dev(U, "U", (h.V, 4, 3, 3))
+    pB = _dev(B, "B", (h.V, 4, 3, m))
+    if Y is None:
+        Y = torch.empty((h.V, 4, 3, m), dtype=torch.complex128, device=B.device)
+    pY = _dev(Y, "Y", (h.V, 4, 3, m))
+    o = default_opts(**opts)
+    st, est, true = _new_stats(s, m)
+    code = load().dsbcg_solve_rational(
+        h.ptr, pU, float(kappa), pB, int(m), sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        cf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(s), float(c0), float(tol),
+        ctypes.byref(o), pY, ctypes.byref(st), _stream(stream))
+    stats = _stats_dict(code, st, est, true, s, m)
+    if code == DSBCG_ERR_NOT_CONVERGED and not raise_not_converged:
+        return Y, stats
+    _check(code)
+    return Y, stats
 
 
 def dsbcg_grad(h: Handle, U, kappa: float, sigma, X, Lam, want_U=True, want_B=True,

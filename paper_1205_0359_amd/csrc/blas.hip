@@ -638,7 +638,9 @@ __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
 }
 
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
-    if (a.nshift < 1 || a.nshift > 16 || a.m < 1 || a.m > 16 || a.bend < 0 || a.bend > 16 ||
+    // m = 0: only P_{j,end} is formed (partial-fraction form)
+    if (a.nshift < 1 || a.nshift > 16 || a.m < 0 || a.m > 16 || a.bend < 0 || a.bend > 16 ||
+        a.m + a.bend < 1 || (a.m == 0 && a.xinit) ||
         a.bp0 < 0 || a.bp0 > 16 || a.ncolv < 0 || a.nmt < 1 || a.nmt > 4 ||
         a.nmt * 8 < a.m + a.bend || a.pairs_p != (a.bp0 + 1) / 2 ||
         a.npairs != a.pairs_p + (a.ncolv + 1) / 2)
@@ -661,6 +663,108 @@ hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
         else DSBCG_WIN(float, 4, 4);
     }
 #undef DSBCG_WIN
+    return hipGetLastError();
+}
+
+// Partial-fraction window update (see RatArgs).  Lane layout as in
+// window_kernel: lane = row + 16 k, k = 2 (input column of the pair) +
+// (real / imaginary part); the next pair's inputs and coefficients are
+// loaded while the current pair multiplies.
+template <typename R, int NMT, int TILES>
+__global__ __launch_bounds__(256) void rational_window_kernel(RatArgs a) {
+    typedef typename Mfma<R>::v4 v4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t n = a.nrows;
+    const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 16 * TILES;
+    if (r0 >= n) return;  // no barriers below: a wave past the end just leaves
+    const int rl = lane & 15, part = (lane >> 4) & 1, sel = lane >> 5;
+    const R *tab = (const R *)a.table + lane;
+    const int npp = a.nshift * a.pairs_p;  // pairs from the P_{j,i0}
+    const int npairs = a.npairs;
+
+    // input (pair, tile) of this lane: P_{j,i0} pairs first, then window columns
+    auto load = [&](int pair, R d[TILES]) {
+        const R *src = nullptr;
+        int64_t off = 0;
+        if (pair < npp) {
+            const int js = pair / a.pairs_p, p = 2 * (pair - js * a.pairs_p) + sel;
+            if (p < a.bp0) {
+                src = (const R *)a.Pold + (size_t)2 * a.shifts[js] * a.pstride;
+                off = 2 * (int64_t)p * n;
+            }
+        } else {
+            const int col = 2 * (pair - npp) + sel;
+            if (col < a.ncolv) src = (const R *)a.colptr[col];
+        }
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) {
+            const int64_t row = r0 + t * 16 + rl;
+            d[t] = (src && row < n) ? src[off + 2 * row + part] : (R)0;
+        }
+    };
+
+    v4 acc[TILES][NMT];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) acc[t][mt] = v4{0, 0, 0, 0};
+    R d[TILES], cf[NMT];
+    load(0, d);
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt) cf[mt] = tab[mt * 64];
+    for (int pr = 0; pr < npairs; ++pr) {
+        const int pn = pr + 1 < npairs ? pr + 1 : pr;
+        R dn[TILES], cn[NMT];
+        load(pn, dn);
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) cn[mt] = tab[((size_t)pn * NMT + mt) * 64];
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+            for (int t = 0; t < TILES; ++t) acc[t][mt] = Mfma<R>::mac(cf[mt], d[t], acc[t][mt]);
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) d[t] = dn[t];
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) cf[mt] = cn[mt];
+    }
+    // lane holds rows r0 + 16 t + rl, complex outputs q = 8 mt + 2 g and q + 1
+    const int g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        const int64_t row = r0 + t * 16 + rl;
+        if (row >= n) continue;
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = mt * 8 + 2 * g + h;
+                if (q < a.m) {
+                    zd *y = a.Y + (int64_t)q * n + row;
+                    *y = mk<double>(y->x + (double)acc[t][mt][2 * h], y->y + (double)acc[t][mt][2 * h + 1]);
+                }
+            }
+    }
+}
+
+hipError_t rational_window_apply(bool fp64, const RatArgs &a, hipStream_t st) {
+    if (a.nshift < 1 || a.nshift > 16 || a.m < 1 || a.m > 16 || a.bp0 < 0 || a.bp0 > 16 ||
+        a.ncolv < 0 || a.pairs_p != (a.bp0 + 1) / 2 || a.nmt != (a.m + 7) / 8 ||
+        a.npairs != a.nshift * a.pairs_p + (a.ncolv + 1) / 2 || !a.Y || !a.table)
+        return hipErrorInvalidValue;
+    if (a.nrows <= 0 || a.npairs == 0) return hipSuccess;
+    constexpr int kWaves = 4;
+    const int tiles = fp64 ? 4 : 8;
+    const int64_t rows_per_wg = (int64_t)kWaves * 16 * tiles;
+    const dim3 grid((unsigned)((a.nrows + rows_per_wg - 1) / rows_per_wg)), block(64 * kWaves);
+#define DSBCG_RW(R, M, T) hipLaunchKernelGGL((rational_window_kernel<R, M, T>), grid, block, 0, st, a)
+    if (fp64) {
+        if (a.nmt == 1) DSBCG_RW(double, 1, 4);
+        else DSBCG_RW(double, 2, 4);
+    } else {
+        if (a.nmt == 1) DSBCG_RW(float, 1, 8);
+        else DSBCG_RW(float, 2, 8);
+    }
+#undef DSBCG_RW
     return hipGetLastError();
 }
 

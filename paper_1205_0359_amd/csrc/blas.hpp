@@ -83,6 +83,30 @@ struct WinArgs {
 };
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st);
 
+// Window update of the partial-fraction sum Y = c0 B + sum_j c_j X_j, the
+// per-shift iterates never being formed:
+//   Y += sum_j c_j (P_{j,i0} Fp_j + sum_u V_u F_{j,u})
+// as ONE matrix-core contraction of [P_{j_1,i0} | ... | P_{j_s,i0} | V_window]
+// with the combined table of small_rational_table.  No input is shared
+// between waves, so each wave owns its rows and streams its inputs.
+struct RatArgs {
+    int64_t nrows;
+    int ncolv;                  // window columns
+    const void *const *colptr;  // device array [ncolv]
+    int bp0;                    // width of each P_{j,i0} (0: no P term)
+    const void *Pold;           // P buffer, shift j at j * pstride
+    int64_t pstride;
+    const int32_t *shifts;      // device [nshift]
+    int nshift;                 // <= 16
+    int m;                      // columns of Y
+    zd *Y;                      // [m][nrows] FP64, accumulated
+    const void *table;          // [npairs][nmt][64] in the data precision
+    int pairs_p;                // ceil(bp0 / 2) pairs per shift
+    int npairs;                 // nshift * pairs_p + ceil(ncolv / 2)
+    int nmt;                    // ceil(m / 8)
+};
+hipError_t rational_window_apply(bool fp64, const RatArgs &a, hipStream_t st);
+
 // Checks a field for NaN/Inf: sets *flag (device int) to 1 if any is found.
 hipError_t find_nonfinite(const double *data, int64_t count, int32_t *flag, hipStream_t st);
 

@@ -379,6 +379,75 @@ hipError_t small_window_table(const WinCoef wc, const WindowTable &wt, const int
     return hipGetLastError();
 }
 
+// One block of 64 lanes per (input pair, output tile) of the combined table.
+template <typename R>
+__global__ __launch_bounds__(64) void rational_table_kernel(WinCoef wc, WindowTable wt,
+                                                            const int32_t *__restrict__ shifts,
+                                                            const double *__restrict__ coef, R *table) {
+    const int pair = blockIdx.x, mt = blockIdx.y;
+    const int lane = threadIdx.x;
+    const int i = lane & 15, k = lane >> 4;
+    // output real i of the tile: complex output and part, ordered as in
+    // window_table_kernel for the same instruction
+    int ql, po;
+    if (sizeof(R) == 8) {
+        ql = 2 * (i & 3) + ((i >> 2) >> 1);
+        po = (i >> 2) & 1;
+    } else {
+        ql = i >> 1;
+        po = i & 1;
+    }
+    const int q = mt * 8 + ql;
+    const int pin = k & 1;
+    zd c = mk<double>(0, 0);
+    if (q < wt.m) {
+        const int npp = wt.nshift * wt.pairs_p;
+        if (pair < npp) {
+            const int js = pair / wt.pairs_p;
+            const int p = 2 * (pair - js * wt.pairs_p) + (k >> 1);
+            const int j = shifts[js];
+            if (p < wt.bp0) {
+                const zd f = wc.Wfp[j * 256 + p * 16 + q];
+                c = mk<double>(coef[j] * f.x, coef[j] * f.y);
+            }
+        } else {
+            const int col = 2 * (pair - npp) + (k >> 1);
+            if (col < wt.ncolv) {
+                int u = 0, c0 = 0;
+                while (u < wt.K - 1 && col >= c0 + wt.wb[u]) c0 += wt.wb[u++];
+                const int slot = wt.slot0 + u;
+                for (int js = 0; js < wt.nshift; ++js) {
+                    const int j = shifts[js];
+                    if (slot < wc.Wcount[j]) {
+                        const zd f = wc.Wf[((size_t)j * kWinMax + slot) * 256 + (col - c0) * 16 + q];
+                        c.x += coef[j] * f.x;
+                        c.y += coef[j] * f.y;
+                    }
+                }
+            }
+        }
+    }
+    const double v = (po == 0) ? (pin == 0 ? c.x : -c.y) : (pin == 0 ? c.y : c.x);
+    table[((size_t)pair * gridDim.y + mt) * 64 + lane] = (R)v;
+}
+
+hipError_t small_rational_table(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
+                                const double *coef, bool fp64, void *table, hipStream_t stream) {
+    const int npairs = wt.nshift * wt.pairs_p + (wt.ncolv + 1) / 2;
+    if (wt.nshift <= 0 || npairs <= 0) return hipSuccess;
+    if (wt.K < 1 || wt.slot0 < 0 || wt.slot0 + wt.K > kWinMax || wt.m < 1 || wt.m > 16 ||
+        wt.nshift > 16 || wt.pairs_p != (wt.bp0 + 1) / 2)
+        return hipErrorInvalidValue;
+    const dim3 grid(npairs, (wt.m + 7) / 8);
+    if (fp64)
+        hipLaunchKernelGGL(rational_table_kernel<double>, grid, dim3(64), 0, stream, wc, wt, shifts, coef,
+                           (double *)table);
+    else
+        hipLaunchKernelGGL(rational_table_kernel<float>, grid, dim3(64), 0, stream, wc, wt, shifts, coef,
+                           (float *)table);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // alpha_i = herm(raw Gram); coef[1] = -alpha_i for the block combination.
 // ---------------------------------------------------------------------------

@@ -101,6 +101,15 @@ struct WindowTable {
 hipError_t small_window_table(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
                               const int32_t *pmask, bool fp64, void *table, hipStream_t stream);
 
+// Combined table of the partial-fraction window update (rational_window_apply):
+// table[pair][mt][lane] in the same lane order, for the outputs 0..m-1 of Y,
+// with input pairs [P_{j,i0} of each window shift (ceil(bp0 / 2) pairs each,
+// in the order of `shifts`) | window columns].  Entries: c_j Fp_j for the
+// P_{j,i0} inputs and sum_j c_j F_{j,u} for the window columns (coef: device
+// [kS] real coefficients by shift index).  wt.bend is ignored.
+hipError_t small_rational_table(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
+                                const double *coef, bool fp64, void *table, hipStream_t stream);
+
 // First pass of the deflated CholQR of W: Cholesky of G = W^H W with column
 // dropping (remainder <= tau_W * ||T||_est); also updates ||T||_est from
 // alpha_i and beta_i.

@@ -103,6 +103,7 @@ struct dsbcg_ctx {
     DevBuf Bint, Q, wbuf;                                // deflated QR of B
     DevBuf R0, R1, R2, R3, Rres, Xref;                   // true residuals, refinement
     DevBuf Xin, Yout;                                    // dsbcg_apply_* conversions
+    DevBuf Ycm, ycoef, Xrat;                             // partial-fraction form
     DevBuf partials, red, list, wlist, st, rep;
     std::vector<DevBuf> Vring, Vring32;                  // window rings of Lanczos blocks
     StepReport *rep_host = nullptr;
@@ -113,7 +114,7 @@ struct dsbcg_ctx {
         DevBuf *all[] = {&Ul64, &Ul32, &V0,  &T,   &W,    &P[0], &P[1], &X,
                          &T32, &W32, &P32[0], &P32[1], &wcoef, &wtable, &colptr,
                          &Bint, &Q,    &wbuf, &R0,   &R1,   &R2,  &R3,   &Rres, &Xref, &Xin,
-                         &Yout, &partials, &red, &list, &wlist, &st, &rep};
+                         &Yout, &Ycm, &ycoef, &Xrat, &partials, &red, &list, &wlist, &st, &rep};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (auto &b : Vring)
@@ -340,6 +341,14 @@ struct SolveStats {
     double est[kS * kS] = {};
 };
 
+// Partial-fraction output of solve_core: Y = c0 B + sum_j c_j X_j is
+// accumulated window by window and the X_j are never formed.
+struct RatSpec {
+    const double *coef;  // host [s]
+    double c0;
+    void *Yapi;          // device [V][4][3][m] FP64
+};
+
 // Initial deflated QR of the right-hand sides (M <= 256 column-major FP64
 // columns in h->Bint): classical Gram-Schmidt applied twice, column by
 // column, in column order.  Column l is dropped when its remainder is
@@ -523,17 +532,20 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
 // links in h->Ul32 for the FP32 form).
 int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m,
                const double *sigma, int s, double tol, const dsbcg_opts &o, double switch_at,
-               void *Xapi, SolveStats &stt, hipStream_t st) {
+               void *Xapi, SolveStats &stt, hipStream_t st, const RatSpec *rat) {
     const int64_t V = h->g.V, n = 12 * V;
     const bool form32 = o.precision == DSBCG_FP32_RELIABLE;
     const int M = bstride ? m * s : m;  // stacked right-hand-side columns
+    const bool rmode = rat != nullptr;  // partial-fraction output, no X_j
+    if (rmode && (form32 || bstride != 0))
+        return fail(DSBCG_ERR_ARG, "internal: the partial-fraction form runs in FP64 on one B");
 
     CHK(ensure_common(h));
     CHK(ensure(h->Bint, (size_t)n * M * sizeof(zd)));
     CHK(ensure(h->Q, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
     CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
     CHK(ensure(h->V0, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
-    CHK(ensure(h->X, (size_t)n * m * s * sizeof(zd)));
+    if (!rmode) CHK(ensure(h->X, (size_t)n * m * s * sizeof(zd)));
 
     SmallState *S = stp(h);
     StepReport *rep = repp(h);
@@ -541,6 +553,16 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     for (int j = 0; j < (bstride ? s : 1); ++j)
         CHK(copy(h, m, api((const zd *)B + (int64_t)j * bstride, m),
                  cm((zd *)h->Bint.p + (int64_t)j * m * n, n, true), false, st));
+    if (rmode) {
+        // Y = c0 B; the windows add sum_j c_j X_j
+        CHK(ensure(h->Ycm, (size_t)n * m * sizeof(zd)));
+        CHK(ensure(h->ycoef, kS * sizeof(double)));
+        std::vector<double> cf(kS, 0.0);
+        for (int j = 0; j < s; ++j) cf[j] = rat->coef[j];
+        HIPCHK(hipMemcpyAsync(h->ycoef.p, cf.data(), kS * sizeof(double), hipMemcpyHostToDevice, st));
+        PROF_LAUNCH(h, kProfConvert, copy_bytes(V, m, 16, 16, false), st,
+                    copy_field(V, m, cm(h->Bint.p, n, true), cm(h->Ycm.p, n, true), false, rat->c0, st));
+    }
 
     int m1 = 0;
     CHK(initial_qr(h, M, o.tau_B, st, &m1));
@@ -675,7 +697,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         for (int j = 0; j < s; ++j) wl[16 + j] = pm[j];
         HIPCHK(hipMemcpyAsync(h->wlist.p, wl, 64 * sizeof(int32_t), hipMemcpyHostToDevice, st));
         const int32_t *dshift = (const int32_t *)h->wlist.p, *dpm = dshift + 16;
-        if (xfresh) {
+        if (xfresh && !rmode) {
             // the first window writes X_j of its shifts; the others start from zero
             std::vector<char> in_w(s, 0);
             for (int j : wset) in_w[j] = 1;
@@ -726,6 +748,64 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             if (wt.ncolv > 0)
                 HIPCHK(hipMemcpyAsync(dcol, colptr_host.data() + cp0, (size_t)wt.ncolv * sizeof(void *),
                                       hipMemcpyHostToDevice, st));
+            if (rmode) {
+                // P_{j,end} of the shifts going on, then Y += sum_j c_j (increment of X_j)
+                if (bend > 0) {
+                    WindowTable wp = wt;
+                    wp.m = 0;
+                    wp.nmt = (bend + 7) / 8;
+                    double *tab = (double *)h->wtable.p + tab_off;
+                    tab_off += (size_t)wp.nshift * wp.npairs * wp.nmt * 64;
+                    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_table(WC, wp, dshift, dpm, true, tab, st));
+                    WinArgs wa;
+                    memset(&wa, 0, sizeof(wa));
+                    wa.nrows = n;
+                    wa.ncolv = wp.ncolv;
+                    wa.colptr = (const void *const *)dcol;
+                    wa.bp0 = wp.bp0;
+                    wa.Pold = h->P[pcur].p;
+                    wa.Pnew = h->P[pnew].p;
+                    wa.bend = bend;
+                    wa.pstride = n * wmax;
+                    wa.m = 0;
+                    wa.X = (zd *)h->Ycm.p;  // not written with m = 0
+                    wa.xstride = 0;
+                    wa.table = tab;
+                    wa.npairs = wp.npairs;
+                    wa.pairs_p = wp.pairs_p;
+                    wa.nmt = wp.nmt;
+                    wa.shifts = dshift;
+                    wa.nshift = wp.nshift;
+                    wa.xmask = WC.Wmask;
+                    wa.pmask = dpm;
+                    const double bytes =
+                        (double)n * sizeof(zd) * (wp.ncolv + wp.nshift * (wp.bp0 + bend));
+                    PROF_LAUNCH(h, kProfShift, bytes, st, window_apply(true, wa, st));
+                }
+                RatArgs ra;
+                memset(&ra, 0, sizeof(ra));
+                ra.nrows = n;
+                ra.ncolv = wt.ncolv;
+                ra.colptr = (const void *const *)dcol;
+                ra.bp0 = wt.bp0;
+                ra.Pold = h->P[pcur].p;
+                ra.pstride = n * wmax;
+                ra.shifts = dshift;
+                ra.nshift = wt.nshift;
+                ra.m = m;
+                ra.Y = (zd *)h->Ycm.p;
+                ra.pairs_p = wt.pairs_p;
+                ra.npairs = wt.nshift * wt.pairs_p + (wt.ncolv + 1) / 2;
+                ra.nmt = (m + 7) / 8;
+                double *tab = (double *)h->wtable.p + tab_off;
+                tab_off += (size_t)ra.npairs * ra.nmt * 64;
+                ra.table = tab;
+                PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                            small_rational_table(WC, wt, dshift, (const double *)h->ycoef.p, true, tab, st));
+                const double bytes = (double)n * sizeof(zd) * (wt.ncolv + wt.nshift * wt.bp0 + 2.0 * m);
+                PROF_LAUNCH(h, kProfShift, bytes, st, rational_window_apply(true, ra, st));
+                continue;
+            }
             double *tab = (double *)h->wtable.p + tab_off;
             tab_off += (size_t)wt.nshift * wt.npairs * wt.nmt * 64;
             PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_table(WC, wt, dshift, dpm, f64s, tab, st));
@@ -914,15 +994,18 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         bw[i + 1] = bnew;
         stt.final_width = bnew;
     }
-    if (xfresh)  // no window was applied (no step, or nothing to update)
+    if (xfresh && !rmode)  // no window was applied (no step, or nothing to update)
         HIPCHK(hipMemsetAsync(h->X.p, 0, (size_t)n * m * s * sizeof(zd), st));
     stt.block_iters += iters;
     if (status == DSBCG_OK && !done && o.fixed_iters <= 0)
         status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
-    // iterates to the caller's layout
-    for (int j = 0; j < s; ++j)
-        CHK(copy(h, m, cm((zd *)h->X.p + (int64_t)j * n * m, n, true),
-                 api((zd *)Xapi + (int64_t)j * n * m, m), false, st));
+    // iterates (or their partial-fraction sum) to the caller's layout
+    if (rmode)
+        CHK(copy(h, m, cm(h->Ycm.p, n, true), api(rat->Yapi, m), false, st));
+    else
+        for (int j = 0; j < s; ++j)
+            CHK(copy(h, m, cm((zd *)h->X.p + (int64_t)j * n * m, n, true),
+                     api((zd *)Xapi + (int64_t)j * n * m, m), false, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int j = 0; j < s; ++j)
         for (int l = 0; l < m; ++l) stt.est[j * m + l] = h->rep_host->est[j][l];
@@ -1057,9 +1140,10 @@ namespace {
 // Validated solve of (sigma_j I + A) X_j = B_j, B_j = B + j * bstride
 // (bstride = 0: one B for every shift), followed by the FP64 true residuals
 // and, for shifts that miss tol, FP64 re-solves of their residual blocks.
-int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, int64_t bstride,
-                  int32_t m, const double *sigma, int32_t s, double tol, const dsbcg_opts *opts,
-                  void *X, dsbcg_stats *stats, hipStream_t st) {
+// Argument checks shared by the solve entry points; resolves the defaults of
+// the options into *o.
+int solve_args(dsbcg_handle h, const void *U, const void *B, int32_t m, const double *sigma, int32_t s,
+               double tol, double kappa, const void *X, const dsbcg_opts *opts, dsbcg_opts *o) {
     if (!h || !U || !B || !sigma || !X) return fail(DSBCG_ERR_ARG, "NULL argument");
     if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
     if (s < 1 || s > DSBCG_MAX_SHIFTS) return fail(DSBCG_ERR_ARG, "s out of range");
@@ -1067,16 +1151,39 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
     if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
     for (int j = 0; j < s; ++j)
         if (!std::isfinite(sigma[j])) return fail(DSBCG_ERR_ARG, "sigma not finite");
-    dsbcg_opts o;
-    dsbcg_default_opts(&o);
-    if (opts) o = *opts;
-    if (o.precision != DSBCG_FP64 && o.precision != DSBCG_FP32_RELIABLE)
+    dsbcg_default_opts(o);
+    if (opts) *o = *opts;
+    if (o->precision != DSBCG_FP64 && o->precision != DSBCG_FP32_RELIABLE)
         return fail(DSBCG_ERR_ARG, "unknown precision");
-    if (o.window < 0) return fail(DSBCG_ERR_ARG, "window must be >= 0");
-    if (o.tau_B < 0) o.tau_B = 0.1 * tol;
-    if (o.tau_W < 0) o.tau_W = 1e-12;
-    if (o.max_iters < 1) o.max_iters = 1;
-    if (o.switch_at < 0) o.switch_at = std::min(1e-2, 1e5 * tol);
+    if (o->window < 0) return fail(DSBCG_ERR_ARG, "window must be >= 0");
+    if (o->tau_B < 0) o->tau_B = 0.1 * tol;
+    if (o->tau_W < 0) o->tau_W = 1e-12;
+    if (o->max_iters < 1) o->max_iters = 1;
+    if (o->switch_at < 0) o->switch_at = std::min(1e-2, 1e5 * tol);
+    return DSBCG_OK;
+}
+
+void fill_stats(dsbcg_stats *stats, const SolveStats &stt, const double *tr, int s, int m, double main_max) {
+    if (!stats) return;
+    double *est = stats->est_relres, *tru = stats->true_relres;
+    if (est) std::copy(stt.est, stt.est + (size_t)s * m, est);
+    if (tru) std::copy(tr, tr + (size_t)s * m, tru);
+    stats->block_iters = stt.block_iters;
+    stats->rank0 = stt.rank0;
+    stats->deflations = stt.deflations;
+    stats->reliable_updates = stt.reliable_updates;
+    stats->refine_iters = stt.refine_iters;
+    stats->final_width = stt.final_width;
+    stats->switch_iter = stt.switch_iter;
+    stats->main_relres_max = main_max;
+    stats->mvms = stt.mvms;
+}
+
+int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, int64_t bstride,
+                  int32_t m, const double *sigma, int32_t s, double tol, const dsbcg_opts *opts,
+                  void *X, dsbcg_stats *stats, hipStream_t st) {
+    dsbcg_opts o;
+    CHK(solve_args(h, U, B, m, sigma, s, tol, kappa, X, opts, &o));
     const int64_t n = 12 * (int64_t)h->g.V;
 
     CHK(ensure_common(h));
@@ -1086,7 +1193,7 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
 
     SolveStats stt;
     double main_max = 0.0;
-    int status = solve_core(h, kappa, B, bstride, m, sigma, s, tol, o, o.switch_at, X, stt, st);
+    int status = solve_core(h, kappa, B, bstride, m, sigma, s, tol, o, o.switch_at, X, stt, st, nullptr);
     bool fallback = false;
     if (status == DSBCG_ERR_ARG && bstride != 0 && stt.rank0 == 0) {
         // the blocks span more than 16 directions: one block solve per shift
@@ -1096,7 +1203,7 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
         for (int j = 0; j < s && status == DSBCG_OK; ++j) {
             SolveStats one;
             status = solve_core(h, kappa, (const zd *)B + (int64_t)j * bstride, 0, m, &sigma[j], 1,
-                                tol, o, o.switch_at, (zd *)X + (int64_t)j * n * m, one, st);
+                                tol, o, o.switch_at, (zd *)X + (int64_t)j * n * m, one, st, nullptr);
             stt.block_iters += one.block_iters;
             stt.mvms += one.mvms;
             stt.reliable_updates += one.reliable_updates;
@@ -1135,7 +1242,7 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
                 ro.tau_B = 0.1 * tol;
                 SolveStats rs;
                 const double rtol = std::max(0.5 * tol * ratio, 1e-15);
-                int rc = solve_core(h, kappa, h->Rres.p, 0, m, &sigma[j], 1, rtol, ro, 0.0, h->Xref.p, rs, st);
+                int rc = solve_core(h, kappa, h->Rres.p, 0, m, &sigma[j], 1, rtol, ro, 0.0, h->Xref.p, rs, st, nullptr);
                 if (rc != DSBCG_OK && rc != DSBCG_ERR_NOT_CONVERGED) return rc;
                 stt.refine_iters += rs.block_iters;
                 stt.mvms += rs.mvms;
@@ -1150,20 +1257,7 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
             status = fail(DSBCG_ERR_NOT_CONVERGED,
                           "true relative residual " + std::to_string(worst) + " above tol after refinement");
     }
-    if (stats) {
-        double *est = stats->est_relres, *tru = stats->true_relres;
-        if (est) std::copy(stt.est, stt.est + (size_t)s * m, est);
-        if (tru) std::copy(tr.begin(), tr.end(), tru);
-        stats->block_iters = stt.block_iters;
-        stats->rank0 = stt.rank0;
-        stats->deflations = stt.deflations;
-        stats->reliable_updates = stt.reliable_updates;
-        stats->refine_iters = stt.refine_iters;
-        stats->final_width = stt.final_width;
-        stats->switch_iter = stt.switch_iter;
-        stats->main_relres_max = main_max;
-        stats->mvms = stt.mvms;
-    }
+    fill_stats(stats, stt, tr.data(), s, m, main_max);
     return status;
 }
 
@@ -1175,6 +1269,46 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
                 const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
                 dsbcg_stats *stats, dsbcg_stream stream) {
     return solve_checked(h, U, kappa, B, 0, m, sigma, s, tol, opts, X, stats, (hipStream_t)stream);
+}
+
+int dsbcg_solve_rational(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
+                         const double *sigma, const double *coef, int32_t s, double c0, double tol,
+                         const dsbcg_opts *opts, void *Y, dsbcg_stats *stats, dsbcg_stream stream) {
+    hipStream_t st = (hipStream_t)stream;
+    dsbcg_opts o;
+    CHK(solve_args(h, U, B, m, sigma, s, tol, kappa, Y, opts, &o));
+    if (!coef) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (!std::isfinite(c0)) return fail(DSBCG_ERR_ARG, "c0 not finite");
+    for (int j = 0; j < s; ++j)
+        if (!std::isfinite(coef[j])) return fail(DSBCG_ERR_ARG, "coefficient not finite");
+    if (Y == B) return fail(DSBCG_ERR_ARG, "Y must not alias B");
+    const int64_t n = 12 * (int64_t)h->g.V;
+    CHK(ensure_common(h));
+    if (o.precision == DSBCG_FP32_RELIABLE) {
+        // the checked solve (FP64 true residuals, re-solves) into workspace,
+        // then Y = c0 B + sum_j c_j X_j
+        CHK(ensure(h->Xrat, (size_t)n * m * s * sizeof(zd)));
+        const int status = solve_checked(h, U, kappa, B, 0, m, sigma, s, tol, &o, h->Xrat.p, stats, st);
+        if (status != DSBCG_OK && status != DSBCG_ERR_NOT_CONVERGED) return status;
+        PROF_LAUNCH(h, kProfConvert, copy_bytes(h->g.V, m, 16, 16, false), st,
+                    copy_field(h->g.V, m, api(B, m), api(Y, m), false, c0, st));
+        for (int j = 0; j < s; ++j)
+            PROF_LAUNCH(h, kProfConvert, copy_bytes(h->g.V, m, 16, 16, true), st,
+                        copy_field(h->g.V, m, api((const zd *)h->Xrat.p + (int64_t)j * n * m, m), api(Y, m),
+                                   true, coef[j], st));
+        HIPCHK(hipStreamSynchronize(st));
+        return status;
+    }
+    CHK(check_finite_links(h, U, st));
+    CHK(prepare_links(h, U, true, st));
+    SolveStats stt;
+    RatSpec rs{coef, c0, Y};
+    const int status = solve_core(h, kappa, B, 0, m, sigma, s, tol, o, o.switch_at, nullptr, stt, st, &rs);
+    if (status != DSBCG_OK && status != DSBCG_ERR_NOT_CONVERGED) return status;
+    // no per-shift iterates, so no true residuals: reported as -1
+    std::vector<double> tr((size_t)s * m, -1.0);
+    fill_stats(stats, stt, tr.data(), s, m, -1.0);
+    return status;
 }
 
 int dsbcg_solve_multi(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,

@@ -1,0 +1,186 @@
+"""Partial-fraction form Y = c0 B + sum_j c_j (sigma_j + A)^{-1} B on the GPU.
+
+FP64 form (the per-shift iterates are never formed; the window contraction
+accumulates the sum directly): parity with the oracle's partial-fraction sum
+of its own iterates at a fixed number of block steps for several window
+lengths (one window; several windows, where the P_{j,i0} terms of every
+shift enter), agreement with dsbcg_solve followed by the sum when systems
+freeze at different steps, the dense solution, deflated and zero columns,
+zero coefficients (Y = c0 B exactly) and the error paths.  FP32 form: the
+checked solve followed by the sum.  Tolerances: 1e-10 relative at fixed
+steps (expected ~1e-13), the same iterates of the other entry point to
+1e-11, and sum_j |c_j| cond_j tol against dense solves."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1205_0359_amd import inputs
+import paper_1205_0359_amd as dsb
+
+from gpu_util import announce, dev, host, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+COEF4 = (0.31, -1.7, 2.2, 0.05)
+
+
+def _op(L, U, kappa):
+    V = int(np.prod(L))
+
+    def f(Y):
+        return oracle.apply_A(L, U, kappa, np.ascontiguousarray(Y).reshape(V, 4, 3, -1)).reshape(12 * V, -1)
+    return f
+
+
+def _problem(L, m, seed, kind="haar", rhs="gaussian"):
+    V = int(np.prod(L))
+    U = inputs.make_links(L, kind, inputs.rng_for(seed, 0))
+    if rhs == "deflating":
+        B = inputs.deflating_rhs(inputs.rng_for(seed, 1), inputs.rng_for(seed, 2), V)
+    else:
+        B = inputs.make_rhs(rhs, V, m, inputs.rng_for(seed, 1))
+    return U, B
+
+
+def _rational(L, U, kappa, B, sig, coef, c0, tol, **kw):
+    h = dsb.Handle(L)
+    Y, st = dsb.dsbcg_solve_rational(h, dev(U), kappa, dev(B), sig, coef, c0, tol, **kw)
+    return host(Y), st
+
+
+@pytest.mark.parametrize("window", [0, 1, 3, 5])
+def test_fixed_iterations_match_oracle(window):
+    L, m, sig, k = (4, 4, 4, 6), 5, (1e-3, 3e-2, 0.5, 2.0), 11
+    announce("rational fixed", L, m, sig, k, window)
+    kappa = 0.124
+    U, B = _problem(L, m, 900, "haar")
+    n = 12 * int(np.prod(L))
+    ref = oracle.dsbcg(_op(L, U, kappa), B.reshape(n, m), sig, 1e-30, fixed_iters=k)
+    want = oracle.partial_fraction(B.reshape(n, m), ref.X, COEF4, 0.7)
+    Y, st = _rational(L, U, kappa, B, sig, COEF4, 0.7, 1e-30, fixed_iters=k, window=window)
+    assert st["block_iters"] == k and st["rank0"] == m
+    assert rel_fro(Y.reshape(n, m), want) <= 1e-10
+    np.testing.assert_allclose(st["est_relres"], ref.est, rtol=1e-8, atol=1e-14)
+    assert np.all(st["true_relres"] == -1.0) and st["main_relres_max"] == -1.0
+
+
+@pytest.mark.parametrize("window", [0, 2])
+def test_freezing_matches_solve_then_sum(window):
+    """Systems that freeze at different steps contribute their final iterates:
+    the same numbers as dsbcg_solve followed by the sum."""
+    L, m = (4, 4, 4, 4), 5
+    sig = (1e-3, 0.05, 0.8, 4.0)
+    announce("rational freezing", L, m, sig, window)
+    U, B = _problem(L, m, 906, "smooth")
+    B[..., 2] *= 1e-3
+    n = 12 * int(np.prod(L))
+    h = dsb.Handle(L)
+    X, sx = dsb.dsbcg_solve(h, dev(U), 0.125, dev(B), sig, 1e-10, window=window)
+    X = host(X).reshape(len(sig), n, m)
+    Y, sy = _rational(L, U, 0.125, B, sig, COEF4, -0.4, 1e-10, window=window)
+    assert sy["block_iters"] == sx["block_iters"]
+    want = oracle.partial_fraction(B.reshape(n, m), X, COEF4, -0.4)
+    assert rel_fro(Y.reshape(n, m), want) <= 1e-11
+
+
+def test_converges_to_dense_partial_fraction():
+    w = inputs.WORKLOADS["haar4^4_m4_s3"]
+    announce("rational dense", w.name)
+    U, B = w.make()
+    n, m = w.n, w.m
+    coef = (1.5, -0.25, 0.8)
+    Y, st = _rational(w.L, U, w.kappa, B, w.shifts, coef, 0.3, w.tol)
+    assert st["status"] == "OK"
+    op = _op(w.L, U, w.kappa)
+    A = op(np.eye(n, dtype=complex))
+    ev = np.linalg.eigvalsh(A)
+    Bn = B.reshape(n, m)
+    dense = 0.3 * Bn
+    bound = 0.0
+    for c, sg in zip(coef, w.shifts):
+        dense = dense + c * np.linalg.solve(A + sg * np.eye(n), Bn)
+        bound += abs(c) * (ev[-1] + sg) / (ev[0] + sg) / (ev[0] + sg)
+    err = np.linalg.norm(Y.reshape(n, m) - dense)
+    assert err <= bound * w.tol * np.linalg.norm(Bn)
+
+
+def test_deflated_and_zero_columns():
+    L = (4, 4, 4, 4)
+    announce("rational deflating", L)
+    kappa = 0.124
+    U, B = _problem(L, 8, 930, "haar", "deflating")
+    B[..., 3] = 0
+    sig = tuple(np.logspace(-5, 0, 10))
+    coef = tuple(np.linspace(-1.0, 1.0, 10))
+    n = 12 * int(np.prod(L))
+    Y, st = _rational(L, U, kappa, B, sig, coef, 0.5, 1e-10)
+    h = dsb.Handle(L)
+    X, sx = dsb.dsbcg_solve(h, dev(U), kappa, dev(B), sig, 1e-10)
+    want = oracle.partial_fraction(B.reshape(n, 8), host(X).reshape(10, n, 8), coef, 0.5)
+    assert st["rank0"] == sx["rank0"] == 4
+    assert rel_fro(Y.reshape(n, 8), want) <= 1e-11
+    assert np.all(Y[..., 3] == 0)
+
+
+def test_zero_coefficients_give_c0_B_exactly():
+    L = (2, 2, 4, 4)
+    announce("rational zero coefficients", L)
+    U, B = _problem(L, 3, 940, "smooth")
+    Y, st = _rational(L, U, 0.125, B, (1e-2, 0.5), (0.0, 0.0), -1.25, 1e-10)
+    assert np.array_equal(Y, -1.25 * B)
+
+
+def test_fp32_form_is_checked_solve_then_sum():
+    L, m = (4, 4, 4, 6), 4
+    sig = (1e-4, 1e-2, 1.0)
+    coef = (0.9, -0.3, 1.1)
+    announce("rational fp32", L, m, sig)
+    U, B = _problem(L, m, 950, "haar")
+    n = 12 * int(np.prod(L))
+    h = dsb.Handle(L)
+    X, sx = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=dsb.DSBCG_FP32_RELIABLE)
+    Y, sy = dsb.dsbcg_solve_rational(h, dev(U), 0.124, dev(B), sig, coef, 0.2, 1e-10,
+                                     precision=dsb.DSBCG_FP32_RELIABLE)
+    assert sy["true_relres"].max() <= 1e-10 and sy["switch_iter"] > 0
+    want = oracle.partial_fraction(B.reshape(n, m), host(X).reshape(len(sig), n, m), coef, 0.2)
+    assert rel_fro(host(Y).reshape(n, m), want) <= 1e-13
+
+
+def test_error_paths():
+    L = (2, 2, 4, 4)
+    announce("rational errors", L)
+    U, B = _problem(L, 2, 960)
+    h = dsb.Handle(L)
+    dU, dB = dev(U), dev(B)
+    with pytest.raises(ValueError):
+        dsb.dsbcg_solve_rational(h, dU, 0.12, dB, (0.1, 0.2), (1.0,), 0.0, 1e-10)
+    with pytest.raises(dsb.DSBCGError):
+        dsb.dsbcg_solve_rational(h, dU, 0.12, dB, (0.1,), (float("nan"),), 0.0, 1e-10)
+    with pytest.raises(dsb.DSBCGError):
+        dsb.dsbcg_solve_rational(h, dU, 0.12, dB, (0.1,), (1.0,), float("inf"), 1e-10)
+    with pytest.raises(dsb.DSBCGError):
+        dsb.dsbcg_solve_rational(h, dU, 0.12, dB, (0.1,), (1.0,), 0.0, 1e-10, Y=dB)
+    with pytest.raises(dsb.NotHPDError):
+        dsb.dsbcg_solve_rational(h, dU, 0.12, dB, (0.1, -10.0), (1.0, 1.0), 0.0, 1e-10)
+    Y, st = dsb.dsbcg_solve_rational(h, dU, 0.12, dB, (1e-2,), (2.0,), 0.0, 1e-10, max_iters=2,
+                                     raise_not_converged=False)
+    assert st["status"] == "ERR_NOT_CONVERGED"
+    n = 12 * int(np.prod(L))
+    ref = oracle.dsbcg(_op(L, U, 0.12), B.reshape(n, 2), (1e-2,), 1e-10, fixed_iters=2)
+    assert rel_fro(host(Y).reshape(n, 2), 2.0 * ref.X[0]) <= 1e-11
+
+
+def test_full_size_16x16x16x16_matches_solve_then_sum():
+    """The 16^4 smooth-link workload: the partial-fraction form agrees with
+    the per-shift solve summed afterwards."""
+    w = inputs.WORKLOADS["smooth16^4_m12_s8"]
+    announce("rational full size", w.name)
+    U, B = w.make()
+    coef = tuple(np.linspace(0.2, 1.6, len(w.shifts)))
+    h = dsb.Handle(w.L)
+    dU, dB = dev(U), dev(B)
+    X, sx = dsb.dsbcg_solve(h, dU, w.kappa, dB, w.shifts, w.tol)
+    Y, sy = dsb.dsbcg_solve_rational(h, dU, w.kappa, dB, w.shifts, coef, 1.0, w.tol)
+    assert sy["status"] == "OK" and sy["block_iters"] == sx["block_iters"]
+    want = oracle.partial_fraction(B.reshape(w.n, w.m), host(X).reshape(len(w.shifts), w.n, w.m), coef, 1.0)
+    assert rel_fro(host(Y).reshape(w.n, w.m), want) <= 1e-11
