@@ -502,8 +502,9 @@ hipError_t copy_field(int64_t V, int cols, FieldDesc in, FieldDesc out, bool acc
 // accumulators; each lane group then stores 16 consecutive rows.
 //
 // A workgroup owns 16 * TILES consecutive rows and has one wave per shift of
-// the window; the window columns are staged chunk by chunk in LDS and read
-// by every wave, the P_{j,i0} columns are read by their own wave only.
+// the window; the window columns are staged chunk by chunk in LDS (double
+// buffered, asynchronous copies) and read by every wave, the P_{j,i0}
+// columns are read by their own wave only.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Mfma;
@@ -522,107 +523,154 @@ struct Mfma<double> {
     }
 };
 
-// window columns per LDS chunk: 32 KiB of staged rows
-template <typename R, int TILES>
-struct WinChunk {
-    static constexpr int value = 32768 / (16 * TILES * (int)sizeof(cx<R>));
+// Stage geometry of the window contraction: PAIRS input pairs (2 PAIRS
+// columns) of the workgroup's 64 rows, plus the coefficients of those pairs
+// for every shift of the launch.  Fewer pairs for wide outputs.
+template <typename R, int NMT>
+struct WinStage {
+    static constexpr int pairs = NMT == 1 ? 4 : (NMT == 2 ? 2 : 1);
+    static constexpr int rows = 64;                                  // rows per workgroup
+    static constexpr int rpl = 16 / (int)sizeof(cx<R>);              // rows per lane and copy
+    static constexpr int data_bytes = 2 * pairs * rows * (int)sizeof(cx<R>);
+    static constexpr int data_copies = data_bytes / 1024;            // 1 KiB copies
+    static constexpr int coef_elems = pairs * NMT * 64;               // per shift
+    static constexpr int coef_bytes = coef_elems * (int)sizeof(R);
+    static constexpr int coef_copies = (coef_bytes + 1023) / 1024;
+    static_assert(data_bytes % 1024 == 0 && coef_bytes % 16 == 0, "16-byte lanes, 1 KiB copies");
 };
 
-template <typename R, int NMT, int TILES>
+// Issue the asynchronous global-to-LDS copies of stage k into buf: the data
+// block [column][64 rows] of cx<R>, then per shift the table entries
+// [pair][mt][lane] of the stage's pairs.  Lane l of a copy writes 16 bytes
+// at (copy base) + 16 l; the waves share the copies.  Columns past the
+// window, rows past n and pairs past the table read column 0 / row 0 /
+// pair 0 instead: they are skipped or their outputs discarded, so only
+// finite values matter there.  FP32 rows move in aligned pairs (n even).
+template <typename R, int NMT>
+__device__ inline void stage_window(const WinArgs &a, int k, int64_t r0, char *buf, int lane, int wave,
+                                    int nw) {
+    typedef WinStage<R, NMT> S;
+    const int npairs_v = (a.ncolv + 1) >> 1;
+    const int total = S::data_copies + a.nshift * S::coef_copies;
+    for (int q = wave; q < total; q += nw) {
+        const void *src;
+        char *dst;
+        if (q < S::data_copies) {
+            const int e = q * 64 * S::rpl + lane * S::rpl;
+            const int cc = e / S::rows, r = e - cc * S::rows;
+            const int c = k * 2 * S::pairs + cc;
+            int64_t row = r0 + r;
+            if (row >= a.nrows) row = 0;
+            src = (const cx<R> *)a.colptr[c < a.ncolv ? c : 0] + row;
+            dst = buf + q * 1024;
+        } else {
+            const int js = (q - S::data_copies) / S::coef_copies;
+            const int cq = (q - S::data_copies) - js * S::coef_copies;
+            const int byte = cq * 1024 + lane * 16;
+            if (byte >= S::coef_bytes) continue;  // partial last copy
+            const int e = byte / (int)sizeof(R);
+            int pair = k * S::pairs + e / (NMT * 64);
+            const int rest = e % (NMT * 64);
+            if (pair >= npairs_v) pair = 0;
+            src = (const R *)a.table + ((size_t)js * a.npairs + a.pairs_p + pair) * NMT * 64 + rest;
+            dst = buf + S::data_bytes + js * S::coef_bytes + cq * 1024;
+        }
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    }
+}
+
+// Workgroup: 64 rows, 4 waves per group of up to SPW shifts; wave w takes the
+// 16-row tile w % 4 for the shifts of group w / 4.  Each SIMD thus holds one
+// wave of every group and the matrix-core work is the same on all four.
+// The stages are double buffered: the copies of stage k + 1 run while stage
+// k multiplies; every operand of the multiply comes from LDS.
+template <typename R, int NMT, int SPW>
 __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
-    constexpr int CH = WinChunk<R, TILES>::value;
-    static_assert(CH % 2 == 0, "chunks hold whole input pairs");
-    constexpr int RW = 16 * TILES;  // rows per workgroup
+    typedef WinStage<R, NMT> S;
     typedef typename Mfma<R>::v4 v4;
-    __shared__ cx<R> vt[CH * RW];
+    extern __shared__ __align__(16) char win_smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int grp = wave >> 2, tile = wave & 3;
     const int64_t n = a.nrows;
-    const int64_t r0 = (int64_t)blockIdx.x * RW;
-    const bool active = wave < a.nshift;
-    const int j = active ? a.shifts[wave] : 0;
-    const R *tab = (const R *)a.table + (size_t)wave * a.npairs * NMT * 64 + lane;
-    const int rl = lane & 15;           // row within a 16-row tile
+    const int64_t r0 = (int64_t)blockIdx.x * S::rows;
+    const int rl = lane & 15;           // row within the tile
     const int part = (lane >> 4) & 1;   // real (0) or imaginary (1) part of the input
     const int sel = lane >> 5;          // input column of the pair
+    const int64_t row = r0 + tile * 16 + rl;
+    const int js0 = grp * SPW;
+    const int nsw = min(SPW, a.nshift - js0);  // >= 1 by the launch shape
+    const int npairs_v = (a.ncolv + 1) >> 1;
+    const int nst = (npairs_v + S::pairs - 1) / S::pairs;
+    const int buf_bytes = S::data_bytes + a.nshift * S::coef_bytes;
 
-    v4 acc[TILES][NMT];
-#pragma unroll
-    for (int t = 0; t < TILES; ++t)
-#pragma unroll
-        for (int mt = 0; mt < NMT; ++mt) acc[t][mt] = v4{0, 0, 0, 0};
+    // the first stage's copies overlap the P_{j,i0} part
+    if (nst > 0) stage_window<R, NMT>(a, 0, r0, win_smem, lane, wave, nw);
 
-    // inputs from P_{j,i0}, per wave
-    if (active && a.bp0 > 0) {
-        const R *P = (const R *)a.Pold + (size_t)2 * j * a.pstride;
-        for (int pp = 0; pp < a.pairs_p; ++pp) {
-            const int p = 2 * pp + sel;
-            R d[TILES];
+    v4 acc[SPW][NMT];
 #pragma unroll
-            for (int t = 0; t < TILES; ++t) {
-                const int64_t row = r0 + t * 16 + rl;
-                d[t] = (p < a.bp0 && row < n) ? P[2 * ((int64_t)p * n + row) + part] : (R)0;
-            }
+    for (int u = 0; u < SPW; ++u)
 #pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) {
-                const R cf = tab[(pp * NMT + mt) * 64];
+        for (int mt = 0; mt < NMT; ++mt) acc[u][mt] = v4{0, 0, 0, 0};
+
+    // inputs from P_{j,i0}, per shift; coefficients straight from the table
+    if (a.bp0 > 0) {
 #pragma unroll
-                for (int t = 0; t < TILES; ++t) acc[t][mt] = Mfma<R>::mac(cf, d[t], acc[t][mt]);
+        for (int u = 0; u < SPW; ++u) {
+            if (u >= nsw) break;
+            const int js = js0 + u;
+            const R *P = (const R *)a.Pold + (size_t)2 * a.shifts[js] * a.pstride;
+            const R *tab = (const R *)a.table + (size_t)js * a.npairs * NMT * 64 + lane;
+            for (int pp = 0; pp < a.pairs_p; ++pp) {
+                const int p = 2 * pp + sel;
+                const R d = (p < a.bp0 && row < n) ? P[2 * ((int64_t)p * n + row) + part] : (R)0;
+#pragma unroll
+                for (int mt = 0; mt < NMT; ++mt)
+                    acc[u][mt] = Mfma<R>::mac(tab[(pp * NMT + mt) * 64], d, acc[u][mt]);
             }
         }
     }
-    // window columns, staged in LDS (columns past the end and rows past n are zero)
-    for (int c0 = 0; c0 < a.ncolv; c0 += CH) {
+    for (int k = 0; k < nst; ++k) {
+        // stage k has landed for every wave, and every wave is done with
+        // stage k - 1, whose buffer takes stage k + 1
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        for (int e = threadIdx.x; e < CH * RW; e += blockDim.x) {
-            const int cc = e / RW, r = e - cc * RW;
-            const int c = c0 + cc;
-            const int64_t row = r0 + r;
-            cx<R> v = mk<R>(0, 0);
-            if (c < a.ncolv && row < n) v = ((const cx<R> *)a.colptr[c])[row];
-            vt[e] = v;
-        }
-        __syncthreads();
-        if (!active) continue;
-        const int npp = (min(CH, a.ncolv - c0) + 1) >> 1;
-        const R *tc = tab + (size_t)(a.pairs_p + (c0 >> 1)) * NMT * 64;
-        // coefficients of the next pair are loaded while this pair multiplies
-        R cf[NMT];
+        if (k + 1 < nst) stage_window<R, NMT>(a, k + 1, r0, win_smem + ((k + 1) & 1) * buf_bytes, lane, wave, nw);
+        const char *buf = win_smem + (k & 1) * buf_bytes;
+        const cx<R> *dat = (const cx<R> *)buf;
+        const R *cof = (const R *)(buf + S::data_bytes) + (size_t)js0 * S::coef_elems + lane;
+        const int npp = min(S::pairs, npairs_v - k * S::pairs);
 #pragma unroll
-        for (int mt = 0; mt < NMT; ++mt) cf[mt] = tc[mt * 64];
-        for (int pp = 0; pp < npp; ++pp) {
-            const R *src = (const R *)&vt[(2 * pp + sel) * RW + rl] + part;
-            R d[TILES];
+        for (int pp = 0; pp < S::pairs; ++pp) {
+            if (pp < npp) {
+                const R d = ((const R *)&dat[(2 * pp + sel) * S::rows + tile * 16 + rl])[part];
 #pragma unroll
-            for (int t = 0; t < TILES; ++t) d[t] = src[2 * t * 16];
-            R cn[NMT];
-            const int pn = pp + 1 < npp ? pp + 1 : pp;
+                for (int u = 0; u < SPW; ++u) {
+                    if (u < nsw) {
 #pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) cn[mt] = tc[(pn * NMT + mt) * 64];
-#pragma unroll
-            for (int mt = 0; mt < NMT; ++mt)
-#pragma unroll
-                for (int t = 0; t < TILES; ++t) acc[t][mt] = Mfma<R>::mac(cf[mt], d[t], acc[t][mt]);
-#pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) cf[mt] = cn[mt];
+                        for (int mt = 0; mt < NMT; ++mt)
+                            acc[u][mt] = Mfma<R>::mac(cof[u * S::coef_elems + (pp * NMT + mt) * 64], d, acc[u][mt]);
+                    }
+                }
+            }
         }
     }
-    if (!active) return;
-    // lane holds rows r0 + 16 t + rl, complex outputs q = 8 mt + 2 g and q + 1
+    if (row >= n) return;
+    // lane holds row `row`, complex outputs q = 8 mt + 2 g and q + 1 of each shift
     const int g = lane >> 4;
-    const uint32_t xm = a.xmask[j];
-    const bool wp = a.pmask[j] != 0;
-    zd *X = a.X + (size_t)j * a.xstride;
-    cx<R> *Pn = (cx<R> *)a.Pnew + (size_t)j * a.pstride;
 #pragma unroll
-    for (int t = 0; t < TILES; ++t) {
-        const int64_t row = r0 + t * 16 + rl;
-        if (row >= n) continue;
+    for (int u = 0; u < SPW; ++u) {
+        if (u >= nsw) break;
+        const int j = a.shifts[js0 + u];
+        const uint32_t xm = a.xmask[j];
+        const bool wp = a.pmask[j] != 0;
+        zd *X = a.X + (size_t)j * a.xstride;
+        cx<R> *Pn = (cx<R> *)a.Pnew + (size_t)j * a.pstride;
 #pragma unroll
         for (int mt = 0; mt < NMT; ++mt) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int q = mt * 8 + 2 * g + h;
-                const R re = acc[t][mt][2 * h], im = acc[t][mt][2 * h + 1];
+                const R re = acc[u][mt][2 * h], im = acc[u][mt][2 * h + 1];
                 if (q < a.m) {
                     zd *x = X + (int64_t)q * n + row;
                     if (a.xinit)  // first window: X_j = increment (zero where never updated)
@@ -637,33 +685,72 @@ __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
     }
 }
 
+template <typename R, int NMT, int SPW>
+hipError_t window_launch(const WinArgs &a, hipStream_t st) {
+    typedef WinStage<R, NMT> S;
+    const int groups = (a.nshift + SPW - 1) / SPW;
+    const dim3 block(64 * 4 * groups);
+    const dim3 grid((unsigned)((a.nrows + S::rows - 1) / S::rows));
+    const size_t lds = 2 * ((size_t)S::data_bytes + (size_t)a.nshift * S::coef_bytes);
+    hipLaunchKernelGGL((window_kernel<R, NMT, SPW>), grid, block, lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename R, int NMT>
+hipError_t window_launch_spw(const WinArgs &a, int spw, hipStream_t st) {
+    if (spw == 1) return window_launch<R, NMT, 1>(a, st);
+    // wide FP64 outputs keep at most two shifts' accumulators per wave
+    if constexpr (sizeof(R) == 8 && NMT >= 3) {
+        return window_launch<R, NMT, 2>(a, st);
+    } else {
+        if (spw == 2) return window_launch<R, NMT, 2>(a, st);
+        return window_launch<R, NMT, 4>(a, st);
+    }
+}
+
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
-    // m = 0: only P_{j,end} is formed (partial-fraction form)
+    // m = 0: only P_{j,end} is formed (partial-fraction form).  The staged
+    // copies move rows in aligned pairs in FP32: nrows must be even.
     if (a.nshift < 1 || a.nshift > 16 || a.m < 0 || a.m > 16 || a.bend < 0 || a.bend > 16 ||
+        (a.nrows & 1) || (a.ncolv > 0 && !a.colptr) ||
         a.m + a.bend < 1 || (a.m == 0 && a.xinit) ||
         a.bp0 < 0 || a.bp0 > 16 || a.ncolv < 0 || a.nmt < 1 || a.nmt > 4 ||
         a.nmt * 8 < a.m + a.bend || a.pairs_p != (a.bp0 + 1) / 2 ||
         a.npairs != a.pairs_p + (a.ncolv + 1) / 2)
         return hipErrorInvalidValue;
     if (a.nrows <= 0) return hipSuccess;
-    const dim3 block(64 * a.nshift);
-    // 16-row tiles per wave: as many as the accumulators allow (8, 4 or 2)
-    const int tiles = fp64 ? (a.nmt <= 2 ? 4 : 2) : (a.nmt <= 2 ? 8 : 4);
-    const dim3 grid((unsigned)((a.nrows + 16 * tiles - 1) / (16 * tiles)));
-#define DSBCG_WIN(R, M, T) hipLaunchKernelGGL((window_kernel<R, M, T>), grid, block, 0, st, a)
-    if (fp64) {
-        if (a.nmt == 1) DSBCG_WIN(double, 1, 4);
-        else if (a.nmt == 2) DSBCG_WIN(double, 2, 4);
-        else if (a.nmt == 3) DSBCG_WIN(double, 3, 2);
-        else DSBCG_WIN(double, 4, 2);
-    } else {
-        if (a.nmt == 1) DSBCG_WIN(float, 1, 8);
-        else if (a.nmt == 2) DSBCG_WIN(float, 2, 8);
-        else if (a.nmt == 3) DSBCG_WIN(float, 3, 4);
-        else DSBCG_WIN(float, 4, 4);
+    // shifts per launch: at most 16 waves (4 groups) of SPW <= 4 shifts, FP64
+    // accumulators of wide outputs in at most 2 shifts per wave, and at most
+    // 64 KiB of double-buffered LDS
+    const size_t esz = fp64 ? sizeof(double) : sizeof(float);
+    const int max_spw = (fp64 && a.nmt >= 3) ? 2 : 4;
+    const int pairs = a.nmt == 1 ? 4 : (a.nmt == 2 ? 2 : 1);
+    const size_t data_bytes = 2 * (size_t)pairs * 64 * 2 * esz, coef_bytes = (size_t)pairs * a.nmt * 64 * esz;
+    const int lds_cnt = (int)((32768 - data_bytes) / coef_bytes);
+    const int max_cnt = std::min(std::min(16, 4 * max_spw), lds_cnt);
+    for (int js0 = 0; js0 < a.nshift; js0 += max_cnt) {
+        WinArgs b = a;
+        b.nshift = std::min(max_cnt, a.nshift - js0);
+        b.shifts = a.shifts + js0;
+        b.table = (const char *)a.table + (size_t)js0 * a.npairs * a.nmt * 64 * esz;
+        const int spw = b.nshift <= 4 ? 1 : (b.nshift <= 8 ? 2 : 4);
+        hipError_t e;
+#define DSBCG_WIN(R)                                                        \
+    switch (a.nmt) {                                                        \
+    case 1: e = window_launch_spw<R, 1>(b, spw, st); break;                 \
+    case 2: e = window_launch_spw<R, 2>(b, spw, st); break;                 \
+    case 3: e = window_launch_spw<R, 3>(b, spw, st); break;                 \
+    default: e = window_launch_spw<R, 4>(b, spw, st); break;                \
     }
+        if (fp64) {
+            DSBCG_WIN(double)
+        } else {
+            DSBCG_WIN(float)
+        }
 #undef DSBCG_WIN
-    return hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Partial-fraction window update (see RatArgs).  Lane layout as in

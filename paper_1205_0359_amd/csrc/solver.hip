@@ -221,6 +221,33 @@ double copy_bytes(int64_t V, int cols, size_t in_esz, size_t out_esz, bool accum
     return (double)V * 12 * cols * ((double)in_esz + (accumulate ? 2.0 : 1.0) * (double)out_esz);
 }
 
+// The window rings are sized from the free device memory by each solve and
+// kept between solves; a later solve that needs more per-shift memory (more
+// shifts, wider blocks) releases them first and sizes them again.
+void release_rings(dsbcg_ctx *h) {
+    for (auto &b : h->Vring)
+        if (b.p) {
+            (void)hipFree(b.p);
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+    for (auto &b : h->Vring32)
+        if (b.p) {
+            (void)hipFree(b.p);
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+}
+
+// ensure() for per-solve workspace: on a failed allocation the window rings
+// are released and the allocation is tried once more.
+int ensure_ws(dsbcg_ctx *h, DevBuf &b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return DSBCG_OK;
+    if (ensure(b, bytes) == DSBCG_OK) return DSBCG_OK;
+    release_rings(h);
+    return ensure(b, bytes);
+}
+
 int ensure_common(dsbcg_ctx *h) {
     CHK(ensure(h->partials, (size_t)h->nwg_max * 256 * sizeof(zd)));
     CHK(ensure(h->red, 8 * 256 * sizeof(zd)));
@@ -467,10 +494,10 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
     const int64_t n = 12 * (int64_t)h->g.V;
     const size_t blk = (size_t)n * m * sizeof(zd);
     CHK(ensure_common(h));
-    CHK(ensure(h->R0, blk));
-    CHK(ensure(h->R1, blk));
-    CHK(ensure(h->R2, blk));
-    CHK(ensure(h->R3, blk));
+    CHK(ensure_ws(h, h->R0, blk));
+    CHK(ensure_ws(h, h->R1, blk));
+    CHK(ensure_ws(h, h->R2, blk));
+    CHK(ensure_ws(h, h->R3, blk));
     Ts ts{h, true, st, n};
     std::vector<double> bn(m);
     std::vector<zd> cf(512, mk<double>(0, 0));
@@ -541,11 +568,11 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         return fail(DSBCG_ERR_ARG, "internal: the partial-fraction form runs in FP64 on one B");
 
     CHK(ensure_common(h));
-    CHK(ensure(h->Bint, (size_t)n * M * sizeof(zd)));
-    CHK(ensure(h->Q, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
-    CHK(ensure(h->wbuf, (size_t)n * sizeof(zd)));
-    CHK(ensure(h->V0, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
-    if (!rmode) CHK(ensure(h->X, (size_t)n * m * s * sizeof(zd)));
+    CHK(ensure_ws(h, h->Bint, (size_t)n * M * sizeof(zd)));
+    CHK(ensure_ws(h, h->Q, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
+    CHK(ensure_ws(h, h->wbuf, (size_t)n * sizeof(zd)));
+    CHK(ensure_ws(h, h->V0, (size_t)n * std::min(M, (int)kS) * sizeof(zd)));
+    if (!rmode) CHK(ensure_ws(h, h->X, (size_t)n * m * s * sizeof(zd)));
 
     SmallState *S = stp(h);
     StepReport *rep = repp(h);
@@ -555,7 +582,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                  cm((zd *)h->Bint.p + (int64_t)j * m * n, n, true), false, st));
     if (rmode) {
         // Y = c0 B; the windows add sum_j c_j X_j
-        CHK(ensure(h->Ycm, (size_t)n * m * sizeof(zd)));
+        CHK(ensure_ws(h, h->Ycm, (size_t)n * m * sizeof(zd)));
         CHK(ensure(h->ycoef, kS * sizeof(double)));
         std::vector<double> cf(kS, 0.0);
         for (int j = 0; j < s; ++j) cf[j] = rat->coef[j];
@@ -575,15 +602,15 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     const int wmax = std::max(m1, 1);
     const int steps = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
     const size_t b64 = (size_t)n * wmax * sizeof(zd), b32 = (size_t)n * wmax * sizeof(zf);
-    CHK(ensure(h->T, b64));
-    CHK(ensure(h->W, b64));
-    CHK(ensure(h->P[0], b64 * s));
-    CHK(ensure(h->P[1], b64 * s));
+    CHK(ensure_ws(h, h->T, b64));
+    CHK(ensure_ws(h, h->W, b64));
+    CHK(ensure_ws(h, h->P[0], b64 * s));
+    CHK(ensure_ws(h, h->P[1], b64 * s));
     if (form32) {
-        CHK(ensure(h->T32, b32));
-        CHK(ensure(h->W32, b32));
-        CHK(ensure(h->P32[0], b32 * s));
-        CHK(ensure(h->P32[1], b32 * s));
+        CHK(ensure_ws(h, h->T32, b32));
+        CHK(ensure_ws(h, h->W32, b32));
+        CHK(ensure_ws(h, h->P32[0], b32 * s));
+        CHK(ensure_ws(h, h->P32[1], b32 * s));
     }
     CHK(ensure(h->wcoef, wincoef_bytes()));
     CHK(ensure(h->wlist, 64 * sizeof(int32_t)));
@@ -612,6 +639,20 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         K32 = std::min(K, std::max(1, o.ru_interval));
     }
     const int nring64 = K64 + 2, nring32 = form32 ? K32 + 2 : 0;
+    // the budget counted every block the rings hold: give back the ones this
+    // solve does not use before allocating the others
+    for (size_t k = nring64; k < h->Vring.size(); ++k)
+        if (h->Vring[k].p) {
+            HIPCHK(hipFree(h->Vring[k].p));
+            h->Vring[k].p = nullptr;
+            h->Vring[k].bytes = 0;
+        }
+    for (size_t k = nring32; k < h->Vring32.size(); ++k)
+        if (h->Vring32[k].p) {
+            HIPCHK(hipFree(h->Vring32[k].p));
+            h->Vring32[k].p = nullptr;
+            h->Vring32[k].bytes = 0;
+        }
     if ((int)h->Vring.size() < nring64) h->Vring.resize(nring64);
     if ((int)h->Vring32.size() < nring32) h->Vring32.resize(nring32);
     for (int k = 1; k < nring64; ++k) CHK(ensure(h->Vring[k], b64));
@@ -1105,8 +1146,8 @@ int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     CHK(check_field_args(h, U, X, Y, m, kappa));
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = 12 * (int64_t)h->g.V;
-    CHK(ensure(h->Xin, (size_t)n * m * sizeof(zd)));
-    CHK(ensure(h->Yout, (size_t)n * m * sizeof(zd)));
+    CHK(ensure_ws(h, h->Xin, (size_t)n * m * sizeof(zd)));
+    CHK(ensure_ws(h, h->Yout, (size_t)n * m * sizeof(zd)));
     CHK(prepare_links(h, U, true, st));
     CHK(copy(h, m, api(X, m), cm(h->Xin.p, n, true), false, st));
     CHK(stencil(h, true, h->Ul64.p, kappa, h->Xin.p, h->Yout.p, m, dagger != 0, st));
@@ -1123,9 +1164,9 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     const bool f64 = precision == DSBCG_FP64;
     const int64_t n = 12 * (int64_t)h->g.V;
     const size_t esz = f64 ? sizeof(zd) : sizeof(zf);
-    CHK(ensure(h->Xin, (size_t)n * m * esz));
-    CHK(ensure(h->Yout, (size_t)n * m * esz));
-    CHK(ensure(h->T, (size_t)n * m * esz));
+    CHK(ensure_ws(h, h->Xin, (size_t)n * m * esz));
+    CHK(ensure_ws(h, h->Yout, (size_t)n * m * esz));
+    CHK(ensure_ws(h, h->T, (size_t)n * m * esz));
     CHK(prepare_links(h, U, f64, st));
     CHK(copy(h, m, api(X, m), cm(h->Xin.p, n, f64), false, st));
     CHK(apply_A_cm(h, f64, f64 ? h->Ul64.p : h->Ul32.p, kappa, h->Xin.p, h->T.p, h->Yout.p, m, st));
@@ -1229,8 +1270,8 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
                 if (worst <= tol) continue;
                 any = true;
                 // residual block R_j, then (sigma_j + A) E = R_j in FP64 and X_j += E
-                CHK(ensure(h->Rres, (size_t)n * m * sizeof(zd)));
-                CHK(ensure(h->Xref, (size_t)n * m * sizeof(zd)));
+                CHK(ensure_ws(h, h->Rres, (size_t)n * m * sizeof(zd)));
+                CHK(ensure_ws(h, h->Xref, (size_t)n * m * sizeof(zd)));
                 std::vector<double> tmp((size_t)s * m);
                 CHK(true_residuals(h, st, kappa, B, bstride, X, m, sigma, s, tmp.data(), j, h->Rres.p));
                 double ratio = 1e300;
@@ -1287,7 +1328,7 @@ int dsbcg_solve_rational(dsbcg_handle h, const void *U, double kappa, const void
     if (o.precision == DSBCG_FP32_RELIABLE) {
         // the checked solve (FP64 true residuals, re-solves) into workspace,
         // then Y = c0 B + sum_j c_j X_j
-        CHK(ensure(h->Xrat, (size_t)n * m * s * sizeof(zd)));
+        CHK(ensure_ws(h, h->Xrat, (size_t)n * m * s * sizeof(zd)));
         const int status = solve_checked(h, U, kappa, B, 0, m, sigma, s, tol, &o, h->Xrat.p, stats, st);
         if (status != DSBCG_OK && status != DSBCG_ERR_NOT_CONVERGED) return status;
         PROF_LAUNCH(h, kProfConvert, copy_bytes(h->g.V, m, 16, 16, false), st,
@@ -1329,10 +1370,10 @@ int dsbcg_grad(dsbcg_handle h, const void *U, double kappa, const double *sigma,
     const int64_t n = 12 * (int64_t)h->g.V;
     const size_t blk = (size_t)n * m * sizeof(zd);
     CHK(ensure_common(h));
-    CHK(ensure(h->R0, blk));
-    CHK(ensure(h->R1, blk));
-    CHK(ensure(h->R2, blk));
-    CHK(ensure(h->R3, blk));
+    CHK(ensure_ws(h, h->R0, blk));
+    CHK(ensure_ws(h, h->R1, blk));
+    CHK(ensure_ws(h, h->R2, blk));
+    CHK(ensure_ws(h, h->R3, blk));
     if (dU) CHK(prepare_links(h, U, true, st));
     Ts ts{h, true, st, n};
     for (int j = 0; j < s; ++j) {
@@ -1381,8 +1422,8 @@ int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *P
     // the kernel reads both fields column-major; convert in chunks of <= 16 columns
     const int64_t n = 12 * V;
     const int chunk = std::min<int>(nvec, 16);
-    CHK(ensure(h->Xin, (size_t)n * chunk * sizeof(zd)));
-    CHK(ensure(h->Yout, (size_t)n * chunk * sizeof(zd)));
+    CHK(ensure_ws(h, h->Xin, (size_t)n * chunk * sizeof(zd)));
+    CHK(ensure_ws(h, h->Yout, (size_t)n * chunk * sizeof(zd)));
     for (int c0 = 0; c0 < nvec; c0 += chunk) {
         const int cols = std::min(chunk, nvec - c0);
         CHK(copy(h, cols, FieldDesc{const_cast<void *>(Phi), kApi, nvec, c0, true},
