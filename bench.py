@@ -247,6 +247,7 @@ def run_form(dsb, h, dU, dB, w, prec, steps, warmup):
         "rank0": stats[-1]["rank0"],
         "reliable_updates": stats[-1]["reliable_updates"],
         "refine_iters": stats[-1]["refine_iters"],
+        "qr2_skipped": stats[-1]["qr2_skipped"],
         "max_true_relres": worst,
         "kernels": {k: {"ms_per_solve": v["ms"] / steps,
                         "launches_per_solve": v["launches"] / steps,

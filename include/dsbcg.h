@@ -102,6 +102,8 @@ typedef struct {
     int32_t refine_iters;     /* block steps spent in refinement solves */
     int32_t final_width;      /* width of the last Lanczos block */
     int32_t switch_iter;      /* FP32 form: first block step run with FP32 vectors (0: none) */
+    int32_t qr2_skipped;      /* block steps whose second CholQR pass was not needed (the
+                                 unit-norm kept columns had condition number <= 16) */
     double main_relres_max;   /* largest FP64 true relative residual after the main phase,
                                  before any re-solve (0 when true residuals were not formed) */
     int64_t mvms;             /* applications of A to one vector by the method: sum of the
@@ -162,7 +164,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
  * dsbcg_solve; every system (l, j) is iterated to the same tol.
  *   DSBCG_FP64: the per-shift X_j are never formed.  The window contraction
  *     accumulates sum_j coef_j X_j directly into Y (one output block instead
- *     of s), and no s*V*12*m workspace is held.  Convergence is judged by the
+ *     of s), and no s*V*12*m workspace is held.  Convergence is decided by the
  *     estimated residuals of the method (Sec. 3): stats->true_relres is filled
  *     with -1 (not formed) and main_relres_max is -1.
  *   DSBCG_FP32_RELIABLE: the checked solve of dsbcg_solve (FP64 true

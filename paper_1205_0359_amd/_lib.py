@@ -53,7 +53,8 @@ class dsbcg_stats(ctypes.Structure):
     _fields_ = [("block_iters", ctypes.c_int32), ("rank0", ctypes.c_int32),
                 ("deflations", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("final_width", ctypes.c_int32),
-                ("switch_iter", ctypes.c_int32), ("main_relres_max", ctypes.c_double),
+                ("switch_iter", ctypes.c_int32), ("qr2_skipped", ctypes.c_int32),
+                ("main_relres_max", ctypes.c_double),
                 ("mvms", ctypes.c_int64),
                 ("est_relres", ctypes.POINTER(ctypes.c_double)),
                 ("true_relres", ctypes.POINTER(ctypes.c_double))]
@@ -252,7 +253,7 @@ def _stats_dict(code, st, est, true, s, m):
         "status": STATUS_NAMES.get(code, code),
         "block_iters": st.block_iters, "rank0": st.rank0, "deflations": st.deflations,
         "reliable_updates": st.reliable_updates, "refine_iters": st.refine_iters,
-        "final_width": st.final_width, "switch_iter": st.switch_iter,
+        "final_width": st.final_width, "switch_iter": st.switch_iter, "qr2_skipped": st.qr2_skipped,
         "main_relres_max": st.main_relres_max, "mvms": int(st.mvms),
         "est_relres": est.reshape(s, m).T.copy(), "true_relres": true.reshape(s, m).T.copy(),
     }

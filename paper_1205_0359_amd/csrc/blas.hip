@@ -85,6 +85,7 @@ __device__ inline void combine_row(const TsArgs &a, const cx<R> *coef, int64_t r
 // 3 the diagonal of out^H out only (column norms); K inputs.
 template <typename R, int B, int K, int GRAM>
 __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
+    if (a.skip && *a.skip) return;  // uniform: before any barrier
     __shared__ cx<R> coef[3 * B * B];
     __shared__ zd red[4][B * B];
     load_coefs<R, B>(a, coef);
@@ -179,6 +180,7 @@ struct TileRows {
 
 template <typename R>
 __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
+    if (a.skip && *a.skip) return;  // uniform: before any barrier
     constexpr int B = kMaxW;
     constexpr int kTileRows = TileRows<R>::value;
     __shared__ cx<R> coef[3 * B * B];

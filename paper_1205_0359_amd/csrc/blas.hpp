@@ -29,6 +29,7 @@ struct TsArgs {
     int bl;
     zd *partials;            // [nwg][16*16] FP64 partial Gram matrices
     int64_t rows_per_wg;
+    const int32_t *skip;     // device flag or NULL: when set the launch does nothing
 };
 
 // Launch the combination / Gram kernel; *nwg receives the workgroup count

@@ -534,6 +534,18 @@ __global__ void chol_deflate_kernel(SmallState *st, StepReport *rep,
         }
         for (int r = 0; r < nk; ++r) st->C1[piv[r] * 16 + q] = x[r];
     }
+    // condition of the kept columns scaled to unit norm, Rs = R_KK D^{-1}:
+    // ||Rs||_F^2 = nk and Rs^{-1} = D R_KK^{-1} (rows scaled by the norms)
+    double inv2 = 0.0;
+    for (int c = 0; c < nk; ++c) {
+        double d2 = 0.0;
+        for (int r = 0; r <= c; ++r) d2 += norm2(R[r * 16 + piv[c]]);
+        double row2 = 0.0;
+        for (int q = 0; q < nk; ++q) row2 += norm2(st->C1[piv[c] * 16 + q]);
+        inv2 += d2 * row2;
+    }
+    st->skip_qr2 = (nk > 0 && nk * inv2 <= 16.0 * 16.0) ? 1 : 0;
+    rep->skip_qr2 = st->skip_qr2;
     rep->bnew = nk;
     for (int r = 0; r < 16; ++r) rep->kept[r] = (r < nk) ? piv[r] : -1;
 }
@@ -559,9 +571,12 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
     const int nk = rep->bnew;
     if (t == 0) {
         fail = 0;
-        // G2 = R2^H R2, R2 upper triangular (nk x nk)
+        // G2 = R2^H R2, R2 upper triangular (nk x nk); R2 = I when the
+        // second pass was not run
         for (int e = 0; e < 256; ++e) R2[e] = mk<double>(0, 0);
-        for (int k = 0; k < nk; ++k) {
+        if (st->skip_qr2)
+            for (int k = 0; k < nk; ++k) R2[k * 16 + k] = mk<double>(1, 0);
+        for (int k = 0; k < nk && !st->skip_qr2; ++k) {
             double d = G2[k * 16 + k].x;
             for (int q = 0; q < k; ++q) d -= norm2(R2[q * 16 + k]);
             if (!(d > 0.0)) {

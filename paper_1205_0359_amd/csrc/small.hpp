@@ -30,6 +30,7 @@ struct SmallState {
     int32_t colmap[kS][kS];     // stacked column of right-hand side l of shift j
     double test;         // running estimate of ||T||: max Frobenius norm of alpha_i, beta_i
     int32_t b, bp, m, s;
+    int32_t skip_qr2;    // the first CholQR pass is orthogonal enough: no second pass
 };
 
 // What the host reads after every block step.
@@ -41,6 +42,7 @@ struct StepReport {
     uint32_t colmask[kS];// per shift: columns still being updated
     double est[kS][kS];  // [j][l] estimated relative residual
     double scalar[4];    // [0]: norm of the last CGS remainder, [1]: kept flag of that column
+    int32_t skip_qr2;    // the second CholQR pass of this step was not run
 };
 
 enum { kFlagNotHPD = 1, kFlagQR2 = 2, kFlagNonFinite = 4, kFlagRank = 8 };
@@ -112,7 +114,11 @@ hipError_t small_rational_table(const WinCoef wc, const WindowTable &wt, const i
 
 // First pass of the deflated CholQR of W: Cholesky of G = W^H W with column
 // dropping (remainder <= tau_W * ||T||_est); also updates ||T||_est from
-// alpha_i and beta_i.
+// alpha_i and beta_i.  Sets skip_qr2 when the kept columns, scaled to unit
+// norm, have a condition number of at most 16 (bounded through the Frobenius
+// norms of the scaled factor and its inverse): one CholQR pass then leaves
+// their loss of orthogonality at a few hundred units of rounding, and the
+// second pass is not run.
 hipError_t small_chol_deflate(SmallState *st, StepReport *rep, const zd *alpha_raw, const zd *G,
                               double tau_W, hipStream_t stream);
 

@@ -364,6 +364,7 @@ int prepare_links(dsbcg_ctx *h, const void *U, bool fp64, hipStream_t st) {
 struct SolveStats {
     int32_t block_iters = 0, rank0 = 0, deflations = 0, reliable_updates = 0, refine_iters = 0;
     int32_t final_width = 0, switch_iter = 0;
+    int32_t qr2_skipped = 0;  // steps whose second CholQR pass was not needed
     int64_t mvms = 0;
     double est[kS * kS] = {};
 };
@@ -988,13 +989,15 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         PROF_LAUNCH(h, kProfSmall, 0.0, st,
                     small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1),
                                        lo ? std::max(o.tau_W, 1e-8) : o.tau_W, st));
-        // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new width
+        // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new
+        // width.  Skipped on the device when the first pass sets skip_qr2.
         {
             TsArgs a = ts_args(n);
             a.K = 1;
             a.X[0] = Wb; a.bx[0] = b; a.C[0] = S->C1;
             a.bout = b;
             a.gram = 1;
+            a.skip = &S->skip_qr2;
             CHK(ts.run_reduce(a, b, 2));
         }
         PROF_LAUNCH(h, kProfSmall, 0.0, st,
@@ -1012,6 +1015,13 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         }
         CHK(read_report(h, st));
         const StepReport &R = *h->rep_host;
+        if (h->prof && R.skip_qr2) {
+            // the second-pass launch returned at once: it moved no data
+            const int cls = prof_cls(kProfBlock, f64);
+            h->prof_bytes[cls] -= (double)b * n * (f64 ? sizeof(zd) : sizeof(zf));
+            h->prof_launches[cls] -= 1;
+        }
+        stt.qr2_skipped += R.skip_qr2 ? 1 : 0;
         if (R.flags & kFlagNotHPD) {
             status = fail(DSBCG_ERR_NOT_HPD, "shifted block lost positive definiteness at step " +
                                                  std::to_string(i) + ": sigma_j I + A is not hpd");
@@ -1216,6 +1226,7 @@ void fill_stats(dsbcg_stats *stats, const SolveStats &stt, const double *tr, int
     stats->refine_iters = stt.refine_iters;
     stats->final_width = stt.final_width;
     stats->switch_iter = stt.switch_iter;
+    stats->qr2_skipped = stt.qr2_skipped;
     stats->main_relres_max = main_max;
     stats->mvms = stt.mvms;
 }
@@ -1248,6 +1259,7 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
             stt.block_iters += one.block_iters;
             stt.mvms += one.mvms;
             stt.reliable_updates += one.reliable_updates;
+            stt.qr2_skipped += one.qr2_skipped;
             stt.rank0 = std::max(stt.rank0, one.rank0);
             for (int l = 0; l < m; ++l) stt.est[j * m + l] = one.est[l];
         }

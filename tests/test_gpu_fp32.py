@@ -107,3 +107,37 @@ def test_fp32_form_full_size_24x24x24x48():
     assert np.abs(host(Ag)[sites] - AX).max() <= 1e-12 * np.abs(AX).max()
     print("fp32 full", w.name, "steps", st["block_iters"], "switch", st["switch_iter"],
           "refine", st["refine_iters"], "max", st["true_relres"].max())
+
+
+def test_fp32_form_full_size_32x32x32x64():
+    """The 32^3 x 64 workload (m = 8 of rank 5, 10 shifts) in the shape the
+    benchmark times: every (l, j) at FP64 true residual <= 1e-10; the
+    duplicated right-hand sides give identical solution columns; the oracle
+    evaluates b - (sigma_j + A) x_j at sampled sites for the smallest and
+    largest shift (restricted to those sites it is at most tol ||b_l||) and
+    A x_j against the library's operator."""
+    w = inputs.WORKLOADS["haar32^3x64_m8r5_s10"]
+    announce("fp32 form full size", w.name)
+    U, B = w.make()
+    h = dsb.Handle(w.L)
+    dU = dev(U)
+    X, st = dsb.dsbcg_solve(h, dU, w.kappa, dev(B), w.shifts, w.tol, precision=FP32)
+    assert st["status"] == "OK" and st["rank0"] == 5 and st["switch_iter"] > 0
+    assert st["true_relres"].max() <= w.tol
+    scale = float(X.abs().max())
+    assert float((X[..., 2] - X[..., 0]).abs().max()) <= 1e-13 * scale
+    assert float((X[..., 5] - X[..., 1]).abs().max()) <= 1e-13 * scale
+    rng = np.random.default_rng(7)
+    sites = np.concatenate([[0, w.V - 1], rng.integers(0, w.V, 30)])
+    bnorm = np.linalg.norm(B.reshape(-1, w.m), axis=0)
+    for j in (0, len(w.shifts) - 1):
+        Xh = host(X[j])
+        AX = oracle.apply_A_sites(w.L, U, w.kappa, Xh, sites)
+        R = B[sites] - w.shifts[j] * Xh[sites] - AX
+        on_sites = np.sqrt((np.abs(R) ** 2).sum(axis=(0, 1, 2)))
+        assert np.all(on_sites <= w.tol * bnorm), j
+        Ag = host(dsb.dsbcg_apply_A(h, dU, w.kappa, X[j].contiguous()))
+        assert np.abs(Ag[sites] - AX).max() <= 1e-12 * np.abs(AX).max()
+        del Xh, Ag
+    print("fp32 full", w.name, "steps", st["block_iters"], "switch", st["switch_iter"],
+          "refine", st["refine_iters"], "max", st["true_relres"].max())

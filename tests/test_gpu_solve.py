@@ -54,6 +54,7 @@ def test_fixed_iteration_parity_fp64(L, m, sig, k, kind):
     ref = oracle.dsbcg(_op(L, U, kappa), B.reshape(n, m), sig, 1e-30, fixed_iters=k)
     X, st = _gpu_solve(L, U, kappa, B, sig, 1e-30, fixed_iters=k)
     assert st["block_iters"] == ref.iters and st["rank0"] == ref.rank0
+    assert 0 <= st["qr2_skipped"] <= k
     for j in range(len(sig)):
         got = X[j].reshape(n, m)
         assert rel_fro(got, ref.X[j]) <= 1e-10, j
