@@ -81,6 +81,70 @@ __device__ inline void combine_row(const TsArgs &a, const cx<R> *coef, int64_t r
     }
 }
 
+// RPT consecutive rows per thread, loaded and stored as one 16-byte vector
+// (two FP32 complex numbers, or one FP64).  Rows come in aligned groups:
+// the row count, column strides and block bases are multiples of RPT.
+template <typename R, int RPT>
+struct RowVec;
+template <>
+struct RowVec<double, 1> {
+    static __device__ inline void load(const cx<double> *p, cx<double> v[1]) { v[0] = *p; }
+    static __device__ inline void store(cx<double> *p, const cx<double> v[1]) { *p = v[0]; }
+};
+template <>
+struct RowVec<float, 2> {
+    static __device__ inline void load(const cx<float> *p, cx<float> v[2]) {
+        const float4 w = *(const float4 *)p;
+        v[0] = mk<float>(w.x, w.y);
+        v[1] = mk<float>(w.z, w.w);
+    }
+    static __device__ inline void store(cx<float> *p, const cx<float> v[2]) {
+        *(float4 *)p = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    }
+};
+
+template <typename R>
+struct RowsPerThread {
+    static constexpr int value = sizeof(R) == 4 ? 2 : 1;
+};
+
+// combine_row for RPT consecutive rows (widths B <= 8): every input in flight
+// at once, one coefficient row at a time.
+template <typename R, int B, int K, int RPT>
+__device__ inline void combine_rows(const TsArgs &a, const cx<R> *coef, int64_t row, cx<R> o[RPT][B]) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+        for (int q = 0; q < B; ++q) o[i][q] = mk<R>(0, 0);
+    cx<R> x[K][B][RPT];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (k < a.K) {
+            const cx<R> *X = (const cx<R> *)a.X[k] + row;
+            const int last = max(a.bx[k] - 1, 0);
+#pragma unroll
+            for (int p = 0; p < B; ++p) RowVec<R, RPT>::load(X + (int64_t)min(p, last) * a.cs[k], x[k][p]);
+        } else {
+#pragma unroll
+            for (int p = 0; p < B; ++p)
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) x[k][p][i] = mk<R>(0, 0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int p = 0; p < B; ++p) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const cx<R> c = coef[(k * B + p) * B + q];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) cmac(o[i][q], x[k][p][i], c);
+            }
+        }
+}
+
 // Register Gram: GRAM 0 none, 1 out^H out (upper triangle, mirrored), 2 L^H out,
 // 3 the diagonal of out^H out only (column norms); K inputs.
 template <typename R, int B, int K, int GRAM>
@@ -98,43 +162,54 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
     const int64_t r1 = min(a.nrows, r0 + a.rows_per_wg);
     cx<R> *out = (cx<R> *)a.out;
     const int bl = GRAM == 2 ? a.bl : 0;
+    constexpr int RPT = RowsPerThread<R>::value;
 #pragma unroll 1
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += 256) {
-        cx<R> l[B];
+    for (int64_t row = r0 + RPT * threadIdx.x; row < r1; row += 256 * RPT) {
+        cx<R> l[B][RPT];
         if (GRAM == 2) {
             const cx<R> *Lp = (const cx<R> *)a.L + row;
 #pragma unroll
             for (int p = 0; p < B; ++p) {
-                const cx<R> v = Lp[(int64_t)min(p, bl - 1) * a.csl];
-                l[p] = p < bl ? v : mk<R>(0, 0);
+                RowVec<R, RPT>::load(Lp + (int64_t)min(p, bl - 1) * a.csl, l[p]);
+                if (p >= bl)
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) l[p][i] = mk<R>(0, 0);
             }
         }
-        cx<R> o[B];
-        combine_row<R, B, K>(a, coef, row, o);
+        cx<R> o[RPT][B];
+        combine_rows<R, B, K, RPT>(a, coef, row, o);
         if (out)
 #pragma unroll
             for (int q = 0; q < B; ++q)
-                if (q < a.bout) out[q * a.cso + row] = o[q];
-        if (GRAM == 1) {
-            zd od[B];
+                if (q < a.bout) {
+                    cx<R> v[RPT];
 #pragma unroll
-            for (int q = 0; q < B; ++q) od[q] = cvt<double>(o[q]);
+                    for (int i = 0; i < RPT; ++i) v[i] = o[i][q];
+                    RowVec<R, RPT>::store(out + q * a.cso + row, v);
+                }
 #pragma unroll
-            for (int p = 0; p < B; ++p)
+        for (int i = 0; i < RPT; ++i) {
+            if (GRAM == 1) {
+                zd od[B];
 #pragma unroll
-                for (int q = p; q < B; ++q) cmac_conj(G[p * B + q], od[p], od[q]);
-        } else if (GRAM == 3) {
+                for (int q = 0; q < B; ++q) od[q] = cvt<double>(o[i][q]);
 #pragma unroll
-            for (int q = 0; q < B; ++q) G[q * B + q].x += norm2(cvt<double>(o[q]));
-        } else if (GRAM == 2) {
-            zd od[B];
+                for (int p = 0; p < B; ++p)
 #pragma unroll
-            for (int q = 0; q < B; ++q) od[q] = cvt<double>(o[q]);
+                    for (int q = p; q < B; ++q) cmac_conj(G[p * B + q], od[p], od[q]);
+            } else if (GRAM == 3) {
 #pragma unroll
-            for (int p = 0; p < B; ++p) {
-                const zd lp = cvt<double>(l[p]);
+                for (int q = 0; q < B; ++q) G[q * B + q].x += norm2(cvt<double>(o[i][q]));
+            } else if (GRAM == 2) {
+                zd od[B];
 #pragma unroll
-                for (int q = 0; q < B; ++q) cmac_conj(G[p * B + q], lp, od[q]);
+                for (int q = 0; q < B; ++q) od[q] = cvt<double>(o[i][q]);
+#pragma unroll
+                for (int p = 0; p < B; ++p) {
+                    const zd lp = cvt<double>(l[p][i]);
+#pragma unroll
+                    for (int q = 0; q < B; ++q) cmac_conj(G[p * B + q], lp, od[q]);
+                }
             }
         }
     }
@@ -315,7 +390,16 @@ hipError_t ts_run(bool fp64, TsArgs a, int max_wg, int *nwg_out, hipStream_t st)
     for (int k = 0; k < a.K; ++k) w = std::max(w, a.bx[k]);
     if (a.gram == 2) w = std::max(w, a.bl);
     const bool reg = w <= 6 || (w <= 8 && (a.gram == 0 || a.gram == 3));
-    const int tile = reg ? 256 : (fp64 ? TileRows<double>::value : TileRows<float>::value);
+    // the FP32 register kernel moves two rows per thread: even row counts,
+    // column strides and block offsets
+    if (reg && !fp64) {
+        if (a.nrows & 1) return hipErrorInvalidValue;
+        for (int k = 0; k < a.K; ++k)
+            if ((a.cs[k] & 1) || ((uintptr_t)a.X[k] & 15)) return hipErrorInvalidValue;
+        if (a.out && ((a.cso & 1) || ((uintptr_t)a.out & 15))) return hipErrorInvalidValue;
+        if (a.gram == 2 && ((a.csl & 1) || ((uintptr_t)a.L & 15))) return hipErrorInvalidValue;
+    }
+    const int tile = reg ? (fp64 ? 256 : 512) : (fp64 ? TileRows<double>::value : TileRows<float>::value);
     int64_t tiles = (a.nrows + tile - 1) / tile;
     int nwg = (int)(tiles < max_wg ? tiles : max_wg);
     if (nwg < 1) nwg = 1;
