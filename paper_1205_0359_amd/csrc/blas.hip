@@ -81,18 +81,15 @@ __device__ inline void combine_row(const TsArgs &a, const cx<R> *coef, int64_t r
     }
 }
 
-// RPT consecutive rows per thread, loaded and stored as one 16-byte vector
-// (two FP32 complex numbers, or one FP64).  Rows come in aligned groups:
-// the row count, column strides and block bases are multiples of RPT.
-template <typename R, int RPT>
-struct RowVec;
+// Rows per thread.  FP32: two consecutive rows, loaded and stored as one
+// 16-byte vector (row counts, column strides and block bases are even).
+// FP64: one row (already a 16-byte access; a second row per thread only
+// costs occupancy).
+template <typename R>
+struct RowGroup;
 template <>
-struct RowVec<double, 1> {
-    static __device__ inline void load(const cx<double> *p, cx<double> v[1]) { v[0] = *p; }
-    static __device__ inline void store(cx<double> *p, const cx<double> v[1]) { *p = v[0]; }
-};
-template <>
-struct RowVec<float, 2> {
+struct RowGroup<float> {
+    static constexpr int rows = 2;
     static __device__ inline void load(const cx<float> *p, cx<float> v[2]) {
         const float4 w = *(const float4 *)p;
         v[0] = mk<float>(w.x, w.y);
@@ -102,14 +99,15 @@ struct RowVec<float, 2> {
         *(float4 *)p = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
     }
 };
-
-template <typename R>
-struct RowsPerThread {
-    static constexpr int value = sizeof(R) == 4 ? 2 : 1;
+template <>
+struct RowGroup<double> {
+    static constexpr int rows = 1;
+    static __device__ inline void load(const cx<double> *p, cx<double> v[1]) { v[0] = *p; }
+    static __device__ inline void store(cx<double> *p, const cx<double> v[1]) { *p = v[0]; }
 };
 
-// combine_row for RPT consecutive rows (widths B <= 8): every input in flight
-// at once, one coefficient row at a time.
+// combine_row for a group of RPT consecutive rows (widths B <= 8): every
+// input in flight at once, one coefficient row at a time.
 template <typename R, int B, int K, int RPT>
 __device__ inline void combine_rows(const TsArgs &a, const cx<R> *coef, int64_t row, cx<R> o[RPT][B]) {
 #pragma unroll
@@ -123,7 +121,7 @@ __device__ inline void combine_rows(const TsArgs &a, const cx<R> *coef, int64_t 
             const cx<R> *X = (const cx<R> *)a.X[k] + row;
             const int last = max(a.bx[k] - 1, 0);
 #pragma unroll
-            for (int p = 0; p < B; ++p) RowVec<R, RPT>::load(X + (int64_t)min(p, last) * a.cs[k], x[k][p]);
+            for (int p = 0; p < B; ++p) RowGroup<R>::load(X + (int64_t)min(p, last) * a.cs[k], x[k][p]);
         } else {
 #pragma unroll
             for (int p = 0; p < B; ++p)
@@ -162,7 +160,7 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
     const int64_t r1 = min(a.nrows, r0 + a.rows_per_wg);
     cx<R> *out = (cx<R> *)a.out;
     const int bl = GRAM == 2 ? a.bl : 0;
-    constexpr int RPT = RowsPerThread<R>::value;
+    constexpr int RPT = RowGroup<R>::rows;
 #pragma unroll 1
     for (int64_t row = r0 + RPT * threadIdx.x; row < r1; row += 256 * RPT) {
         cx<R> l[B][RPT];
@@ -170,7 +168,7 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
             const cx<R> *Lp = (const cx<R> *)a.L + row;
 #pragma unroll
             for (int p = 0; p < B; ++p) {
-                RowVec<R, RPT>::load(Lp + (int64_t)min(p, bl - 1) * a.csl, l[p]);
+                RowGroup<R>::load(Lp + (int64_t)min(p, bl - 1) * a.csl, l[p]);
                 if (p >= bl)
 #pragma unroll
                     for (int i = 0; i < RPT; ++i) l[p][i] = mk<R>(0, 0);
@@ -185,7 +183,7 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
                     cx<R> v[RPT];
 #pragma unroll
                     for (int i = 0; i < RPT; ++i) v[i] = o[i][q];
-                    RowVec<R, RPT>::store(out + q * a.cso + row, v);
+                    RowGroup<R>::store(out + q * a.cso + row, v);
                 }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
