@@ -104,6 +104,7 @@ struct dsbcg_ctx {
     DevBuf R0, R1, R2, R3, Rres, Xref;                   // true residuals, refinement
     DevBuf Xin, Yout;                                    // dsbcg_apply_* conversions
     DevBuf Ycm, ycoef, Xrat;                             // partial-fraction form
+    DevBuf rpart;                                        // true-residual partial norms
     DevBuf partials, red, list, wlist, st, rep;
     std::vector<DevBuf> Vring, Vring32;                  // window rings of Lanczos blocks
     StepReport *rep_host = nullptr;
@@ -114,7 +115,7 @@ struct dsbcg_ctx {
         DevBuf *all[] = {&Ul64, &Ul32, &V0,  &T,   &W,    &P[0], &P[1], &X,
                          &T32, &W32, &P32[0], &P32[1], &wcoef, &wtable, &colptr,
                          &Bint, &Q,    &wbuf, &R0,   &R1,   &R2,  &R3,   &Rres, &Xref, &Xin,
-                         &Yout, &Ycm, &ycoef, &Xrat, &partials, &red, &list, &wlist, &st, &rep};
+                         &Yout, &Ycm, &ycoef, &Xrat, &rpart, &partials, &red, &list, &wlist, &st, &rep};
         for (DevBuf *b : all)
             if (b->p) (void)hipFree(b->p);
         for (auto &b : Vring)
@@ -522,6 +523,23 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
             xj = Xcm + (int64_t)j * n * m;
         else
             CHK(copy(h, m, api((const zd *)Xapi + (int64_t)j * n * m, m), cm(h->R1.p, n, true), false, st));
+        if (keep_j < 0) {
+            // D x_j, then one pass of D^H that forms |b - sigma x_j - A x_j|^2
+            // per column without storing A x_j
+            CHK(stencil(h, true, h->Ul64.p, kappa, xj, h->R2.p, m, false, st));
+            const int nwg = wilson_resid_workgroups(h->g);
+            CHK(ensure_ws(h, h->rpart, ((size_t)nwg * 16 + 16) * sizeof(double)));
+            double *part = (double *)h->rpart.p, *sums = part + (size_t)nwg * 16;
+            PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, m, sizeof(zd)) + (double)h->g.V * 12 * m * sizeof(zd), st,
+                        wilson_resid_norms(h->g, h->Ul64.p, kappa, h->R2.p, h->R0.p, xj, sigma[j], m, part, st));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st, sum_columns(part, nwg, m, sums, st));
+            std::vector<double> r2(m);
+            HIPCHK(hipMemcpyAsync(r2.data(), sums, m * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int l = 0; l < m; ++l)
+                out[j * m + l] = bn[l] > 0 ? std::sqrt(std::max(r2[l], 0.0)) / bn[l] : 0.0;
+            continue;
+        }
         CHK(apply_A_cm(h, true, h->Ul64.p, kappa, xj, h->R2.p, h->R3.p, m, st));
         TsArgs a = ts_args(n);
         a.K = 3;

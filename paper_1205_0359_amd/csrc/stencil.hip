@@ -104,10 +104,28 @@ __device__ inline void direction(cx<R> acc[4][3], const Geom &g, int x, const in
     hop_term<R, MU, -SF, true>(acc, lb + lane, col, g.V, xb);
 }
 
-template <typename R, bool DAG>
-__global__ __launch_bounds__(1024) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
+// RESID: instead of storing y = D^H in (in = D x), accumulate the squared
+// norm of b - sigma x - y per column: wave w (column w) of workgroup q adds
+// its sum to partials[q * 16 + w].  One pass then yields the true residual
+// norms ||b - (sigma + A) x|| without writing A x.
+struct ResidOut {
+    const zd *b;       // column-major, like in
+    const zd *x;
+    double sigma;
+    double *partials;  // [workgroups][16]
+};
+
+// MAXT: the largest block the instantiation is launched with (64 threads per
+// column).  A 512-thread bound gives the FP64 kernel registers without
+// spills (138 instead of 128 + spills) at 3 waves per SIMD instead of 4.
+// Measured on 32^3 x 64: faster for 1, 2, 4 and 8 columns; for 5 (and 7)
+// columns the two resident 5-wave blocks fill the SIMDs unevenly and the
+// 1024-thread form is faster.
+inline bool small_bound(int nb) { return nb <= 8 && nb != 5 && nb != 7; }
+template <typename R, bool DAG, bool RESID, int MAXT>
+__global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
                                                          R kappa, const cx<R> *__restrict__ in,
-                                                         cx<R> *__restrict__ out, int nb) {
+                                                         cx<R> *__restrict__ out, int nb, ResidOut ro) {
     __shared__ cx<R> lf[9 * kSitesPerWG];
     __shared__ cx<R> lb[9 * kSitesPerWG];
     const int lane = threadIdx.x & 63;
@@ -130,6 +148,28 @@ __global__ __launch_bounds__(1024) void wilson_cm_kernel(Geom g, const cx<R> *__
     direction<R, 1, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
     direction<R, 2, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
     direction<R, 3, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    if (RESID) {
+        double r2 = 0.0;
+        if (valid) {
+            const int64_t base = (int64_t)wave * n;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t idx = (int64_t)(s * 3 + a) * g.V + x;
+                    const cx<R> v = col[idx];
+                    const double yr = (double)v.x - (double)kappa * (double)acc[s][a].x;
+                    const double yi = (double)v.y - (double)kappa * (double)acc[s][a].y;
+                    const zd bv = ro.b[base + idx], xv = ro.x[base + idx];
+                    const double rr = bv.x - ro.sigma * xv.x - yr, ri = bv.y - ro.sigma * xv.y - yi;
+                    r2 += rr * rr + ri * ri;
+                }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) r2 += __shfl_xor(r2, off, 64);
+        if (lane == 0 && wave < nb) ro.partials[(int64_t)blockIdx.x * 16 + wave] = r2;
+        return;
+    }
     if (!valid) return;
 
     cx<R> *oc = out + (int64_t)wave * n;
@@ -159,9 +199,16 @@ hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, 
     if (nb < 1 || nb > 16) return hipErrorInvalidValue;
     const dim3 grid((g.V + kSitesPerWG - 1) / kSitesPerWG);
     const dim3 block(64 * nb);
-#define DSBCG_W(R, D)                                                                          \
-    hipLaunchKernelGGL((wilson_cm_kernel<R, D>), grid, block, 0, st, g, (const cx<R> *)Ul, (R)kappa, \
-                       (const cx<R> *)in, (cx<R> *)out, nb)
+    const ResidOut none{nullptr, nullptr, 0.0, nullptr};
+#define DSBCG_W(R, D)                                                                              \
+    do {                                                                                           \
+        if (small_bound(nb))                                                                       \
+            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512>), grid, block, 0, st, g,           \
+                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
+        else                                                                                       \
+            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 1024>), grid, block, 0, st, g,          \
+                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
+    } while (0)
     if (fp64) {
         if (dagger) DSBCG_W(double, true);
         else DSBCG_W(double, false);
@@ -173,27 +220,77 @@ hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, 
     return hipGetLastError();
 }
 
+int wilson_resid_workgroups(const Geom &g) { return (int)((g.V + kSitesPerWG - 1) / kSitesPerWG); }
+
+hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const void *in, const void *b,
+                              const void *x, double sigma, int nb, double *partials, hipStream_t st) {
+    if (nb < 1 || nb > 16 || !partials) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)wilson_resid_workgroups(g));
+    const dim3 block(64 * nb);
+    const ResidOut ro{(const zd *)b, (const zd *)x, sigma, partials};
+    if (small_bound(nb))
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512>), grid, block, 0, st, g, (const zd *)Ul,
+                           kappa, (const zd *)in, (zd *)nullptr, nb, ro);
+    else
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 1024>), grid, block, 0, st, g, (const zd *)Ul,
+                           kappa, (const zd *)in, (zd *)nullptr, nb, ro);
+    return hipGetLastError();
+}
+
+// out[c] = sum over workgroups w < nwg of partials[w * 16 + c], c < nb, in a
+// fixed order (one block per column).
+__global__ __launch_bounds__(256) void sum_columns_kernel(const double *__restrict__ partials, int nwg,
+                                                          double *__restrict__ out) {
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += 256) s += partials[(int64_t)w * 16 + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+}
+
+hipError_t sum_columns(const double *partials, int nwg, int nb, double *out, hipStream_t st) {
+    if (nb < 1 || nb > 16 || nwg < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sum_columns_kernel, dim3(nb), dim3(256), 0, st, partials, nwg, out);
+    return hipGetLastError();
+}
+
 hipError_t neighbor_table(const Geom &g, int32_t *dev_out, hipStream_t st) {
     hipLaunchKernelGGL(neighbor_kernel, dim3((g.V + 255) / 256), dim3(256), 0, st, g, dev_out);
     return hipGetLastError();
 }
 
-// Links [V][4][3][3] (FP64) -> structure of arrays [4][9][V] in FP64 or FP32.
+// Links [V][4][3][3] (site-major, 36 complex per site) to structure-of-arrays
+// [mu*9 + e][V]: 64 sites per workgroup pass through LDS, read as one
+// contiguous 36-complex-per-site block and written as 36 runs of 64 sites.
+// The LDS rows are padded to 37 complex so that the column reads of a wave
+// fall in distinct banks.
 template <typename To>
 __global__ __launch_bounds__(256) void links_soa_kernel(int64_t V, const zd *__restrict__ U,
                                                         cx<To> *__restrict__ out) {
-    const int64_t total = V * 36;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t x = e % V;
-        const int64_t k = e / V;  // mu*9 + element
-        out[e] = cvt<To>(U[x * 36 + k]);
+    constexpr int kSites = 64, kRow = 37;
+    __shared__ zd tile[kSites * kRow];
+    const int64_t x0 = (int64_t)blockIdx.x * kSites;
+    const int ns = (int)min((int64_t)kSites, V - x0);
+    const zd *src = U + x0 * 36;
+    for (int e = threadIdx.x; e < ns * 36; e += blockDim.x) {
+        const int site = e / 36, k = e - site * 36;
+        tile[site * kRow + k] = src[e];
     }
+    __syncthreads();
+    const int site = threadIdx.x & 63;
+    if (site >= ns) return;
+    for (int k = threadIdx.x >> 6; k < 36; k += 4)
+        out[(int64_t)k * V + x0 + site] = cvt<To>(tile[site * kRow + k]);
 }
 
 hipError_t links_to_soa(int64_t V, const void *U, void *out, bool fp64, hipStream_t st) {
-    const int64_t want = (V * 36 + 255) / 256;
-    const dim3 grid((unsigned)(want < 65536 ? want : 65536));
+    const dim3 grid((unsigned)((V + 63) / 64));
     if (fp64)
         hipLaunchKernelGGL((links_soa_kernel<double>), grid, dim3(256), 0, st, V, (const zd *)U,
                            (zd *)out);

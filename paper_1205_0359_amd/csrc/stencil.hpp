@@ -18,6 +18,15 @@ struct Geom {
 hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, const void *in,
                         void *out, int nb, bool dagger, hipStream_t st);
 
+// True residual norms in one pass: with in = D x (column-major, nb columns,
+// FP64), accumulates |b - sigma x - D^H in|^2 per column and workgroup into
+// partials [wilson_resid_workgroups(g)][16]; sum_columns adds them up in a
+// fixed order into out[0..nb).
+int wilson_resid_workgroups(const Geom &g);
+hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const void *in, const void *b,
+                              const void *x, double sigma, int nb, double *partials, hipStream_t st);
+hipError_t sum_columns(const double *partials, int nwg, int nb, double *out, hipStream_t st);
+
 // Links [V][4][3][3] (FP64) -> structure of arrays [4][9][V], FP64 or FP32.
 hipError_t links_to_soa(int64_t V, const void *U, void *out, bool fp64, hipStream_t st);
 
