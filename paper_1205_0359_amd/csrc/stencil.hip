@@ -43,7 +43,7 @@ constexpr int kSitesPerWG = 64;
 // One hop: acc += P_s (W psi(y)) with W = link (ADJ false) or link^H.
 // psi is read at site y of column base `col`; the link matrix comes from LDS
 // as lnk[e * 64] for e = 0..8.
-template <typename R, int MU, int S, bool ADJ>
+template <typename R, int MU, int S, bool ADJ, bool SB>
 __device__ inline void hop_term(cx<R> acc[4][3], const cx<R> *lnk, const cx<R> *__restrict__ col,
                                 int64_t V, int y) {
 #pragma unroll
@@ -73,6 +73,7 @@ __device__ inline void hop_term(cx<R> acc[4][3], const cx<R> *lnk, const cx<R> *
             rebuild_add<R, MU, S, 0>(acc, u);
         else
             rebuild_add<R, MU, S, 1>(acc, u);
+        if (SB) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -88,7 +89,7 @@ __device__ inline void stage_links(cx<R> *lf, cx<R> *lb, const cx<R> *__restrict
     }
 }
 
-template <typename R, int MU, bool DAG>
+template <typename R, int MU, bool DAG, bool SB>
 __device__ inline void direction(cx<R> acc[4][3], const Geom &g, int x, const int c[4],
                                  const cx<R> *__restrict__ Ul, cx<R> *lf, cx<R> *lb,
                                  const cx<R> *__restrict__ col, bool valid, int lane, int wave,
@@ -100,8 +101,9 @@ __device__ inline void direction(cx<R> acc[4][3], const Geom &g, int x, const in
     stage_links<R>(lf, lb, Ul, g.V, MU, x, xb, valid, lane, wave, nwaves);
     __syncthreads();
     if (!valid) return;
-    hop_term<R, MU, SF, false>(acc, lf + lane, col, g.V, xf);
-    hop_term<R, MU, -SF, true>(acc, lb + lane, col, g.V, xb);
+    hop_term<R, MU, SF, false, SB>(acc, lf + lane, col, g.V, xf);
+    if (SB) __builtin_amdgcn_sched_barrier(0);
+    hop_term<R, MU, -SF, true, SB>(acc, lb + lane, col, g.V, xb);
 }
 
 // RESID: instead of storing y = D^H in (in = D x), accumulate the squared
@@ -116,13 +118,17 @@ struct ResidOut {
 };
 
 // MAXT: the largest block the instantiation is launched with (64 threads per
-// column).  A 512-thread bound gives the FP64 kernel registers without
-// spills (138 instead of 128 + spills) at 3 waves per SIMD instead of 4.
-// Measured on 32^3 x 64: faster for 1, 2, 4 and 8 columns; for 5 (and 7)
-// columns the two resident 5-wave blocks fill the SIMDs unevenly and the
-// 1024-thread form is faster.
-inline bool small_bound(int nb) { return nb <= 8 && nb != 5 && nb != 7; }
-template <typename R, bool DAG, bool RESID, int MAXT>
+// column).  A 512-thread bound lets the FP64 kernel keep its 138 registers
+// without spills, at 3 waves per SIMD instead of 4 (1024-thread bound: 128
+// registers and spills).  SB: scheduling barriers between the half-spinor
+// terms, which hold the FP64 kernel at 126 registers (4 waves per SIMD, no
+// spills) at the price of less load overlap.  Measured on 32^3 x 64: the
+// plain 512-thread form is fastest for 1, 2, 4 and 8 columns; with 5 or 7
+// columns the resident blocks fill the SIMDs unevenly at 3 waves, and the
+// SB form is fastest.
+inline bool small_bound(int nb) { return nb <= 8; }
+inline bool sched_split(bool fp64, int nb) { return fp64 && (nb == 5 || nb == 7); }
+template <typename R, bool DAG, bool RESID, int MAXT, bool SB>
 __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
                                                          R kappa, const cx<R> *__restrict__ in,
                                                          cx<R> *__restrict__ out, int nb, ResidOut ro) {
@@ -144,10 +150,10 @@ __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[s][a] = mk<R>(0, 0);
 
-    direction<R, 0, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
-    direction<R, 1, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
-    direction<R, 2, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
-    direction<R, 3, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    direction<R, 0, DAG, SB>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    direction<R, 1, DAG, SB>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    direction<R, 2, DAG, SB>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    direction<R, 3, DAG, SB>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
     if (RESID) {
         double r2 = 0.0;
         if (valid) {
@@ -202,11 +208,14 @@ hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, 
     const ResidOut none{nullptr, nullptr, 0.0, nullptr};
 #define DSBCG_W(R, D)                                                                              \
     do {                                                                                           \
-        if (small_bound(nb))                                                                       \
-            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512>), grid, block, 0, st, g,           \
+        if (sched_split(fp64, nb))                                                                 \
+            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512, true>), grid, block, 0, st, g,     \
+                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
+        else if (small_bound(nb))                                                                  \
+            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512, false>), grid, block, 0, st, g,    \
                                (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
         else                                                                                       \
-            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 1024>), grid, block, 0, st, g,          \
+            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 1024, false>), grid, block, 0, st, g,   \
                                (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
     } while (0)
     if (fp64) {
@@ -229,11 +238,11 @@ hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const
     const dim3 block(64 * nb);
     const ResidOut ro{(const zd *)b, (const zd *)x, sigma, partials};
     if (small_bound(nb))
-        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512>), grid, block, 0, st, g, (const zd *)Ul,
-                           kappa, (const zd *)in, (zd *)nullptr, nb, ro);
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, false>), grid, block, 0, st, g,
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro);
     else
-        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 1024>), grid, block, 0, st, g, (const zd *)Ul,
-                           kappa, (const zd *)in, (zd *)nullptr, nb, ro);
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 1024, false>), grid, block, 0, st, g,
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro);
     return hipGetLastError();
 }
 
