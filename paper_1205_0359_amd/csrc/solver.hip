@@ -571,11 +571,13 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
 
 // The DSBlockCG iteration.  FP64 form: every vector in FP64.  FP32 form: the
 // iteration starts in FP64 and continues the same recurrences with FP32
-// vectors once every active estimate is <= switch_at; from then on
-// X_j = X_hi + X_lo with X_lo in FP32, added into the FP64 X_hi every
-// ru_interval steps and at the end.  Writes the iterates to Xapi
-// ([s][V][4][3][m], FP64).  The FP64 links must be in h->Ul64 (and the FP32
-// links in h->Ul32 for the FP32 form).
+// vectors once every active estimate is <= switch_at.  The iterates are
+// formed window by window from the kept Lanczos blocks (FP32 blocks
+// contracted in FP32) and accumulated in FP64; a window of FP32 blocks ends
+// at least every ru_interval steps.  Writes the iterates to Xapi
+// ([s][V][4][3][m], FP64), or with rat their partial-fraction sum to
+// rat->Yapi.  The FP64 links must be in h->Ul64 (and the FP32 links in
+// h->Ul32 for the FP32 form).
 int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m,
                const double *sigma, int s, double tol, const dsbcg_opts &o, double switch_at,
                void *Xapi, SolveStats &stt, hipStream_t st, const RatSpec *rat) {
