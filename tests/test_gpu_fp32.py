@@ -141,3 +141,22 @@ def test_fp32_form_full_size_32x32x32x64():
         del Xh, Ag
     print("fp32 full", w.name, "steps", st["block_iters"], "switch", st["switch_iter"],
           "refine", st["refine_iters"], "max", st["true_relres"].max())
+
+
+def test_fp32_form_wide_outputs_over_several_windows():
+    """FP32 windows with wide outputs (12 right-hand sides, P formed at each
+    window end) agree with one automatic window to FP32 accuracy and reach
+    the tolerance."""
+    L, m = (4, 4, 4, 6), 12
+    sig = tuple(np.logspace(-4, 0, 10))
+    announce("fp32 form wide windows", L, m)
+    U = inputs.make_links(L, "haar", inputs.rng_for(980, 0))
+    B = inputs.make_rhs("gaussian", int(np.prod(L)), m, inputs.rng_for(980, 1))
+    h = dsb.Handle(L)
+    X2, s2 = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=FP32, window=2, ru_interval=3)
+    X0, s0 = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=FP32)
+    assert s2["status"] == "OK" and s2["true_relres"].max() <= 1e-10
+    assert s2["reliable_updates"] > 1
+    n = 12 * int(np.prod(L))
+    for j in range(len(sig)):
+        assert rel_fro(host(X2[j]).reshape(n, m), host(X0[j]).reshape(n, m)) <= 1e-8, j

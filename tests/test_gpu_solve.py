@@ -218,3 +218,22 @@ def test_full_size_fp64_16x16x16x16():
         tr = oracle.true_relres(op, B.reshape(w.n, w.m), [w.shifts[j]], X[j].reshape(1, w.n, w.m))
         assert tr.max() <= w.tol
         np.testing.assert_allclose(tr[:, 0], st["true_relres"][:, j], rtol=1e-5)
+
+
+@pytest.mark.parametrize("m,s,window", [(12, 10, 2), (16, 16, 3), (9, 13, 2)])
+def test_wide_outputs_over_several_windows(m, s, window):
+    """Windows that form P_{j,end} with wide outputs (m + b_end complex
+    outputs: 3 or 4 matrix-core tiles) and more shifts than one launch takes
+    (the shift set is split across launches), against the oracle's
+    step-wise iterates at a fixed step count."""
+    L, k = (4, 4, 4, 4), 7
+    sig = tuple(np.logspace(-3, 0, s))
+    announce("solve wide windows", L, m, s, window)
+    kappa = 0.124
+    U, B = _problem(L, m, 880 + m, "haar")
+    n = 12 * int(np.prod(L))
+    ref = oracle.dsbcg(_op(L, U, kappa), B.reshape(n, m), sig, 1e-30, fixed_iters=k)
+    X, st = _gpu_solve(L, U, kappa, B, sig, 1e-30, fixed_iters=k, window=window)
+    assert st["block_iters"] == k
+    for j in range(s):
+        assert rel_fro(X[j].reshape(n, m), ref.X[j]) <= 1e-10, j
