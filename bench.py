@@ -445,6 +445,8 @@ def main():
 
     # the stencil on the solve's block width
     stencil = stencil_rate(dsb, h, dU, w, head["rank0"], args.precision, args.stencil_calls)
+    other = "fp64" if args.precision == "fp32" else "fp32"
+    stencil_other = stencil_rate(dsb, h, dU, w, head["rank0"], other, args.stencil_calls) if args.compare else None
 
     # dominant kernel of the headline form (by time inside the timed region)
     kern = {k: v for k, v in head["kernels"].items() if v["ms_per_solve"] > 0}
@@ -487,6 +489,7 @@ def main():
                    "form": args.precision},
         "forms": results,
         "stencil": stencil,
+        "stencil_" + other: stencil_other,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "grad": grad,
