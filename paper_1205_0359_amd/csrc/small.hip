@@ -475,79 +475,101 @@ hipError_t small_prep_alpha(SmallState *st, const zd *alpha_raw, hipStream_t str
 // Column k of W is kept when the Schur remainder d_k of W^H W exceeds
 // (tau_W ||T||_est)^2; R1 gets one row per kept column.
 // ---------------------------------------------------------------------------
-__global__ void chol_deflate_kernel(SmallState *st, StepReport *rep,
-                                    const zd *__restrict__ alpha_raw, const zd *__restrict__ G,
-                                    double tau_W) {
-    if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepReport *rep,
+                                                          const zd *__restrict__ alpha_raw,
+                                                          const zd *__restrict__ G, double tau_W) {
+    // the inputs go to LDS with every lane, the sequential factorisation
+    // then runs on LDS only (thread 0), and the results leave in parallel
+    __shared__ zd Gs[256], R[256], C1s[256];
+    __shared__ double nrm[2];
+    __shared__ int piv[16], nks, skip;
+    const int t = threadIdx.x;
     const int b = st->b, bp = st->bp;
-    // ||T||_est from alpha_i and beta_i
     (void)alpha_raw;
-    double na = 0.0;
-    for (int r = 0; r < b; ++r)
-        for (int c = 0; c < b; ++c) na += norm2(st->alpha[r * 16 + c]);
-    double nb = 0.0;
-    if (bp > 0)
-        for (int r = 0; r < b; ++r)
-            for (int c = 0; c < bp; ++c) nb += norm2(st->beta[r * 16 + c]);
-    double test = st->test;
-    test = fmax(test, sqrt(na));
-    test = fmax(test, sqrt(nb));
-    st->test = test;
-    const double thr = tau_W * test;
-
-    zd R[256];
-    int piv[16];
-    int nk = 0;
-    for (int k = 0; k < b; ++k) {
-        double d = G[k * 16 + k].x;
-        for (int r = 0; r < nk; ++r) {
-            zd v = G[piv[r] * 16 + k];
-            for (int q = 0; q < r; ++q) v = v - conj(R[q * 16 + piv[r]]) * R[q * 16 + k];
-            v = zdivr(v, R[r * 16 + piv[r]].x);
-            R[r * 16 + k] = v;
-            d -= norm2(v);
-        }
-        if (d > thr * thr) {
-            for (int c = 0; c < b; ++c) R[nk * 16 + c] = mk<double>(0, 0);
-            for (int q = 0; q < nk; ++q) { /* rows above keep their entries */ }
-            R[nk * 16 + k] = mk<double>(sqrt(d), 0.0);
-            piv[nk] = k;
-            ++nk;
-        } else {
-            // dropped column: its entries in the kept rows stay as computed
-        }
+    // ||T||_est from alpha_i and beta_i
+    double na = 0.0, nb = 0.0;
+    for (int e = t; e < 256; e += 64) {
+        Gs[e] = G[e];
+        const int r = e / 16, c = e - r * 16;
+        if (r < b && c < b) na += norm2(st->alpha[e]);
+        if (r < b && c < bp) nb += norm2(st->beta[e]);
+        R[e] = mk<double>(0, 0);
+        C1s[e] = mk<double>(0, 0);
     }
-    // R has nk rows; zero the entries left of each pivot
-    for (int r = 0; r < nk; ++r)
-        for (int c = 0; c < piv[r]; ++c) R[r * 16 + c] = mk<double>(0, 0);
-    for (int r = 0; r < nk; ++r)
-        for (int c = 0; c < b; ++c) st->R1[r * 16 + c] = R[r * 16 + c];
-    // C1 = E_K R_KK^{-1}: R_KK (nk x nk) is R restricted to the pivot columns
-    for (int e = 0; e < 256; ++e) st->C1[e] = mk<double>(0, 0);
-    for (int q = 0; q < nk; ++q) {
-        // column q of R_KK^{-1}: solve R_KK x = e_q (upper triangular)
-        zd x[16];
-        for (int r = nk - 1; r >= 0; --r) {
-            zd v = (r == q) ? mk<double>(1, 0) : mk<double>(0, 0);
-            for (int c = r + 1; c < nk; ++c) v = v - R[r * 16 + piv[c]] * x[c];
-            x[r] = zdivr(v, R[r * 16 + piv[r]].x);
+    for (int off = 32; off > 0; off >>= 1) {
+        na += __shfl_xor(na, off, 64);
+        nb += __shfl_xor(nb, off, 64);
+    }
+    if (t == 0) {
+        nrm[0] = na;
+        nrm[1] = nb;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double test = st->test;
+        test = fmax(test, sqrt(nrm[0]));
+        test = fmax(test, sqrt(nrm[1]));
+        st->test = test;
+        const double thr = tau_W * test;
+        int nk = 0;
+        for (int k = 0; k < b; ++k) {
+            double d = Gs[k * 16 + k].x;
+            for (int r = 0; r < nk; ++r) {
+                zd v = Gs[piv[r] * 16 + k];
+                for (int q = 0; q < r; ++q) v = v - conj(R[q * 16 + piv[r]]) * R[q * 16 + k];
+                v = zdivr(v, R[r * 16 + piv[r]].x);
+                R[r * 16 + k] = v;
+                d -= norm2(v);
+            }
+            if (d > thr * thr) {
+                // a kept column: new row nk of R (dropped columns keep the
+                // entries computed for the rows above)
+                for (int c = 0; c < b; ++c) R[nk * 16 + c] = mk<double>(0, 0);
+                R[nk * 16 + k] = mk<double>(sqrt(d), 0.0);
+                piv[nk] = k;
+                ++nk;
+            }
         }
-        for (int r = 0; r < nk; ++r) st->C1[piv[r] * 16 + q] = x[r];
+        // R has nk rows; zero the entries left of each pivot
+        for (int r = 0; r < nk; ++r)
+            for (int c = 0; c < piv[r]; ++c) R[r * 16 + c] = mk<double>(0, 0);
+        // C1 = E_K R_KK^{-1}: R_KK (nk x nk) is R restricted to the pivot columns
+        for (int q = 0; q < nk; ++q) {
+            // column q of R_KK^{-1}: solve R_KK x = e_q (upper triangular)
+            zd x[16];
+            for (int r = nk - 1; r >= 0; --r) {
+                zd v = (r == q) ? mk<double>(1, 0) : mk<double>(0, 0);
+                for (int c = r + 1; c < nk; ++c) v = v - R[r * 16 + piv[c]] * x[c];
+                x[r] = zdivr(v, R[r * 16 + piv[r]].x);
+            }
+            for (int r = 0; r < nk; ++r) C1s[piv[r] * 16 + q] = x[r];
+        }
+        // condition of the kept columns scaled to unit norm, Rs = R_KK D^{-1}:
+        // ||Rs||_F^2 = nk and Rs^{-1} = D R_KK^{-1} (rows scaled by the norms)
+        double inv2 = 0.0;
+        for (int c = 0; c < nk; ++c) {
+            double d2 = 0.0;
+            for (int r = 0; r <= c; ++r) d2 += norm2(R[r * 16 + piv[c]]);
+            double row2 = 0.0;
+            for (int q = 0; q < nk; ++q) row2 += norm2(C1s[piv[c] * 16 + q]);
+            inv2 += d2 * row2;
+        }
+        nks = nk;
+        skip = (nk > 0 && nk * inv2 <= 16.0 * 16.0) ? 1 : 0;
     }
-    // condition of the kept columns scaled to unit norm, Rs = R_KK D^{-1}:
-    // ||Rs||_F^2 = nk and Rs^{-1} = D R_KK^{-1} (rows scaled by the norms)
-    double inv2 = 0.0;
-    for (int c = 0; c < nk; ++c) {
-        double d2 = 0.0;
-        for (int r = 0; r <= c; ++r) d2 += norm2(R[r * 16 + piv[c]]);
-        double row2 = 0.0;
-        for (int q = 0; q < nk; ++q) row2 += norm2(st->C1[piv[c] * 16 + q]);
-        inv2 += d2 * row2;
+    __syncthreads();
+    const int nk = nks;
+    for (int e = t; e < 256; e += 64) {
+        const int r = e / 16;
+        if (r < nk) st->R1[e] = R[e];
+        st->C1[e] = C1s[e];
     }
-    st->skip_qr2 = (nk > 0 && nk * inv2 <= 16.0 * 16.0) ? 1 : 0;
-    rep->skip_qr2 = st->skip_qr2;
-    rep->bnew = nk;
-    for (int r = 0; r < 16; ++r) rep->kept[r] = (r < nk) ? piv[r] : -1;
+    if (t < 16) rep->kept[t] = (t < nk) ? piv[t] : -1;
+    if (t == 0) {
+        st->skip_qr2 = skip;
+        rep->skip_qr2 = skip;
+        rep->bnew = nk;
+    }
 }
 
 hipError_t small_chol_deflate(SmallState *st, StepReport *rep, const zd *alpha_raw, const zd *G,
@@ -564,20 +586,28 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
                                                      const zd *__restrict__ G2, double tol,
                                                      int freeze, const int32_t *__restrict__ list,
                                                      int nact) {
-    __shared__ zd R2[256], BN[256];
+    __shared__ zd R2[256], BN[256], G2s[256], C1s[256], R1s[256];
     __shared__ int fail;
     const int t = threadIdx.x;
     const int b = st->b, m = st->m;
     const int nk = rep->bnew;
+    const int skip = st->skip_qr2;
+    // inputs to LDS with every lane; the sequential part below reads LDS only
+    for (int e = t; e < 256; e += blockDim.x) {
+        G2s[e] = skip ? mk<double>(0, 0) : G2[e];
+        C1s[e] = st->C1[e];
+        R1s[e] = st->R1[e];
+        R2[e] = mk<double>(0, 0);
+    }
+    __syncthreads();
     if (t == 0) {
         fail = 0;
         // G2 = R2^H R2, R2 upper triangular (nk x nk); R2 = I when the
         // second pass was not run
-        for (int e = 0; e < 256; ++e) R2[e] = mk<double>(0, 0);
-        if (st->skip_qr2)
+        if (skip)
             for (int k = 0; k < nk; ++k) R2[k * 16 + k] = mk<double>(1, 0);
-        for (int k = 0; k < nk && !st->skip_qr2; ++k) {
-            double d = G2[k * 16 + k].x;
+        for (int k = 0; k < nk && !skip; ++k) {
+            double d = G2s[k * 16 + k].x;
             for (int q = 0; q < k; ++q) d -= norm2(R2[q * 16 + k]);
             if (!(d > 0.0)) {
                 fail = 1;
@@ -586,7 +616,7 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
             const double rd = sqrt(d);
             R2[k * 16 + k] = mk<double>(rd, 0.0);
             for (int c = k + 1; c < nk; ++c) {
-                zd v = G2[k * 16 + c];
+                zd v = G2s[k * 16 + c];
                 for (int q = 0; q < k; ++q) v = v - conj(R2[q * 16 + k]) * R2[q * 16 + c];
                 R2[k * 16 + c] = zdivr(v, rd);
             }
@@ -596,7 +626,7 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
         for (int r = 0; r < b; ++r) {
             zd x[16];
             for (int c = 0; c < nk; ++c) {
-                zd v = st->C1[r * 16 + c];
+                zd v = C1s[r * 16 + c];
                 for (int q = 0; q < c; ++q) v = v - x[q] * R2[q * 16 + c];
                 x[c] = zdivr(v, R2[c * 16 + c].x);
             }
@@ -607,7 +637,7 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
             for (int c = 0; c < 16; ++c) {
                 zd v = mk<double>(0, 0);
                 if (r < nk && c < b)
-                    for (int q = r; q < nk; ++q) v = v + R2[r * 16 + q] * st->R1[q * 16 + c];
+                    for (int q = r; q < nk; ++q) v = v + R2[r * 16 + q] * R1s[q * 16 + c];
                 BN[r * 16 + c] = v;
             }
     }

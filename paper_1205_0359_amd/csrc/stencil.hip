@@ -107,8 +107,8 @@ __device__ inline void direction(cx<R> acc[4][3], const Geom &g, int x, const in
 }
 
 // RESID: instead of storing y = D^H in (in = D x), accumulate the squared
-// norm of b - sigma x - y per column: wave w (column w) of workgroup q adds
-// its sum to partials[q * 16 + w].  One pass then yields the true residual
+// norm of b - sigma x - y per column: wave w (column w) of workgroup q
+// writes its sum to partials[w * (workgroups) + q].  One pass then yields the true residual
 // norms ||b - (sigma + A) x|| without writing A x.
 struct ResidOut {
     const zd *b;       // column-major, like in
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) r2 += __shfl_xor(r2, off, 64);
-        if (lane == 0 && wave < nb) ro.partials[(int64_t)blockIdx.x * 16 + wave] = r2;
+        if (lane == 0 && wave < nb) ro.partials[(int64_t)wave * gridDim.x + blockIdx.x] = r2;
         return;
     }
     if (!valid) return;
@@ -246,14 +246,15 @@ hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const
     return hipGetLastError();
 }
 
-// out[c] = sum over workgroups w < nwg of partials[w * 16 + c], c < nb, in a
+// out[c] = sum over workgroups w < nwg of partials[c * nwg + w], c < nb, in a
 // fixed order (one block per column).
 __global__ __launch_bounds__(256) void sum_columns_kernel(const double *__restrict__ partials, int nwg,
                                                           double *__restrict__ out) {
     __shared__ double red[256];
     const int c = blockIdx.x;
+    const double *p = partials + (int64_t)c * nwg;
     double s = 0.0;
-    for (int w = threadIdx.x; w < nwg; w += 256) s += partials[(int64_t)w * 16 + c];
+    for (int w = threadIdx.x; w < nwg; w += 256) s += p[w];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {

@@ -20,7 +20,7 @@ hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, 
 
 // True residual norms in one pass: with in = D x (column-major, nb columns,
 // FP64), accumulates |b - sigma x - D^H in|^2 per column and workgroup into
-// partials [wilson_resid_workgroups(g)][16]; sum_columns adds them up in a
+// partials [nb][wilson_resid_workgroups(g)]; sum_columns adds them up in a
 // fixed order into out[0..nb).
 int wilson_resid_workgroups(const Geom &g);
 hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const void *in, const void *b,
