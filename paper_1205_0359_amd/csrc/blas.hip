@@ -668,58 +668,30 @@ __device__ inline void stage_window(const WinArgs &a, int k, int64_t r0, char *b
 // wave of every group and the matrix-core work is the same on all four.
 // The stages are double buffered: the copies of stage k + 1 run while stage
 // k multiplies; every operand of the multiply comes from LDS.
+// The staged window columns of one precision (a.colptr, a.ncolv, a.table),
+// multiplied into acc.  With issued, stage 0 is already on its way into the
+// first buffer; otherwise it is issued here once every wave is done with
+// the buffers.
 template <typename R, int NMT, int SPW>
-__global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
+__device__ inline void window_stages(const WinArgs &a, char *smem, int64_t r0, int lane, int wave, int nw,
+                                     int tile, int js0, int nsw, bool issued,
+                                     typename Mfma<R>::v4 (&acc)[SPW][NMT]) {
     typedef WinStage<R, NMT> S;
-    typedef typename Mfma<R>::v4 v4;
-    extern __shared__ __align__(16) char win_smem[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int grp = wave >> 2, tile = wave & 3;
-    const int64_t n = a.nrows;
-    const int64_t r0 = (int64_t)blockIdx.x * S::rows;
-    const int rl = lane & 15;           // row within the tile
-    const int part = (lane >> 4) & 1;   // real (0) or imaginary (1) part of the input
-    const int sel = lane >> 5;          // input column of the pair
-    const int64_t row = r0 + tile * 16 + rl;
-    const int js0 = grp * SPW;
-    const int nsw = min(SPW, a.nshift - js0);  // >= 1 by the launch shape
+    const int rl = lane & 15, part = (lane >> 4) & 1, sel = lane >> 5;
     const int npairs_v = (a.ncolv + 1) >> 1;
     const int nst = (npairs_v + S::pairs - 1) / S::pairs;
     const int buf_bytes = S::data_bytes + a.nshift * S::coef_bytes;
-
-    // the first stage's copies overlap the P_{j,i0} part
-    if (nst > 0) stage_window<R, NMT>(a, 0, r0, win_smem, lane, wave, nw);
-
-    v4 acc[SPW][NMT];
-#pragma unroll
-    for (int u = 0; u < SPW; ++u)
-#pragma unroll
-        for (int mt = 0; mt < NMT; ++mt) acc[u][mt] = v4{0, 0, 0, 0};
-
-    // inputs from P_{j,i0}, per shift; coefficients straight from the table
-    if (a.bp0 > 0) {
-#pragma unroll
-        for (int u = 0; u < SPW; ++u) {
-            if (u >= nsw) break;
-            const int js = js0 + u;
-            const R *P = (const R *)a.Pold + (size_t)2 * a.shifts[js] * a.pstride;
-            const R *tab = (const R *)a.table + (size_t)js * a.npairs * NMT * 64 + lane;
-            for (int pp = 0; pp < a.pairs_p; ++pp) {
-                const int p = 2 * pp + sel;
-                const R d = (p < a.bp0 && row < n) ? P[2 * ((int64_t)p * n + row) + part] : (R)0;
-#pragma unroll
-                for (int mt = 0; mt < NMT; ++mt)
-                    acc[u][mt] = Mfma<R>::mac(tab[(pp * NMT + mt) * 64], d, acc[u][mt]);
-            }
-        }
+    if (!issued) {
+        __syncthreads();
+        if (nst > 0) stage_window<R, NMT>(a, 0, r0, smem, lane, wave, nw);
     }
     for (int k = 0; k < nst; ++k) {
         // stage k has landed for every wave, and every wave is done with
         // stage k - 1, whose buffer takes stage k + 1
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (k + 1 < nst) stage_window<R, NMT>(a, k + 1, r0, win_smem + ((k + 1) & 1) * buf_bytes, lane, wave, nw);
-        const char *buf = win_smem + (k & 1) * buf_bytes;
+        if (k + 1 < nst) stage_window<R, NMT>(a, k + 1, r0, smem + ((k + 1) & 1) * buf_bytes, lane, wave, nw);
+        const char *buf = smem + (k & 1) * buf_bytes;
         const cx<R> *dat = (const cx<R> *)buf;
         const R *cof = (const R *)(buf + S::data_bytes) + (size_t)js0 * S::coef_elems + lane;
         const int npp = min(S::pairs, npairs_v - k * S::pairs);
@@ -738,6 +710,67 @@ __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
             }
         }
     }
+}
+
+template <typename R, int NMT, int SPW, bool TWO>
+__global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
+    typedef WinStage<R, NMT> S;
+    typedef typename Mfma<R>::v4 v4;
+    typedef typename Mfma<float>::v4 v4f;
+    extern __shared__ __align__(16) char win_smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int grp = wave >> 2, tile = wave & 3;
+    const int64_t n = a.nrows;
+    const int64_t r0 = (int64_t)blockIdx.x * S::rows;
+    const int rl = lane & 15;           // row within the tile
+    const int part = (lane >> 4) & 1;   // real (0) or imaginary (1) part of the input
+    const int sel = lane >> 5;          // input column of the pair
+    const int64_t row = r0 + tile * 16 + rl;
+    const int js0 = grp * SPW;
+    const int nsw = min(SPW, a.nshift - js0);  // >= 1 by the launch shape
+
+    // the first stage's copies overlap the P_{j,i0} part
+    if (a.ncolv > 0) stage_window<R, NMT>(a, 0, r0, win_smem, lane, wave, nw);
+
+    v4 acc[SPW][NMT];
+    v4f acc2[SPW][NMT];
+#pragma unroll
+    for (int u = 0; u < SPW; ++u)
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) {
+            acc[u][mt] = v4{0, 0, 0, 0};
+            acc2[u][mt] = v4f{0, 0, 0, 0};
+        }
+
+    // inputs from P_{j,i0}, per shift; coefficients straight from the table
+    if (a.bp0 > 0) {
+#pragma unroll
+        for (int u = 0; u < SPW; ++u) {
+            if (u >= nsw) break;
+            const int js = js0 + u;
+            const R *P = (const R *)a.Pold + (size_t)2 * a.shifts[js] * a.pstride;
+            const R *tab = (const R *)a.table + (size_t)js * a.npairs * NMT * 64 + lane;
+            for (int pp = 0; pp < a.pairs_p; ++pp) {
+                const int p = 2 * pp + sel;
+                const R d = (p < a.bp0 && row < n) ? P[2 * ((int64_t)p * n + row) + part] : (R)0;
+#pragma unroll
+                for (int mt = 0; mt < NMT; ++mt)
+                    acc[u][mt] = Mfma<R>::mac(tab[(pp * NMT + mt) * 64], d, acc[u][mt]);
+            }
+        }
+    }
+    window_stages<R, NMT, SPW>(a, win_smem, r0, lane, wave, nw, tile, js0, nsw, true, acc);
+    if (TWO) {
+        // the FP32 part of the window, in the same buffers
+        WinArgs b = a;
+        b.ncolv = a.ncolv2;
+        b.colptr = a.colptr2;
+        b.table = a.table2;
+        b.npairs = a.npairs2;
+        b.pairs_p = 0;
+        b.bp0 = 0;
+        window_stages<float, NMT, SPW>(b, win_smem, r0, lane, wave, nw, tile, js0, nsw, false, acc2);
+    }
     if (row >= n) return;
     // lane holds row `row`, complex outputs q = 8 mt + 2 g and q + 1 of each shift
     const int g = lane >> 4;
@@ -748,21 +781,28 @@ __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
         const uint32_t xm = a.xmask[j];
         const bool wp = a.pmask[j] != 0;
         zd *X = a.X + (size_t)j * a.xstride;
-        cx<R> *Pn = (cx<R> *)a.Pnew + (size_t)j * a.pstride;
 #pragma unroll
         for (int mt = 0; mt < NMT; ++mt) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int q = mt * 8 + 2 * g + h;
-                const R re = acc[u][mt][2 * h], im = acc[u][mt][2 * h + 1];
+                double re = (double)acc[u][mt][2 * h], im = (double)acc[u][mt][2 * h + 1];
+                if (TWO) {
+                    re += (double)acc2[u][mt][2 * h];
+                    im += (double)acc2[u][mt][2 * h + 1];
+                }
                 if (q < a.m) {
                     zd *x = X + (int64_t)q * n + row;
                     if (a.xinit)  // first window: X_j = increment (zero where never updated)
-                        *x = mk<double>((double)re, (double)im);
+                        *x = mk<double>(re, im);
                     else if ((xm >> q) & 1u)
-                        *x = mk<double>(x->x + (double)re, x->y + (double)im);
+                        *x = mk<double>(x->x + re, x->y + im);
                 } else if (wp && q - a.m < a.bend) {
-                    Pn[(int64_t)(q - a.m) * n + row] = mk<R>(re, im);
+                    const int64_t at = (int64_t)j * a.pstride + (int64_t)(q - a.m) * n + row;
+                    if (TWO)
+                        ((zf *)a.Pnew2)[at] = mk<float>((float)re, (float)im);
+                    else
+                        ((cx<R> *)a.Pnew)[at] = mk<R>((R)re, (R)im);
                 }
             }
         }
@@ -776,7 +816,13 @@ hipError_t window_launch(const WinArgs &a, hipStream_t st) {
     const dim3 block(64 * 4 * groups);
     const dim3 grid((unsigned)((a.nrows + S::rows - 1) / S::rows));
     const size_t lds = 2 * ((size_t)S::data_bytes + (size_t)a.nshift * S::coef_bytes);
-    hipLaunchKernelGGL((window_kernel<R, NMT, SPW>), grid, block, lds, st, a);
+    if constexpr (sizeof(R) == 8) {
+        if (a.ncolv2 > 0) {
+            hipLaunchKernelGGL((window_kernel<R, NMT, SPW, true>), grid, block, lds, st, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((window_kernel<R, NMT, SPW, false>), grid, block, lds, st, a);
     return hipGetLastError();
 }
 
@@ -800,7 +846,9 @@ hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
         a.m + a.bend < 1 || (a.m == 0 && a.xinit) ||
         a.bp0 < 0 || a.bp0 > 16 || a.ncolv < 0 || a.nmt < 1 || a.nmt > 4 ||
         a.nmt * 8 < a.m + a.bend || a.pairs_p != (a.bp0 + 1) / 2 ||
-        a.npairs != a.pairs_p + (a.ncolv + 1) / 2)
+        a.npairs != a.pairs_p + (a.ncolv + 1) / 2 ||
+        (a.ncolv2 > 0 && (!fp64 || !a.colptr2 || !a.table2 || a.npairs2 != (a.ncolv2 + 1) / 2 ||
+                          (a.bend > 0 && !a.Pnew2))))
         return hipErrorInvalidValue;
     if (a.nrows <= 0) return hipSuccess;
     // shifts per launch: at most 16 waves (4 groups) of SPW <= 4 shifts, FP64
@@ -817,6 +865,7 @@ hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
         b.nshift = std::min(max_cnt, a.nshift - js0);
         b.shifts = a.shifts + js0;
         b.table = (const char *)a.table + (size_t)js0 * a.npairs * a.nmt * 64 * esz;
+        if (a.ncolv2 > 0) b.table2 = (const char *)a.table2 + (size_t)js0 * a.npairs2 * a.nmt * 64 * sizeof(float);
         const int spw = b.nshift <= 4 ? 1 : (b.nshift <= 8 ? 2 : 4);
         hipError_t e;
 #define DSBCG_WIN(R)                                                        \

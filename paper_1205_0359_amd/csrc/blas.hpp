@@ -81,6 +81,16 @@ struct WinArgs {
     const int32_t *pmask;       // [s] nonzero: write P_{j,end}
     int xinit;                  // nonzero: X_j of the window's shifts is overwritten (every
                                 // column; the coefficients of columns never updated are zero)
+    // Optional second part of the same window in FP32 (a window that spans the
+    // switch to FP32 vectors, FP64 first part): its columns and table (no
+    // P_{j,i0} pairs) are contracted in FP32 and the two parts are added
+    // before X_j and P_{j,end} are written; P_{j,end} then goes to Pnew2 in
+    // FP32.  ncolv2 = 0: no second part.
+    int ncolv2;
+    const void *const *colptr2;
+    const void *table2;         // [nshift][npairs2][nmt][64] FP32
+    int npairs2;                // ceil(ncolv2 / 2)
+    void *Pnew2;                // FP32 P buffer, shift j at j * pstride
 };
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st);
 

@@ -780,7 +780,10 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         // so the first copy's source is not moved by the second segment
         colptr_host.clear();
         colptr_host.reserve((size_t)(i - i0) * wmax);
-        size_t tab_off = 0;  // elements (doubles) into the table buffer
+        size_t tab_off = 0;
+        WinArgs wfirst;  // FP64 part of a window across the switch
+        memset(&wfirst, 0, sizeof(wfirst));
+        double bytes_first = 0.0;  // elements (doubles) into the table buffer
         const int pnew = pcur ^ 1;
         for (size_t sg = 0; sg < seg.size(); ++sg) {
             const Seg &g = seg[sg];
@@ -894,17 +897,38 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             wa.xmask = WC.Wmask;
             wa.pmask = dpm;
             wa.xinit = (xfresh && sg == 0) ? 1 : 0;
+            if (seg.size() == 2 && sg == 0) {
+                // a window across the switch: the FP64 part waits for the FP32
+                // part and both run as one launch that writes X_j once
+                wfirst = wa;
+                bytes_first = (double)n * esz * (wt.ncolv + wt.nshift * wt.bp0);
+                continue;
+            }
+            if (seg.size() == 2) {
+                WinArgs w2 = wfirst;
+                w2.ncolv2 = wa.ncolv;
+                w2.colptr2 = wa.colptr;
+                w2.table2 = wa.table;
+                w2.npairs2 = wa.npairs;
+                w2.Pnew2 = h->P32[pnew].p;
+                // the iteration goes on in FP32: P_{j,end} (both parts) is written in FP32
+                const double bytes = bytes_first + (double)n * ((double)esz * (wt.ncolv + wt.nshift * wt.bend) +
+                                                                (w2.xinit ? 1.0 : 2.0) * sizeof(zd) * m * wt.nshift);
+                PROF_LAUNCH(h, prof_cls(kProfShift, true), bytes, st, window_apply(true, w2, st));
+                stt.reliable_updates += 1;
+                continue;
+            }
             const double bytes = (double)n * ((double)esz * (wt.ncolv + wt.nshift * (wt.bp0 + wt.bend)) +
                                               (wa.xinit ? 1.0 : 2.0) * sizeof(zd) * m * wt.nshift);
             PROF_LAUNCH(h, prof_cls(kProfShift, f64s), bytes, st, window_apply(f64s, wa, st));
             if (!f64s) stt.reliable_updates += 1;
         }
         xfresh = false;
-        if (sw > 0 && bend > 0)
-            // the iteration goes on in FP32: P_{j,i} = FP64 part (+ FP32 part), kept in FP32
+        if (sw > 0 && bend > 0 && seg.size() == 1)
+            // the window ended at the switch step: P_{j,i} leaves the FP64 part in FP32
             for (int j : act)
                 CHK(copy(h, bend, cm((zd *)h->P[pnew].p + (int64_t)j * n * wmax, n, true),
-                         cm((zf *)h->P32[pnew].p + (int64_t)j * n * wmax, n, false), seg.size() == 2, st));
+                         cm((zf *)h->P32[pnew].p + (int64_t)j * n * wmax, n, false), false, st));
         // the host buffers are rewritten only after the next step's report,
         // which waits for the stream
         pcur = pnew;
