@@ -780,10 +780,10 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         // so the first copy's source is not moved by the second segment
         colptr_host.clear();
         colptr_host.reserve((size_t)(i - i0) * wmax);
-        size_t tab_off = 0;
-        WinArgs wfirst;  // FP64 part of a window across the switch
+        size_t tab_off = 0;  // elements (doubles) into the table buffer
+        WinArgs wfirst;      // FP64 part of a window across the switch
         memset(&wfirst, 0, sizeof(wfirst));
-        double bytes_first = 0.0;  // elements (doubles) into the table buffer
+        double bytes_first = 0.0;
         const int pnew = pcur ^ 1;
         for (size_t sg = 0; sg < seg.size(); ++sg) {
             const Seg &g = seg[sg];
