@@ -663,11 +663,6 @@ __device__ inline void stage_window(const WinArgs &a, int k, int64_t r0, char *b
     }
 }
 
-// Workgroup: 64 rows, 4 waves per group of up to SPW shifts; wave w takes the
-// 16-row tile w % 4 for the shifts of group w / 4.  Each SIMD thus holds one
-// wave of every group and the matrix-core work is the same on all four.
-// The stages are double buffered: the copies of stage k + 1 run while stage
-// k multiplies; every operand of the multiply comes from LDS.
 // The staged window columns of one precision (a.colptr, a.ncolv, a.table),
 // multiplied into acc.  With issued, stage 0 is already on its way into the
 // first buffer; otherwise it is issued here once every wave is done with
@@ -712,6 +707,12 @@ __device__ inline void window_stages(const WinArgs &a, char *smem, int64_t r0, i
     }
 }
 
+// Workgroup: 64 rows, 4 waves per group of up to SPW shifts; wave w takes the
+// 16-row tile w % 4 for the shifts of group w / 4.  Each SIMD thus holds one
+// wave of every group and the matrix-core work is the same on all four.
+// The stages are double buffered: the copies of stage k + 1 run while stage
+// k multiplies; every operand of the multiply comes from LDS.  TWO: a second
+// part of the window in FP32 (see WinArgs).
 template <typename R, int NMT, int SPW, bool TWO>
 __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
     typedef WinStage<R, NMT> S;
