@@ -181,6 +181,24 @@ def test_shift_invariance(small):
         assert np.array_equal(r1.X[0], r.X[j])
 
 
+def test_step_count_set_by_the_worst_conditioned_shift(small):
+    """One Lanczos process serves every shift, so the run takes as many block
+    steps as the worst conditioned system alone needs (Sec. 4: the mvm count
+    depends only on the worst conditioned system); larger shifts converge
+    earlier and stop being updated."""
+    w, U, B, op, A = small
+    sig = list(w.shifts)
+    worst = min(sig)
+    r_all = oracle.dsbcg(op, B, sig, w.tol)
+    r_worst = oracle.dsbcg(op, B, [worst], w.tol)
+    r_best = oracle.dsbcg(op, B, [max(sig)], w.tol)
+    assert r_all.iters == r_worst.iters
+    assert r_best.iters < r_worst.iters
+    # the easiest shift froze no later than its own run stopped
+    jb = sig.index(max(sig))
+    assert r_all.frozen_at[:, jb].max() == r_best.iters
+
+
 def test_duplicated_columns_deflate(small):
     w, U, B, op, A = small
     V = w.V
