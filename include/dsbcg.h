@@ -105,7 +105,8 @@ typedef struct {
     int32_t qr2_skipped;      /* block steps whose second CholQR pass was not needed (the
                                  unit-norm kept columns had condition number <= 16) */
     double main_relres_max;   /* largest FP64 true relative residual after the main phase,
-                                 before any re-solve (0 when true residuals were not formed) */
+                                 before any re-solve (0 when true residuals were not formed;
+                                 -1 in the FP64 partial-fraction form) */
     int64_t mvms;             /* applications of A to one vector by the method: sum of the
                                  block widths of the main phase and of refinement solves */
     double *est_relres;       /* host [s*m] (index j*m + l) or NULL: last estimated
@@ -121,7 +122,11 @@ void dsbcg_default_opts(dsbcg_opts *opts);
  * extent >= 2, volume < 2^31 / 12).  Binds the handle to the current device. */
 int dsbcg_create(const int32_t *L, dsbcg_handle *out);
 
-/* Release the handle and its workspace (NULL is ignored). */
+/* Release the handle and its workspace (NULL is ignored).  A solve keeps its
+ * workspace for the next call; with the automatic window length the kept
+ * Lanczos blocks can take about three quarters of the device memory that
+ * was free at the solve, so release the handle (or cap opts.window) when
+ * the memory is needed elsewhere. */
 void dsbcg_destroy(dsbcg_handle h);
 
 /* Export the neighbour table the kernels use: host_out[V][8] receives the
