@@ -502,7 +502,13 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
     CHK(ensure_ws(h, h->R3, blk));
     Ts ts{h, true, st, n};
     std::vector<double> bn(m);
+    std::vector<double> bn_all((size_t)s * m, 0.0);  // ||b_l|| of shift j's block
     std::vector<zd> cf(512, mk<double>(0, 0));
+    // residual sums of every shift land in sums[j * 16 + l]; one copy at the end
+    const int nwg = wilson_resid_workgroups(h->g);
+    CHK(ensure_ws(h, h->rpart, ((size_t)nwg * 16 + 16 * (size_t)kS) * sizeof(double)));
+    double *part = (double *)h->rpart.p, *sums = part + (size_t)nwg * 16;
+    bool batched = false;
     for (int j = 0; j < s; ++j) {
         if (keep_j >= 0 && j != keep_j) continue;
         if (j == 0 || bstride != 0 || keep_j >= 0) {
@@ -527,17 +533,11 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
             // D x_j, then one pass of D^H that forms |b - sigma x_j - A x_j|^2
             // per column without storing A x_j
             CHK(stencil(h, true, h->Ul64.p, kappa, xj, h->R2.p, m, false, st));
-            const int nwg = wilson_resid_workgroups(h->g);
-            CHK(ensure_ws(h, h->rpart, ((size_t)nwg * 16 + 16) * sizeof(double)));
-            double *part = (double *)h->rpart.p, *sums = part + (size_t)nwg * 16;
             PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, m, sizeof(zd)) + (double)h->g.V * 12 * m * sizeof(zd), st,
                         wilson_resid_norms(h->g, h->Ul64.p, kappa, h->R2.p, h->R0.p, xj, sigma[j], m, part, st));
-            PROF_LAUNCH(h, kProfSmall, 0.0, st, sum_columns(part, nwg, m, sums, st));
-            std::vector<double> r2(m);
-            HIPCHK(hipMemcpyAsync(r2.data(), sums, m * sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            for (int l = 0; l < m; ++l)
-                out[j * m + l] = bn[l] > 0 ? std::sqrt(std::max(r2[l], 0.0)) / bn[l] : 0.0;
+            PROF_LAUNCH(h, kProfSmall, 0.0, st, sum_columns(part, nwg, m, sums + 16 * j, st));
+            for (int l = 0; l < m; ++l) bn_all[(size_t)j * m + l] = bn[l];
+            batched = true;
             continue;
         }
         CHK(apply_A_cm(h, true, h->Ul64.p, kappa, xj, h->R2.p, h->R3.p, m, st));
@@ -565,6 +565,16 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
             const double r = std::sqrt(std::max(g[l * 16 + l].x, 0.0));
             out[j * m + l] = bn[l] > 0 ? r / bn[l] : 0.0;
         }
+    }
+    if (batched) {
+        std::vector<double> r2((size_t)16 * s);
+        HIPCHK(hipMemcpyAsync(r2.data(), sums, (size_t)16 * s * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int j = 0; j < s; ++j)
+            for (int l = 0; l < m; ++l) {
+                const double b = bn_all[(size_t)j * m + l];
+                out[j * m + l] = b > 0 ? std::sqrt(std::max(r2[(size_t)16 * j + l], 0.0)) / b : 0.0;
+            }
     }
     return DSBCG_OK;
 }
