@@ -165,3 +165,30 @@ def test_fp32_form_wide_outputs_over_several_windows():
     n = 12 * int(np.prod(L))
     for j in range(len(sig)):
         assert rel_fro(host(X2[j]).reshape(n, m), host(X0[j]).reshape(n, m)) <= 1e-8, j
+
+
+@pytest.mark.parametrize("L", [(5, 5, 5, 7), (3, 5, 7, 9)])
+def test_fp32_form_ragged_lattices(L):
+    """Lattices whose n = 12V is a multiple of none of the tile sizes (512-row
+    Gram tiles, 64-row window tiles, 64-site stencil workgroups): short
+    windows put the window across the switch and several FP32 windows on
+    ragged rows; every (l, j) reaches the FP64 true residual 1e-10 and the
+    solution agrees with the FP64 oracle's."""
+    announce("fp32 form ragged", L)
+    V, m = int(np.prod(L)), 5
+    U = inputs.make_links(L, "haar", inputs.rng_for(883, 0))
+    B = inputs.gaussian_rhs(inputs.rng_for(883, 1), V, m)
+    sig = (1e-4, 1e-2, 0.5)
+    h = dsb.Handle(L)
+    X, st = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=FP32, window=3, ru_interval=4)
+    assert st["status"] == "OK" and st["switch_iter"] > 1
+    assert st["reliable_updates"] > 1
+    assert st["true_relres"].max() <= 1e-10
+    n = 12 * V
+    op = _op(L, U, 0.124)
+    Xh = host(X).reshape(len(sig), n, m)
+    assert oracle.true_relres(op, B.reshape(n, m), sig, Xh).max() <= 1e-10
+    ref = oracle.dsbcg(op, B.reshape(n, m), sig, 1e-10)
+    for j in range(len(sig)):
+        # both are within cond * 1e-10 of the exact solution; cond(A) is ~20 here
+        assert rel_fro(Xh[j], ref.X[j]) <= 1e-8, j

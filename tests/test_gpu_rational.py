@@ -64,6 +64,21 @@ def test_fixed_iterations_match_oracle(window):
     assert np.all(st["true_relres"] == -1.0) and st["main_relres_max"] == -1.0
 
 
+def test_fixed_iterations_ragged_rows():
+    """n = 12V = 11340 is not a multiple of the 64-row tiles of the window and
+    partial-fraction kernels."""
+    L, m, sig, k = (3, 5, 7, 9), 5, (1e-3, 3e-2, 0.5), 9
+    announce("rational fixed ragged", L, m, sig, k)
+    kappa = 0.124
+    U, B = _problem(L, m, 901, "smooth")
+    n = 12 * int(np.prod(L))
+    ref = oracle.dsbcg(_op(L, U, kappa), B.reshape(n, m), sig, 1e-30, fixed_iters=k)
+    want = oracle.partial_fraction(B.reshape(n, m), ref.X, COEF4[:3], -0.4)
+    Y, st = _rational(L, U, kappa, B, sig, COEF4[:3], -0.4, 1e-30, fixed_iters=k, window=3)
+    assert st["block_iters"] == k
+    assert rel_fro(Y.reshape(n, m), want) <= 1e-10
+
+
 @pytest.mark.parametrize("window", [0, 2])
 def test_freezing_matches_solve_then_sum(window):
     """Systems that freeze at different steps contribute their final iterates:
