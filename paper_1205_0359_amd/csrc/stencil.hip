@@ -14,7 +14,10 @@
 // owns 64 consecutive sites and has one wave per column, so every lane of a
 // wave reads consecutive addresses.  Per direction the 64 forward links
 // U_mu(x) and backward links U_mu(x-mu) of the workgroup are staged once in
-// LDS and shared by all nb columns.
+// LDS and shared by all nb columns; the FP64 kernel for 5 to 7 columns
+// instead lets every wave read the links from global memory (the nb waves
+// read the same addresses, so the copies after the first come from cache)
+// and runs without barriers.
 //
 // Each hop first projects the neighbour spinor onto the two-spin subspace of
 // (1 -+ g_mu) (6 complex numbers), multiplies those by the SU(3) link and
@@ -41,10 +44,10 @@ namespace dsbcg {
 constexpr int kSitesPerWG = 64;
 
 // One hop: acc += P_s (W psi(y)) with W = link (ADJ false) or link^H.
-// psi is read at site y of column base `col`; the link matrix comes from LDS
-// as lnk[e * 64] for e = 0..8.
-template <typename R, int MU, int S, bool ADJ, bool SB>
-__device__ inline void hop_term(cx<R> acc[4][3], const cx<R> *lnk, const cx<R> *__restrict__ col,
+// psi is read at site y of column base `col`; element e = 0..8 of the link
+// matrix is lnk[e * ls] (ls = 64 for the LDS tile, V for the global copy).
+template <typename R, int MU, int S, bool ADJ>
+__device__ inline void hop_term(cx<R> acc[4][3], const cx<R> *lnk, int64_t ls, const cx<R> *__restrict__ col,
                                 int64_t V, int y) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -63,9 +66,9 @@ __device__ inline void hop_term(cx<R> acc[4][3], const cx<R> *lnk, const cx<R> *
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 if (ADJ)
-                    cmac_conj(t, lnk[(b * 3 + a) * kSitesPerWG], h[b]);
+                    cmac_conj(t, lnk[(b * 3 + a) * ls], h[b]);
                 else
-                    cmac(t, lnk[(a * 3 + b) * kSitesPerWG], h[b]);
+                    cmac(t, lnk[(a * 3 + b) * ls], h[b]);
             }
             u[a] = t;
         }
@@ -73,7 +76,6 @@ __device__ inline void hop_term(cx<R> acc[4][3], const cx<R> *lnk, const cx<R> *
             rebuild_add<R, MU, S, 0>(acc, u);
         else
             rebuild_add<R, MU, S, 1>(acc, u);
-        if (SB) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -89,7 +91,7 @@ __device__ inline void stage_links(cx<R> *lf, cx<R> *lb, const cx<R> *__restrict
     }
 }
 
-template <typename R, int MU, bool DAG, bool SB>
+template <typename R, int MU, bool DAG>
 __device__ inline void direction(cx<R> acc[4][3], const Geom &g, int x, const int c[4],
                                  const cx<R> *__restrict__ Ul, cx<R> *lf, cx<R> *lb,
                                  const cx<R> *__restrict__ col, bool valid, int lane, int wave,
@@ -101,9 +103,21 @@ __device__ inline void direction(cx<R> acc[4][3], const Geom &g, int x, const in
     stage_links<R>(lf, lb, Ul, g.V, MU, x, xb, valid, lane, wave, nwaves);
     __syncthreads();
     if (!valid) return;
-    hop_term<R, MU, SF, false, SB>(acc, lf + lane, col, g.V, xf);
-    if (SB) __builtin_amdgcn_sched_barrier(0);
-    hop_term<R, MU, -SF, true, SB>(acc, lb + lane, col, g.V, xb);
+    hop_term<R, MU, SF, false>(acc, lf + lane, kSitesPerWG, col, g.V, xf);
+    hop_term<R, MU, -SF, true>(acc, lb + lane, kSitesPerWG, col, g.V, xb);
+}
+
+// The same hops with the links read from the structure-of-arrays copy in
+// global memory (no LDS, no barrier).
+template <typename R, int MU, bool DAG>
+__device__ inline void direction_global(cx<R> acc[4][3], const Geom &g, int x, const int c[4],
+                                        const cx<R> *__restrict__ Ul, const cx<R> *__restrict__ col) {
+    constexpr int SF = DAG ? -1 : 1;
+    const int xf = hop(g, x, c, MU, true);
+    const int xb = hop(g, x, c, MU, false);
+    const cx<R> *u = Ul + (int64_t)MU * 9 * g.V;
+    hop_term<R, MU, SF, false>(acc, u + x, g.V, col, g.V, xf);
+    hop_term<R, MU, -SF, true>(acc, u + xb, g.V, col, g.V, xb);
 }
 
 // RESID: instead of storing y = D^H in (in = D x), accumulate the squared
@@ -120,15 +134,15 @@ struct ResidOut {
 // MAXT: the largest block the instantiation is launched with (64 threads per
 // column).  A 512-thread bound lets the FP64 kernel keep its 138 registers
 // without spills, at 3 waves per SIMD instead of 4 (1024-thread bound: 128
-// registers and spills).  SB: scheduling barriers between the half-spinor
-// terms, which hold the FP64 kernel at 126 registers (4 waves per SIMD, no
-// spills) at the price of less load overlap.  Measured on 32^3 x 64: the
-// plain 512-thread form is fastest for 1, 2, 4 and 8 columns; with 5 or 7
-// columns the resident blocks fill the SIMDs unevenly at 3 waves, and the
-// SB form is fastest.
+// registers and spills).  GL: links read from global memory by every wave
+// instead of staged in LDS behind two barriers per direction (FP64: 144
+// registers, 3 waves per SIMD).  Measured on 32^3 x 64 (FP64, D pass): with
+// 5, 6 and 7 columns the GL form takes 2.13, 2.82 and 3.17 ms against 2.43,
+// 3.05 and 3.62 ms; with 4 and 8 columns the LDS form is as fast or faster,
+// and so it is for FP32 at every width measured (2 to 12).
 inline bool small_bound(int nb) { return nb <= 8; }
-inline bool sched_split(bool fp64, int nb) { return fp64 && (nb == 5 || nb == 7); }
-template <typename R, bool DAG, bool RESID, int MAXT, bool SB>
+inline bool global_links(bool fp64, int nb) { return fp64 && nb >= 5 && nb <= 7; }
+template <typename R, bool DAG, bool RESID, int MAXT, bool GL>
 __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
                                                          R kappa, const cx<R> *__restrict__ in,
                                                          cx<R> *__restrict__ out, int nb, ResidOut ro) {
@@ -150,10 +164,19 @@ __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[s][a] = mk<R>(0, 0);
 
-    direction<R, 0, DAG, SB>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
-    direction<R, 1, DAG, SB>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
-    direction<R, 2, DAG, SB>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
-    direction<R, 3, DAG, SB>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    if (GL) {
+        if (valid) {
+            direction_global<R, 0, DAG>(acc, g, x, c, Ul, col);
+            direction_global<R, 1, DAG>(acc, g, x, c, Ul, col);
+            direction_global<R, 2, DAG>(acc, g, x, c, Ul, col);
+            direction_global<R, 3, DAG>(acc, g, x, c, Ul, col);
+        }
+    } else {
+        direction<R, 0, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+        direction<R, 1, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+        direction<R, 2, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+        direction<R, 3, DAG>(acc, g, x, c, Ul, lf, lb, col, valid, lane, wave, nwaves);
+    }
     if (RESID) {
         double r2 = 0.0;
         if (valid) {
@@ -208,17 +231,22 @@ hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, 
     const ResidOut none{nullptr, nullptr, 0.0, nullptr};
 #define DSBCG_W(R, D)                                                                              \
     do {                                                                                           \
-        if (sched_split(fp64, nb))                                                                 \
-            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512, true>), grid, block, 0, st, g,     \
-                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
-        else if (small_bound(nb))                                                                  \
+        if (small_bound(nb))                                                                       \
             hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512, false>), grid, block, 0, st, g,    \
                                (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
         else                                                                                       \
             hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 1024, false>), grid, block, 0, st, g,   \
                                (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
     } while (0)
-    if (fp64) {
+    if (fp64 && global_links(fp64, nb)) {
+        // 5 to 7 columns: at most 448 threads
+        if (dagger)
+            hipLaunchKernelGGL((wilson_cm_kernel<double, true, false, 512, true>), grid, block, 0, st, g,
+                               (const zd *)Ul, kappa, (const zd *)in, (zd *)out, nb, none);
+        else
+            hipLaunchKernelGGL((wilson_cm_kernel<double, false, false, 512, true>), grid, block, 0, st, g,
+                               (const zd *)Ul, kappa, (const zd *)in, (zd *)out, nb, none);
+    } else if (fp64) {
         if (dagger) DSBCG_W(double, true);
         else DSBCG_W(double, false);
     } else {
@@ -237,7 +265,10 @@ hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const
     const dim3 grid((unsigned)wilson_resid_workgroups(g));
     const dim3 block(64 * nb);
     const ResidOut ro{(const zd *)b, (const zd *)x, sigma, partials};
-    if (small_bound(nb))
+    if (global_links(true, nb))
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, true>), grid, block, 0, st, g,
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro);
+    else if (small_bound(nb))
         hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, false>), grid, block, 0, st, g,
                            (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro);
     else

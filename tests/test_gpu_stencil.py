@@ -42,7 +42,8 @@ def test_apply_A_fp64(L, m):
     assert rel_max(Y, want) <= 1e-13
 
 
-@pytest.mark.parametrize("L,m", [((4, 4, 4, 4), 3), ((3, 4, 5, 6), 8), ((8, 6, 4, 10), 11)])
+@pytest.mark.parametrize("L,m", [((4, 4, 4, 4), 3), ((3, 4, 5, 6), 8), ((8, 6, 4, 10), 11),
+                                 ((5, 3, 7, 2), 5), ((3, 4, 5, 6), 6), ((8, 6, 4, 10), 7)])
 def test_apply_D_and_adjoint_fp64(L, m):
     announce("apply_D fp64", L, m)
     kappa = 0.13
@@ -111,3 +112,22 @@ def test_apply_A_full_size_sampled(name):
         want = oracle.apply_A_sites(w.L, U, w.kappa, B, sites)
         assert rel_max(got, want) <= bound, prec
         del Y
+
+
+def test_apply_A_full_size_five_columns():
+    """32^3 x 64 with the five columns of the deflated block (the FP64 kernel
+    that reads its links from global memory): the oracle evaluates A at 48
+    sampled sites."""
+    w = inputs.WORKLOADS["haar32^3x64_m8r5_s10"]
+    announce("apply_A full size, 5 columns", w.name)
+    U, B = w.make()
+    B5 = np.ascontiguousarray(B[..., [0, 1, 3, 4, 6]])
+    del B
+    h = dsb.Handle(w.L)
+    rng = np.random.default_rng(6)
+    sites = np.concatenate([[0, w.V - 1], rng.integers(0, w.V, 46)])
+    import torch
+    Y = dsb.dsbcg_apply_A(h, dev(U), w.kappa, dev(B5))
+    got = host(Y[torch.from_numpy(sites).to('cuda')])
+    want = oracle.apply_A_sites(w.L, U, w.kappa, B5, sites)
+    assert rel_max(got, want) <= 1e-13
