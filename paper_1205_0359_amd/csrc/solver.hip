@@ -339,8 +339,15 @@ int validate_geom(const int32_t *L) {
 
 int stencil(dsbcg_ctx *h, bool fp64, const void *Ul, double kappa, const void *X, void *Y, int b,
             bool dagger, hipStream_t st) {
-    PROF_LAUNCH(h, prof_cls(kProfStencil, fp64), stencil_bytes(h->g, b, fp64 ? sizeof(zd) : sizeof(zf)), st,
-                wilson_apply(h->g, fp64, Ul, kappa, X, Y, b, dagger, st));
+    const size_t esz = fp64 ? sizeof(zd) : sizeof(zf);
+    const size_t col = (size_t)12 * h->g.V * esz;  // bytes per column
+    for (int c0 = 0; c0 < b;) {
+        const int k = stencil_chunk(fp64, b - c0);
+        PROF_LAUNCH(h, prof_cls(kProfStencil, fp64), stencil_bytes(h->g, k, esz), st,
+                    wilson_apply(h->g, fp64, Ul, kappa, (const char *)X + c0 * col, (char *)Y + c0 * col, k,
+                                 dagger, st));
+        c0 += k;
+    }
     return DSBCG_OK;
 }
 
@@ -533,8 +540,16 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
             // D x_j, then one pass of D^H that forms |b - sigma x_j - A x_j|^2
             // per column without storing A x_j
             CHK(stencil(h, true, h->Ul64.p, kappa, xj, h->R2.p, m, false, st));
-            PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, m, sizeof(zd)) + (double)h->g.V * 12 * m * sizeof(zd), st,
-                        wilson_resid_norms(h->g, h->Ul64.p, kappa, h->R2.p, h->R0.p, xj, sigma[j], m, part, st));
+            for (int c0 = 0; c0 < m;) {
+                const int k = stencil_chunk(true, m - c0);
+                const int64_t off = (int64_t)c0 * n;
+                PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, k, sizeof(zd)) + (double)h->g.V * 12 * k * sizeof(zd),
+                            st,
+                            wilson_resid_norms(h->g, h->Ul64.p, kappa, (const zd *)h->R2.p + off,
+                                               (const zd *)h->R0.p + off, (const zd *)xj + off, sigma[j], k,
+                                               part + (size_t)c0 * nwg, st));
+                c0 += k;
+            }
             PROF_LAUNCH(h, kProfSmall, 0.0, st, sum_columns(part, nwg, m, sums + 16 * j, st));
             for (int l = 0; l < m; ++l) bn_all[(size_t)j * m + l] = bn[l];
             batched = true;

@@ -142,6 +142,13 @@ struct ResidOut {
 // and so it is for FP32 at every width measured (2 to 12).
 inline bool small_bound(int nb) { return nb <= 8; }
 inline bool global_links(bool fp64, int nb) { return fp64 && nb >= 5 && nb <= 7; }
+
+// The FP64 pass costs 425 us per column at 5 columns (GL form) but 478-511 us
+// per column in one launch of 8-16 columns (32^3 x 64).  Launches of 5, then
+// one of 3-7 columns, were measured 6 % (8 columns), 9 % (12) and 16 % (16)
+// faster than one launch, with bitwise equal results.  FP32 costs about the
+// same per column at every width and is not split.
+int stencil_chunk(bool fp64, int nb) { return (fp64 && nb > 7) ? 5 : nb; }
 template <typename R, bool DAG, bool RESID, int MAXT, bool GL>
 __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
                                                          R kappa, const cx<R> *__restrict__ in,

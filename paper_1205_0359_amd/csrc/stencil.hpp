@@ -18,6 +18,11 @@ struct Geom {
 hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, const void *in,
                         void *out, int nb, bool dagger, hipStream_t st);
 
+// Columns of the first launch when a pass over nb columns is split into
+// launches (the remainder is split by the same rule): FP64 passes over more
+// than 7 columns run 5 columns at a time until at most 7 remain.
+int stencil_chunk(bool fp64, int nb);
+
 // True residual norms in one pass: with in = D x (column-major, nb columns,
 // FP64), accumulates |b - sigma x - D^H in|^2 per column and workgroup into
 // partials [nb][wilson_resid_workgroups(g)]; sum_columns adds them up in a
