@@ -193,6 +193,29 @@ def copy_calibration():
     torch.cuda.empty_cache()
 
 
+def copy_ceiling(reps=10):
+    """Device-to-device copy rate of a 1 GiB buffer (the runtime's copy
+    kernel), read plus written bytes per second: the practical HBM ceiling
+    that the stencil rate is also compared with."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBps": round(2 * COPY_BYTES / sec / 1e9, 1), "bytes_per_copy": COPY_BYTES,
+            "kind": "device-to-device copy of 1 GiB (runtime copy kernel), read + written bytes"}
+
+
 def source_digest(paths):
     h = hashlib.sha256()
     for pth in paths:
@@ -421,6 +444,7 @@ def main():
     log(f"[bench] inputs ready in {time.perf_counter() - t:.1f} s")
     dU = torch.from_numpy(U).to("cuda")
     dB = torch.from_numpy(B).to("cuda")
+    ceiling = copy_ceiling()
     h = dsb.Handle(w.L)
 
     forms = [args.precision]
@@ -458,6 +482,7 @@ def main():
     alg_per_launch = kern[dom]["bytes_per_launch"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "frac_of_copy": round(achieved / ceiling["GBps"], 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": alg_per_launch,
                 "avg_launch_us": round(kern[dom]["avg_launch_us"], 2)}
 
@@ -491,6 +516,7 @@ def main():
         "stencil": stencil,
         "stencil_" + other: stencil_other,
         "roofline": roofline,
+        "copy_ceiling": ceiling,
         "cpu_baseline": cpu,
         "grad": grad,
         "partial_fraction": rational,
