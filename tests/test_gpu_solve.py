@@ -237,3 +237,45 @@ def test_wide_outputs_over_several_windows(m, s, window):
     assert st["block_iters"] == k
     for j in range(s):
         assert rel_fro(X[j].reshape(n, m), ref.X[j]) <= 1e-10, j
+
+
+def test_mvm_ordering_of_table_1_through_the_library():
+    """The four methods of the paper's Table 1 (Sec. 4) as special cases of
+    dsbcg_solve (m = 1: shifted CG; s = 1: block CG per shift; m = s = 1: CG)
+    on a near-critical 3^4 field of the table's shape: every run converges,
+    takes the oracle's block-step count to within one step, and the mvm
+    totals are ordered as in the table."""
+    L, kappa, m = (3, 3, 3, 3), 0.125, 4
+    announce("table 1 ordering", L)
+    V = int(np.prod(L))
+    n = 12 * V
+    U = inputs.make_links(L, "smooth", inputs.rng_for(990, 0))
+    B = inputs.gaussian_rhs(inputs.rng_for(990, 1), V, m)
+    sig = tuple(np.logspace(-6, -1, 7))
+    tol = 1e-8
+    op = _op(L, U, kappa)
+    Bn = B.reshape(n, m)
+    h = dsb.Handle(L)
+    dU = dev(U)
+    cases = {
+        "DSBlockCG": [(list(range(m)), sig)],
+        "shiftedCG": [([l], sig) for l in range(m)],
+        "BlockCG": [(list(range(m)), (s,)) for s in sig],
+        "CG": [([l], (s,)) for l in range(m) for s in sig],
+    }
+    totals = {}
+    for name, runs in cases.items():
+        tot = 0
+        for cols, sh in runs:
+            Bc = np.ascontiguousarray(B[..., cols])
+            X, st = dsb.dsbcg_solve(h, dU, kappa, dev(Bc), sh, tol)
+            assert st["status"] == "OK" and st["true_relres"].max() <= tol, (name, cols, sh)
+            ref = oracle.dsbcg(op, np.ascontiguousarray(Bn[:, cols]), sh, tol)
+            assert abs(st["block_iters"] - ref.iters) <= 1, (name, cols, sh, st["block_iters"], ref.iters)
+            tot += st["mvms"]
+        totals[name] = tot
+    order = ("DSBlockCG", "shiftedCG", "BlockCG", "CG")
+    got = [totals[k] for k in order]
+    print("mvms", totals)
+    assert got == sorted(got) and len(set(got)) == 4
+    assert got[0] / got[1] < 0.8
