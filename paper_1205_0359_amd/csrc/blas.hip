@@ -775,6 +775,9 @@ __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
     if (row >= n) return;
     // lane holds row `row`, complex outputs q = 8 mt + 2 g and q + 1 of each shift
     const int g = lane >> 4;
+    // row = c V + x (spin-colour c, site x) is element (x, c) of the caller's layout
+    const int64_t Vs = n / 12, cs = row / Vs;
+    const int64_t api_row = ((row - cs * Vs) * 12 + cs) * a.m;
 #pragma unroll
     for (int u = 0; u < SPW; ++u) {
         if (u >= nsw) break;
@@ -794,10 +797,14 @@ __global__ __launch_bounds__(1024) void window_kernel(WinArgs a) {
                 }
                 if (q < a.m) {
                     zd *x = X + (int64_t)q * n + row;
-                    if (a.xinit)  // first window: X_j = increment (zero where never updated)
-                        *x = mk<double>(re, im);
-                    else if ((xm >> q) & 1u)
-                        *x = mk<double>(x->x + re, x->y + im);
+                    // first window: X_j = increment (zero where never updated)
+                    if (a.xinit || ((xm >> q) & 1u)) {
+                        const zd v = a.xinit ? mk<double>(re, im) : mk<double>(x->x + re, x->y + im);
+                        *x = v;
+                        if (a.Xapi) a.Xapi[(int64_t)j * n * a.m + api_row + q] = v;
+                    } else if (a.Xapi) {
+                        a.Xapi[(int64_t)j * n * a.m + api_row + q] = *x;
+                    }
                 } else if (wp && q - a.m < a.bend) {
                     const int64_t at = (int64_t)j * a.pstride + (int64_t)(q - a.m) * n + row;
                     if (TWO)
@@ -849,7 +856,8 @@ hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
         a.nmt * 8 < a.m + a.bend || a.pairs_p != (a.bp0 + 1) / 2 ||
         a.npairs != a.pairs_p + (a.ncolv + 1) / 2 ||
         (a.ncolv2 > 0 && (!fp64 || !a.colptr2 || !a.table2 || a.npairs2 != (a.ncolv2 + 1) / 2 ||
-                          (a.bend > 0 && !a.Pnew2))))
+                          (a.bend > 0 && !a.Pnew2))) ||
+        (a.Xapi && (a.nrows % 12 != 0 || a.m < 1)))
         return hipErrorInvalidValue;
     if (a.nrows <= 0) return hipSuccess;
     // shifts per launch: at most 16 waves (4 groups) of SPW <= 4 shifts, FP64

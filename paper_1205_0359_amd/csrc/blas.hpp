@@ -91,6 +91,10 @@ struct WinArgs {
     const void *table2;         // [nshift][npairs2][nmt][64] FP32
     int npairs2;                // ceil(ncolv2 / 2)
     void *Pnew2;                // FP32 P buffer, shift j at j * pstride
+    // Optional (nullptr: none): the window's shifts' X_j, every one of the m
+    // columns, also stored in the caller's layout [s][V][4][3][m]
+    // (complex128, V = nrows / 12, shift j at j * nrows * m).
+    zd *Xapi;
 };
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st);
 

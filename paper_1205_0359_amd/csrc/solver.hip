@@ -736,6 +736,8 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     std::vector<int32_t> act;
     std::vector<void *> colptr_host;
     bool xfresh = true;  // X has not been written yet in this solve
+    // shifts whose X_j the last window already stored in the caller's layout
+    std::vector<char> api_done(s, 0);
 
     auto active_list = [&](void) {
         act.clear();
@@ -775,6 +777,8 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             wset = act;
             return DSBCG_OK;
         }
+        // the last window of the solve also writes its shifts' X_j to the caller
+        zd *xapi = (!need_p && !rmode && Xapi) ? (zd *)Xapi : nullptr;
         std::vector<int32_t> pm(s, 0);
         if (need_p)
             for (int j : act) pm[j] = 1;
@@ -922,6 +926,8 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             wa.xmask = WC.Wmask;
             wa.pmask = dpm;
             wa.xinit = (xfresh && sg == 0) ? 1 : 0;
+            wa.Xapi = xapi;
+            const double api_bytes = xapi ? (double)n * sizeof(zd) * m * wt.nshift : 0.0;
             if (seg.size() == 2 && sg == 0) {
                 // a window across the switch: the FP64 part waits for the FP32
                 // part and both run as one launch that writes X_j once
@@ -937,18 +943,22 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                 w2.npairs2 = wa.npairs;
                 w2.Pnew2 = h->P32[pnew].p;
                 // the iteration goes on in FP32: P_{j,end} (both parts) is written in FP32
-                const double bytes = bytes_first + (double)n * ((double)esz * (wt.ncolv + wt.nshift * wt.bend) +
-                                                                (w2.xinit ? 1.0 : 2.0) * sizeof(zd) * m * wt.nshift);
+                const double bytes = bytes_first + api_bytes +
+                                     (double)n * ((double)esz * (wt.ncolv + wt.nshift * wt.bend) +
+                                                  (w2.xinit ? 1.0 : 2.0) * sizeof(zd) * m * wt.nshift);
                 PROF_LAUNCH(h, prof_cls(kProfShift, true), bytes, st, window_apply(true, w2, st));
                 stt.reliable_updates += 1;
                 continue;
             }
-            const double bytes = (double)n * ((double)esz * (wt.ncolv + wt.nshift * (wt.bp0 + wt.bend)) +
+            const double bytes = api_bytes +
+                                 (double)n * ((double)esz * (wt.ncolv + wt.nshift * (wt.bp0 + wt.bend)) +
                                               (wa.xinit ? 1.0 : 2.0) * sizeof(zd) * m * wt.nshift);
             PROF_LAUNCH(h, prof_cls(kProfShift, f64s), bytes, st, window_apply(f64s, wa, st));
             if (!f64s) stt.reliable_updates += 1;
         }
         xfresh = false;
+        if (xapi)
+            for (int j : wset) api_done[j] = 1;
         if (sw > 0 && bend > 0 && seg.size() == 1)
             // the window ended at the switch step: P_{j,i} leaves the FP64 part in FP32
             for (int j : act)
@@ -1124,8 +1134,9 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         CHK(copy(h, m, cm(h->Ycm.p, n, true), api(rat->Yapi, m), false, st));
     else
         for (int j = 0; j < s; ++j)
-            CHK(copy(h, m, cm((zd *)h->X.p + (int64_t)j * n * m, n, true),
-                     api((zd *)Xapi + (int64_t)j * n * m, m), false, st));
+            if (!api_done[j])
+                CHK(copy(h, m, cm((zd *)h->X.p + (int64_t)j * n * m, n, true),
+                         api((zd *)Xapi + (int64_t)j * n * m, m), false, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int j = 0; j < s; ++j)
         for (int l = 0; l < m; ++l) stt.est[j * m + l] = h->rep_host->est[j][l];
