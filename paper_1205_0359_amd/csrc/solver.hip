@@ -499,7 +499,7 @@ int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
 // read instead of Xapi.
 int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi, int64_t bstride,
                    const void *Xapi, int m, const double *sigma, int s, double *out, int keep_j,
-                   void *Rkeep, const zd *Xcm = nullptr) {
+                   void *Rkeep, const zd *Xcm = nullptr, const zd *Bcm = nullptr) {
     const int64_t n = 12 * (int64_t)h->g.V;
     const size_t blk = (size_t)n * m * sizeof(zd);
     CHK(ensure_common(h));
@@ -516,13 +516,17 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
     CHK(ensure_ws(h, h->rpart, ((size_t)nwg * 16 + 16 * (size_t)kS) * sizeof(double)));
     double *part = (double *)h->rpart.p, *sums = part + (size_t)nwg * 16;
     bool batched = false;
+    const zd *bj = (const zd *)h->R0.p;  // shift j's right-hand sides, column-major
     for (int j = 0; j < s; ++j) {
         if (keep_j >= 0 && j != keep_j) continue;
         if (j == 0 || bstride != 0 || keep_j >= 0) {
-            CHK(copy(h, m, api((const zd *)Bapi + (int64_t)j * bstride, m), cm(h->R0.p, n, true), false, st));
+            if (Bcm && keep_j < 0)
+                bj = Bcm + (bstride ? (int64_t)j * n * m : 0);
+            else
+                CHK(copy(h, m, api((const zd *)Bapi + (int64_t)j * bstride, m), cm(h->R0.p, n, true), false, st));
             TsArgs a = ts_args(n);
             a.K = 1;
-            a.X[0] = h->R0.p; a.bx[0] = m; a.C[0] = nullptr;
+            a.X[0] = bj; a.bx[0] = m; a.C[0] = nullptr;
             a.bout = m;
             a.gram = 3;  // column norms only
             CHK(ts.run_reduce(a, m, 4));
@@ -545,8 +549,8 @@ int true_residuals(dsbcg_ctx *h, hipStream_t st, double kappa, const void *Bapi,
                 const int64_t off = (int64_t)c0 * n;
                 PROF_LAUNCH(h, kProfStencil, stencil_bytes(h->g, k, sizeof(zd)) + (double)h->g.V * 12 * k * sizeof(zd),
                             st,
-                            wilson_resid_norms(h->g, h->Ul64.p, kappa, (const zd *)h->R2.p + off,
-                                               (const zd *)h->R0.p + off, (const zd *)xj + off, sigma[j], k,
+                            wilson_resid_norms(h->g, h->Ul64.p, kappa, (const zd *)h->R2.p + off, bj + off,
+                                               (const zd *)xj + off, sigma[j], k,
                                                part + (size_t)c0 * nwg, st));
                 c0 += k;
             }
@@ -1349,10 +1353,12 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
     std::vector<double> tr((size_t)s * m, 0.0);
     const bool want_true = (stats && stats->true_relres) || o.refine;
     if (want_true && status == DSBCG_OK) {
-        // the iterates are still column-major in h->X after one block solve
-        // over all shifts (not after the per-shift fallback)
+        // the iterates and the right-hand sides are still column-major in
+        // h->X and h->Bint after one block solve over all shifts (not after
+        // the per-shift fallback)
         const zd *xcm = !fallback ? (const zd *)h->X.p : nullptr;
-        CHK(true_residuals(h, st, kappa, B, bstride, X, m, sigma, s, tr.data(), -1, nullptr, xcm));
+        const zd *bcm = !fallback ? (const zd *)h->Bint.p : nullptr;
+        CHK(true_residuals(h, st, kappa, B, bstride, X, m, sigma, s, tr.data(), -1, nullptr, xcm, bcm));
         for (double v : tr) main_max = std::max(main_max, v);
         for (int round = 0; o.refine && o.fixed_iters <= 0 && round < 2; ++round) {
             bool any = false;
