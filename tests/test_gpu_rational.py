@@ -199,3 +199,27 @@ def test_full_size_16x16x16x16_matches_solve_then_sum():
     assert sy["status"] == "OK" and sy["block_iters"] == sx["block_iters"]
     want = oracle.partial_fraction(B.reshape(w.n, w.m), host(X).reshape(len(w.shifts), w.n, w.m), coef, 1.0)
     assert rel_fro(host(Y).reshape(w.n, w.m), want) <= 1e-11
+
+
+def test_full_size_32x32x32x64_matches_solve_then_sum():
+    """The 32^3 x 64 workload in the shape the benchmark times: the FP64
+    partial-fraction form takes the solve's step count and agrees with the
+    FP64 solve summed afterwards, c0 B + sum_j c_j X_j formed on the device
+    (the oracle pins both paths at small sizes)."""
+    import torch
+    w = inputs.WORKLOADS["haar32^3x64_m8r5_s10"]
+    announce("rational full size", w.name)
+    U, B = w.make()
+    coef = tuple(np.linspace(0.1, 1.0, len(w.shifts)))
+    h = dsb.Handle(w.L)
+    dU, dB = dev(U), dev(B)
+    X, sx = dsb.dsbcg_solve(h, dU, w.kappa, dB, w.shifts, w.tol)
+    Y, sy = dsb.dsbcg_solve_rational(h, dU, w.kappa, dB, w.shifts, coef, 1.0, w.tol)
+    h.close()
+    assert sy["status"] == "OK" and sy["block_iters"] == sx["block_iters"]
+    want = dB.clone()
+    for j, c in enumerate(coef):
+        want.add_(X[j], alpha=c)
+    del X
+    err = float(torch.linalg.vector_norm(Y - want) / torch.linalg.vector_norm(want))
+    assert err <= 1e-11, err

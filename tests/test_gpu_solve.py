@@ -279,3 +279,34 @@ def test_mvm_ordering_of_table_1_through_the_library():
     print("mvms", totals)
     assert got == sorted(got) and len(set(got)) == 4
     assert got[0] / got[1] < 0.8
+
+
+def test_fp64_form_full_size_32x32x32x64():
+    """The 32^3 x 64 workload (m = 8 of rank 5, 10 shifts) in the FP64 form,
+    as the benchmark times it: every (l, j) reaches the FP64 true residual
+    1e-10, the duplicated right-hand sides give equal solution columns, and
+    the oracle evaluates b - (sigma_j + A) x_j at sampled sites for the
+    smallest and largest shift (restricted to those sites it is at most
+    tol ||b_l||)."""
+    w = inputs.WORKLOADS["haar32^3x64_m8r5_s10"]
+    announce("fp64 form full size", w.name)
+    U, B = w.make()
+    h = dsb.Handle(w.L)
+    X, st = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(B), w.shifts, w.tol)
+    assert st["status"] == "OK" and st["rank0"] == 5
+    assert st["true_relres"].max() <= w.tol
+    h.close()  # the handle keeps most of the free memory as its workspace
+    for j in range(len(w.shifts)):
+        scale = float(X[j].abs().max())
+        assert float((X[j][..., 2] - X[j][..., 0]).abs().max()) <= 1e-13 * scale, j
+        assert float((X[j][..., 5] - X[j][..., 1]).abs().max()) <= 1e-13 * scale, j
+    rng = np.random.default_rng(8)
+    sites = np.concatenate([[0, w.V - 1], rng.integers(0, w.V, 30)])
+    bnorm = np.linalg.norm(B.reshape(-1, w.m), axis=0)
+    for j in (0, len(w.shifts) - 1):
+        Xh = host(X[j])
+        AX = oracle.apply_A_sites(w.L, U, w.kappa, Xh, sites)
+        R = B[sites] - w.shifts[j] * Xh[sites] - AX
+        on_sites = np.sqrt((np.abs(R) ** 2).sum(axis=(0, 1, 2)))
+        assert np.all(on_sites <= w.tol * bnorm), j
+        del Xh
