@@ -77,8 +77,14 @@ typedef struct {
     double tau_B;         /* initial deflation of B: drop column l when its remainder is
                              <= tau_B * ||b_l|| (default 0.1 * tol) */
     double tau_W;         /* in-iteration deflation: drop a new basis column whose remainder is
-                             <= tau_W * ||T||_est (default 1e-12; steps run with FP32 vectors
-                             use max(tau_W, 1e-8)) */
+                             <= tau_W * ||T||_est, ||T||_est the running maximum of the
+                             Frobenius norms of the alpha_i and beta_i (default 1e-12; steps
+                             run with FP32 vectors use max(tau_W, 1e-5)).  The remainder is
+                             the Schur complement of the Cholesky factorisation of W^H W;
+                             where that cannot resolve the decision (a remainder below 1e-10
+                             times the column's squared norm while the threshold lies below
+                             that level) the step's QR is redone by classical Gram-Schmidt
+                             applied twice, column by column, as for B */
     int32_t refine;       /* 1: after the main phase, re-solve (FP64) the shifts whose true
                              residual misses tol (default 1) */
     int32_t freeze;       /* 1: stop updating a system once its estimate reaches tol (default 1) */
@@ -113,6 +119,13 @@ typedef struct {
                                  relative residuals */
     double *true_relres;      /* host [s*m] or NULL: FP64 true relative residuals
                                  ||b_l - (sigma_j + A) x_{l,j}|| / ||b_l|| at return */
+    int32_t *widths;          /* host [widths_len] or NULL: width m_i of the Lanczos block of
+                                 main-phase step i at widths[i-1] (0 past the last step; not
+                                 filled when dsbcg_solve_multi falls back to one solve per
+                                 shift) */
+    int32_t widths_len;
+    int32_t qr_redone;        /* block steps whose deflated QR was redone column by column
+                                 (see dsbcg_opts.tau_W) */
 } dsbcg_stats;
 
 /* Fill opts with the defaults listed above. */

@@ -57,7 +57,9 @@ class dsbcg_stats(ctypes.Structure):
                 ("main_relres_max", ctypes.c_double),
                 ("mvms", ctypes.c_int64),
                 ("est_relres", ctypes.POINTER(ctypes.c_double)),
-                ("true_relres", ctypes.POINTER(ctypes.c_double))]
+                ("true_relres", ctypes.POINTER(ctypes.c_double)),
+                ("widths", ctypes.POINTER(ctypes.c_int32)), ("widths_len", ctypes.c_int32),
+                ("qr_redone", ctypes.c_int32)]
 
 
 _lib = None
@@ -238,18 +240,27 @@ def default_opts(**kw) -> dsbcg_opts:
     return o
 
 
+_MAX_WIDTHS = 4096  # main-phase block widths reported per solve
+
+
 def _new_stats(s, m):
     import numpy as np
     est = np.zeros(s * m)
     true = np.zeros(s * m)
+    widths = np.zeros(_MAX_WIDTHS, dtype=np.int32)
     st = dsbcg_stats()
     st.est_relres = est.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     st.true_relres = true.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st.widths = widths.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    st.widths_len = _MAX_WIDTHS
+    st._widths_buf = widths  # kept alive with the struct
     return st, est, true
 
 
 def _stats_dict(code, st, est, true, s, m):
+    widths = st._widths_buf[:min(st.block_iters, _MAX_WIDTHS)].tolist()
     return {
+        "widths": widths, "qr_redone": st.qr_redone,
         "status": STATUS_NAMES.get(code, code),
         "block_iters": st.block_iters, "rank0": st.rank0, "deflations": st.deflations,
         "reliable_updates": st.reliable_updates, "refine_iters": st.refine_iters,

@@ -511,9 +511,10 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepRe
         test = fmax(test, sqrt(nrm[1]));
         st->test = test;
         const double thr = tau_W * test;
-        int nk = 0;
+        int nk = 0, unresolved = 0;
         for (int k = 0; k < b; ++k) {
-            double d = Gs[k * 16 + k].x;
+            const double gkk = Gs[k * 16 + k].x;
+            double d = gkk;
             for (int r = 0; r < nk; ++r) {
                 zd v = Gs[piv[r] * 16 + k];
                 for (int q = 0; q < r; ++q) v = v - conj(R[q * 16 + piv[r]]) * R[q * 16 + k];
@@ -521,6 +522,9 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepRe
                 R[r * 16 + k] = v;
                 d -= norm2(v);
             }
+            // a remainder at the rounding level of G_kk decides nothing when
+            // the threshold lies below that level
+            if (d <= kResolve * gkk && kResolve * gkk > thr * thr) unresolved = 1;
             if (d > thr * thr) {
                 // a kept column: new row nk of R (dropped columns keep the
                 // entries computed for the rows above)
@@ -556,6 +560,11 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepRe
         }
         nks = nk;
         skip = (nk > 0 && nk * inv2 <= 16.0 * 16.0) ? 1 : 0;
+        st->redo = unresolved;
+        if (unresolved) {
+            skip = 1;
+            rep->flags |= kFlagRedoQR;
+        }
     }
     __syncthreads();
     const int nk = nks;
@@ -588,6 +597,7 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
                                                      int nact) {
     __shared__ zd R2[256], BN[256], G2s[256], C1s[256], R1s[256];
     __shared__ int fail;
+    if (st->redo) return;  // uniform: the QR of this step is redone first
     const int t = threadIdx.x;
     const int b = st->b, m = st->m;
     const int nk = rep->bnew;
@@ -683,6 +693,63 @@ hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double to
 }
 
 // ---------------------------------------------------------------------------
+// Column-by-column deflated QR of W, used when the first CholQR pass cannot
+// resolve a drop decision (classical Gram-Schmidt twice, column order).
+// ---------------------------------------------------------------------------
+__global__ void wqr_begin_kernel(SmallState *st) {
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) st->R1[e] = mk<double>(0, 0);
+}
+
+hipError_t small_wqr_begin(SmallState *st, hipStream_t stream) {
+    hipLaunchKernelGGL(wqr_begin_kernel, dim3(1), dim3(256), 0, stream, st);
+    return hipGetLastError();
+}
+
+__global__ void wqr_decide_kernel(SmallState *st, StepReport *rep, const zd *__restrict__ c1,
+                                  const zd *__restrict__ c2, const zd *__restrict__ nu2, int k, int l,
+                                  double tau) {
+    if (threadIdx.x != 0) return;
+    for (int r = 0; r < k; ++r) {
+        const zd a = c1 ? c1[r * 16] : mk<double>(0, 0);
+        const zd bb = c2 ? c2[r * 16] : mk<double>(0, 0);
+        st->R1[r * 16 + l] = a + bb;
+    }
+    const double nu = sqrt(fmax(nu2[0].x, 0.0));
+    const bool keep = nu > tau * st->test;
+    if (keep) st->R1[k * 16 + l] = mk<double>(nu, 0.0);
+    st->coef[3][0] = mk<double>(keep ? 1.0 / nu : 0.0, 0.0);
+    rep->scalar[0] = nu;
+    rep->scalar[1] = keep ? 1.0 : 0.0;
+}
+
+hipError_t small_wqr_decide(SmallState *st, StepReport *rep, const zd *c1, const zd *c2, const zd *nu2,
+                            int k, int l, double tau, hipStream_t stream) {
+    if (k < 0 || k >= kS || l < 0 || l >= kS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wqr_decide_kernel, dim3(1), dim3(64), 0, stream, st, rep, c1, c2, nu2, k, l, tau);
+    return hipGetLastError();
+}
+
+__global__ void wqr_end_kernel(SmallState *st, StepReport *rep, int nk, WqrKept kept) {
+    const int t = threadIdx.x;
+    if (t < kS) rep->kept[t] = (t < nk) ? kept.col[t] : -1;
+    if (t == 0) {
+        // beta_{i+1} = R1: the second pass is not run, and finish_kernel
+        // takes R2 = I
+        st->skip_qr2 = 1;
+        rep->skip_qr2 = 1;
+        rep->bnew = nk;
+        st->redo = 0;
+        rep->flags &= ~kFlagRedoQR;
+    }
+}
+
+hipError_t small_wqr_end(SmallState *st, StepReport *rep, int nk, WqrKept kept, hipStream_t stream) {
+    if (nk < 0 || nk > kS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wqr_end_kernel, dim3(1), dim3(64), 0, stream, st, rep, nk, kept);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Initial deflated QR of B (classical Gram-Schmidt twice, column order).
 // ---------------------------------------------------------------------------
 __global__ void bnorms_kernel(SmallState *st, StepReport *rep, const zd *__restrict__ G, int c0,
@@ -752,6 +819,8 @@ __global__ void init_shifts_kernel(SmallState *st, StepReport *rep, int m1, int 
     st->m = m;
     st->s = s;
     st->test = 0.0;
+    st->redo = 0;
+    st->skip_qr2 = 0;
     for (int e = 0; e < 256; ++e) st->beta[e] = mk<double>(0, 0);
     for (int j = 0; j < s; ++j) {
         st->sigma[j] = sh.sigma[j];

@@ -31,13 +31,16 @@ struct SmallState {
     double test;         // running estimate of ||T||: max Frobenius norm of alpha_i, beta_i
     int32_t b, bp, m, s;
     int32_t skip_qr2;    // the first CholQR pass is orthogonal enough: no second pass
+    int32_t redo;        // the first CholQR pass could not resolve a drop decision: the
+                         // step's QR is redone column by column (small_wqr_*)
 };
 
 // What the host reads after every block step.
 struct StepReport {
     int32_t bnew;
     int32_t flags;       // bit 0: Delta not positive definite, bit 1: second QR pass failed,
-                         // bit 2: non-finite input
+                         // bit 2: non-finite input, bit 3: rank above 16, bit 4: the
+                         // step's QR must be redone column by column
     int32_t kept[kS];    // pivot columns kept by the deflated QR
     uint32_t colmask[kS];// per shift: columns still being updated
     double est[kS][kS];  // [j][l] estimated relative residual
@@ -45,7 +48,7 @@ struct StepReport {
     int32_t skip_qr2;    // the second CholQR pass of this step was not run
 };
 
-enum { kFlagNotHPD = 1, kFlagQR2 = 2, kFlagNonFinite = 4, kFlagRank = 8 };
+enum { kFlagNotHPD = 1, kFlagQR2 = 2, kFlagNonFinite = 4, kFlagRank = 8, kFlagRedoQR = 16 };
 
 // alpha_i = herm(raw Gram V_i^H W) into the state, and coef[1] = -alpha_i.
 hipError_t small_prep_alpha(SmallState *st, const zd *alpha_raw, hipStream_t stream);
@@ -119,11 +122,40 @@ hipError_t small_rational_table(const WinCoef wc, const WindowTable &wt, const i
 // norms of the scaled factor and its inverse): one CholQR pass then leaves
 // their loss of orthogonality at a few hundred units of rounding, and the
 // second pass is not run.
+//
+// The Schur remainder d_k = G_kk - sum |R_rk|^2 carries rounding of a few
+// units of G_kk, so a remainder below kResolve * G_kk does not decide a drop
+// against a threshold below that level.  Then the kernel sets st->redo and
+// the kFlagRedoQR report flag and skips the second pass; small_finish and the
+// basis scaling (whose launch takes &st->redo as its skip flag) do nothing,
+// and the host redoes the step's QR by classical Gram-Schmidt applied twice
+// on the tall-skinny block (small_wqr_*), which resolves a remainder to a
+// few units of rounding of ||w_k||.
+constexpr double kResolve = 1e-10;
+// Smallest drop threshold tau_W of block steps run with FP32 vectors.
+constexpr double kTauW32 = 1e-5;
 hipError_t small_chol_deflate(SmallState *st, StepReport *rep, const zd *alpha_raw, const zd *G,
                               double tau_W, hipStream_t stream);
 
+// Column-by-column deflated QR of W (classical Gram-Schmidt applied twice,
+// column order, the rule of the initial QR with the absolute threshold
+// tau * ||T||_est): small_wqr_begin clears R1; small_wqr_decide stores
+// column l's coefficients c1 + c2 on the k kept vectors in R1 and keeps the
+// column (new row k, R1[k][l] = ||w||) when ||w|| > tau * ||T||_est, writing
+// coef[3] = 1/||w|| and the decision into rep->scalar like small_cgs_decide;
+// small_wqr_end records the kept columns, sets beta_{i+1} = R1 (no second
+// pass) and clears the redo flag, after which small_finish runs as usual.
+hipError_t small_wqr_begin(SmallState *st, hipStream_t stream);
+hipError_t small_wqr_decide(SmallState *st, StepReport *rep, const zd *c1, const zd *c2, const zd *nu2,
+                            int k, int l, double tau, hipStream_t stream);
+struct WqrKept {
+    int32_t col[kS];
+};
+hipError_t small_wqr_end(SmallState *st, StepReport *rep, int nk, WqrKept kept, hipStream_t stream);
+
 // Second pass: R2 from G2 = Q1^H Q1, beta_{i+1} = R2 R1, C_j = -beta_{i+1} M_{j,i}
-// (= Z_{j,i+1}), estimated residuals and freezing; rotates b, bp.
+// (= Z_{j,i+1}), estimated residuals and freezing; rotates b, bp.  Does
+// nothing while st->redo is set.
 hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double tol, int freeze,
                         const int32_t *shift_list, int nact, hipStream_t stream);
 

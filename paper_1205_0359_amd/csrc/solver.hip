@@ -373,7 +373,9 @@ struct SolveStats {
     int32_t block_iters = 0, rank0 = 0, deflations = 0, reliable_updates = 0, refine_iters = 0;
     int32_t final_width = 0, switch_iter = 0;
     int32_t qr2_skipped = 0;  // steps whose second CholQR pass was not needed
+    int32_t qr_redone = 0;    // steps whose QR was redone column by column
     int64_t mvms = 0;
+    std::vector<int32_t> widths;  // block width of each main-phase step
     double est[kS * kS] = {};
 };
 
@@ -476,6 +478,86 @@ int initial_qr(dsbcg_ctx *h, int M, double tau_B, hipStream_t st, int *m1_out) {
     if (k > 0)
         HIPCHK(hipMemcpyAsync(h->V0.p, Qp, (size_t)n * k * sizeof(zd), hipMemcpyDeviceToDevice, st));
     *m1_out = k;
+    return DSBCG_OK;
+}
+
+// Deflated QR of the b columns of W (column-major, in the data precision of
+// the step) by classical Gram-Schmidt applied twice, column by column, in
+// column order, into Vn: column l is kept when its remainder exceeds
+// tau * ||T||_est (deflation of block vectors that became linearly
+// dependent, Sec. 3).  Runs when the first CholQR pass could not resolve a
+// drop decision (st->redo); leaves beta_{i+1} in R1 for small_finish and the
+// kept count in *nk_out.
+int redo_wqr(dsbcg_ctx *h, bool f64, const void *Wb, void *Vn, int b, double tau, hipStream_t st,
+             int *nk_out) {
+    const int64_t n = 12 * (int64_t)h->g.V;
+    const size_t esz = f64 ? sizeof(zd) : sizeof(zf);
+    Ts ts{h, f64, st, n};
+    SmallState *S = stp(h);
+    StepReport *rep = repp(h);
+    void *wp = h->wbuf.p;  // one column of either precision
+    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_wqr_begin(S, st));
+    WqrKept kept;
+    for (int c = 0; c < kS; ++c) kept.col[c] = -1;
+    int k = 0;
+    for (int l = 0; l < b; ++l) {
+        const void *wl = (const char *)Wb + (size_t)l * n * esz;
+        if (k > 0) {
+            // c1 = Q^H w
+            TsArgs a = ts_args(n);
+            a.K = 1;
+            a.X[0] = wl; a.bx[0] = 1; a.C[0] = nullptr;
+            a.bout = 1;
+            a.gram = 2; a.L = Vn; a.bl = k;
+            CHK(ts.run_reduce(a, k, 1));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st, small_neg_column(S, 0, red_slot(h, 1), k, st));
+            // w' = w - Q c1, c2 = Q^H w'
+            a = ts_args(n);
+            a.K = 2;
+            a.X[0] = wl; a.bx[0] = 1; a.C[0] = nullptr;
+            a.X[1] = Vn; a.bx[1] = k; a.C[1] = coef_slot(h, 0);
+            a.bout = 1;
+            a.out = wp;
+            a.gram = 2; a.L = Vn; a.bl = k;
+            CHK(ts.run_reduce(a, k, 2));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st, small_neg_column(S, 1, red_slot(h, 2), k, st));
+            // w'' = w' - Q c2, ||w''||^2
+            a = ts_args(n);
+            a.K = 2;
+            a.X[0] = wp; a.bx[0] = 1; a.C[0] = nullptr;
+            a.X[1] = Vn; a.bx[1] = k; a.C[1] = coef_slot(h, 1);
+            a.bout = 1;
+            a.out = wp;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, 1, 3));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        small_wqr_decide(S, rep, red_slot(h, 1), red_slot(h, 2), red_slot(h, 3), k, l, tau, st));
+        } else {
+            TsArgs a = ts_args(n);
+            a.K = 1;
+            a.X[0] = wl; a.bx[0] = 1; a.C[0] = nullptr;
+            a.bout = 1;
+            a.out = wp;
+            a.gram = 1;
+            CHK(ts.run_reduce(a, 1, 3));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        small_wqr_decide(S, rep, nullptr, nullptr, red_slot(h, 3), 0, l, tau, st));
+        }
+        CHK(read_report(h, st));
+        if (h->rep_host->scalar[1] > 0.5) {
+            // Q[:, k] = w'' / ||w''||
+            TsArgs a = ts_args(n);
+            a.K = 1;
+            a.X[0] = wp; a.bx[0] = 1; a.C[0] = coef_slot(h, 3);
+            a.bout = 1;
+            a.out = (char *)Vn + (size_t)k * n * esz;
+            CHK(ts.run(a, nullptr));
+            kept.col[k] = l;
+            ++k;
+        }
+    }
+    PROF_LAUNCH(h, kProfSmall, 0.0, st, small_wqr_end(S, rep, k, kept, st));
+    *nk_out = k;
     return DSBCG_OK;
 }
 
@@ -612,6 +694,10 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                void *Xapi, SolveStats &stt, hipStream_t st, const RatSpec *rat) {
     const int64_t V = h->g.V, n = 12 * V;
     const bool form32 = o.precision == DSBCG_FP32_RELIABLE;
+    // drop threshold of steps run with FP32 vectors: an exactly dependent
+    // direction keeps a remainder of a few FP32 units of ||w|| after
+    // orthogonalisation, which 1e-5 ||T||_est clears with a wide margin
+    const double tau32 = std::max(o.tau_W, kTauW32);
     const int M = bstride ? m * s : m;  // stacked right-hand-side columns
     const bool rmode = rat != nullptr;  // partial-fraction output, no X_j
     if (rmode && (form32 || bstride != 0))
@@ -1009,6 +1095,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         Ts ts{h, f64, st, n};
         iters = i;
         stt.mvms += b;
+        stt.widths.push_back(b);
         if ((int)v64.size() < i + 2) {
             v64.resize(i + 2, -1);
             v32.resize(i + 2, -1);
@@ -1070,8 +1157,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         }
         // first CholQR pass with deflation
         PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                    small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1),
-                                       lo ? std::max(o.tau_W, 1e-8) : o.tau_W, st));
+                    small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1), lo ? tau32 : o.tau_W, st));
         // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new
         // width.  Skipped on the device when the first pass sets skip_qr2.
         {
@@ -1087,23 +1173,41 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                     small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
                                  (int)act.size(), st));
         // V_{i+1} = W Rinv: the first bnew columns are the new block (the
-        // others are zero and never read)
+        // others are zero and never read).  Skipped on the device when the
+        // step's QR has to be redone column by column.
         {
             TsArgs a = ts_args(n);
             a.K = 1;
             a.X[0] = Wb; a.bx[0] = b; a.C[0] = S->Rinv;
             a.bout = b;
             a.out = Vn;
+            a.skip = &S->redo;
             CHK(ts.run(a, nullptr));
         }
         CHK(read_report(h, st));
-        const StepReport &R = *h->rep_host;
-        if (h->prof && R.skip_qr2) {
+        if (h->prof && h->rep_host->skip_qr2) {
             // the second-pass launch returned at once: it moved no data
             const int cls = prof_cls(kProfBlock, f64);
             h->prof_bytes[cls] -= (double)b * n * (f64 ? sizeof(zd) : sizeof(zf));
             h->prof_launches[cls] -= 1;
         }
+        if (h->rep_host->flags & kFlagRedoQR) {
+            // a drop decision below the resolution of the Gram matrix: the
+            // skipped scaling moved no data; redo the QR of W column by column
+            if (h->prof) {
+                const int cls = prof_cls(kProfBlock, f64);
+                h->prof_bytes[cls] -= 2.0 * b * n * (f64 ? sizeof(zd) : sizeof(zf));
+                h->prof_launches[cls] -= 1;
+            }
+            int nk = 0;
+            CHK(redo_wqr(h, f64, Wb, Vn, b, lo ? tau32 : o.tau_W, st, &nk));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
+                                     (int)act.size(), st));
+            CHK(read_report(h, st));
+            stt.qr_redone += 1;
+        }
+        const StepReport &R = *h->rep_host;
         stt.qr2_skipped += R.skip_qr2 ? 1 : 0;
         if (R.flags & kFlagNotHPD) {
             status = fail(DSBCG_ERR_NOT_HPD, "shifted block lost positive definiteness at step " +
@@ -1311,8 +1415,12 @@ void fill_stats(dsbcg_stats *stats, const SolveStats &stt, const double *tr, int
     stats->final_width = stt.final_width;
     stats->switch_iter = stt.switch_iter;
     stats->qr2_skipped = stt.qr2_skipped;
+    stats->qr_redone = stt.qr_redone;
     stats->main_relres_max = main_max;
     stats->mvms = stt.mvms;
+    if (stats->widths)
+        for (int32_t k = 0; k < stats->widths_len; ++k)
+            stats->widths[k] = k < (int32_t)stt.widths.size() ? stt.widths[k] : 0;
 }
 
 int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, int64_t bstride,
@@ -1344,6 +1452,8 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
             stt.mvms += one.mvms;
             stt.reliable_updates += one.reliable_updates;
             stt.qr2_skipped += one.qr2_skipped;
+            stt.qr_redone += one.qr_redone;
+            stt.deflations += one.deflations;
             stt.rank0 = std::max(stt.rank0, one.rank0);
             for (int l = 0; l < m; ++l) stt.est[j * m + l] = one.est[l];
         }

@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "Workload", "WORKLOADS", "rng_for", "complex_gaussian", "haar_su3",
     "smooth_su3", "unit_links", "gaussian_rhs", "z2_rhs", "deflating_rhs",
-    "make_links", "make_rhs", "volume",
+    "make_links", "make_rhs", "volume", "site_coordinates", "plane_wave",
 ]
 
 
@@ -167,6 +167,25 @@ def deflating_rhs(rng: np.random.Generator, noise_rng: np.random.Generator, V: i
     B[..., 5] = B[..., 1]
     B[..., 7] = B[..., 4] + 1e-12 * complex_gaussian(noise_rng, (V, 4, 3))
     return B
+
+
+def site_coordinates(L) -> np.ndarray:
+    """(V, 4) integer coordinates (x, y, z, t) of site x + Lx (y + Ly (z + Lz t))."""
+    V = volume(L)
+    idx = np.arange(V)
+    out = np.empty((V, 4), dtype=np.int64)
+    for d in range(4):
+        out[:, d] = idx % L[d]
+        idx = idx // L[d]
+    return out
+
+
+def plane_wave(L, nvec, chi: np.ndarray) -> np.ndarray:
+    """(V, 4, 3) field exp(i p.x) chi with p_mu = 2 pi nvec_mu / L_mu and chi a
+    (4, 3) spin-colour vector."""
+    p = 2.0 * np.pi * np.asarray(nvec, dtype=np.float64) / np.asarray(L, dtype=np.float64)
+    phase = np.exp(1j * (site_coordinates(L) @ p))
+    return phase[:, None, None] * np.asarray(chi, dtype=np.complex128)[None]
 
 
 def make_rhs(kind: str, V: int, m: int, rng: np.random.Generator,

@@ -1,5 +1,6 @@
 """The C-ABI library loads and exports every function include/dsbcg.h declares."""
 import ctypes
+import os
 import subprocess
 
 import pytest
@@ -38,10 +39,31 @@ def test_default_opts_and_argument_errors_without_a_device():
     assert lib.dsbcg_create(None, ctypes.byref(h)) == _lib.DSBCG_ERR_ARG
 
 
-def test_opts_struct_matches_header_layout():
-    # sizes of the C structs as the header lays them out on x86-64
-    assert ctypes.sizeof(_lib.dsbcg_opts) == 56
-    assert ctypes.sizeof(_lib.dsbcg_stats) == 64
+def test_opts_struct_matches_header_layout(tmp_path):
+    """The ctypes mirrors of dsbcg_opts and dsbcg_stats have the size and field
+    offsets that a C compiler gives the header's structs."""
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "dsbcg.h"', "int main(void) {"]
+    for cls in (_lib.dsbcg_opts, _lib.dsbcg_stats):
+        name = cls.__name__
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    include = os.path.dirname(_lib.HEADER_PATH)
+    subprocess.run(["gcc", "-I", include, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for cls in (_lib.dsbcg_opts, _lib.dsbcg_stats):
+        name = cls.__name__
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
 
 
 def test_single_hip_runtime_in_process():
