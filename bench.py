@@ -65,6 +65,10 @@ def parse():
                         "then exit")
     p.add_argument("--command", default="", help="command line recorded with --ingest-counters / "
                                                  "--summarize-stats")
+    p.add_argument("--cpu-sample-only", action="store_true",
+                   help="time the oracle sample with the threads the environment gives it, print "
+                        "its JSON and exit (run by the benchmark itself as a 1-thread child)")
+    p.add_argument("--cpu-sample-sites", type=int, default=1 << 17)
     return p.parse_args()
 
 
@@ -243,14 +247,14 @@ def run_form(dsb, h, dU, dB, w, prec, steps, warmup):
     X = None
     for k in range(warmup):
         log(f"[bench] warmup {prec} {k + 1}/{warmup}")
-        X, st = dsb.dsbcg_solve(h, dU, w.kappa, dB, w.shifts, w.tol, X=X, **kw)
+        X, st = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, X=X, **kw)
     torch.cuda.synchronize()
     dsb.dsbcg_profile_enable(h, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
     for k in range(steps):
-        X, st = dsb.dsbcg_solve(h, dU, w.kappa, dB, w.shifts, w.tol, X=X, **kw)
+        X, st = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, X=X, **kw)
         stats.append(st)
         log(f"[bench] {prec} step {k + 1}/{steps}: {st['block_iters']} block steps, "
             f"max true relres {st['true_relres'].max():.2e}")
@@ -292,12 +296,12 @@ def rational_rate(dsb, h, dU, dB, w, steps, warmup):
     Y = None
     for k in range(warmup):
         log(f"[bench] warmup partial-fraction fp64 {k + 1}/{warmup}")
-        Y, st = dsb.dsbcg_solve_rational(h, dU, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y)
+        Y, st = dsb.dsbcg_solve_rational(h, None, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y)
     torch.cuda.synchronize()
     dsb.dsbcg_profile_enable(h, True)
     t0 = time.perf_counter()
     for k in range(steps):
-        Y, st = dsb.dsbcg_solve_rational(h, dU, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y)
+        Y, st = dsb.dsbcg_solve_rational(h, None, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y)
         log(f"[bench] partial-fraction fp64 step {k + 1}/{steps}: {st['block_iters']} block steps, "
             f"max est relres {st['est_relres'].max():.2e}")
     torch.cuda.synchronize()
@@ -319,26 +323,44 @@ def rational_rate(dsb, h, dU, dB, w, steps, warmup):
     }
 
 
-def stencil_rate(dsb, h, dU, w, b, prec, calls):
-    """D^H D on b columns through dsbcg_apply_A; HIP-event kernel timing."""
+def stencil_rate(dsb, h, w, b, prec, calls):
+    """D^H D on b columns through dsbcg_apply_A with the handle's staged links.
+
+    Two rates of the same algorithmic bytes 2 V (2 b S + L) per application:
+    per call (HIP events on the call stream around `calls` back-to-back
+    dsbcg_apply_A calls, which include the conversion of X from and Y to the
+    caller's [V][4][3][b] layout) and per kernel (the two stencil passes
+    alone, from the library's HIP-event profiler)."""
     import torch
     from paper_1205_0359_amd import inputs
     Xb = torch.from_numpy(inputs.gaussian_rhs(inputs.rng_for(w.wid, 3), w.V, b)).to("cuda")
     Y = torch.empty_like(Xb)
     p = dsb.DSBCG_FP32_RELIABLE if prec == "fp32" else dsb.DSBCG_FP64
+    S, L = (96.0, 288.0) if prec == "fp32" else (192.0, 576.0)
+    alg = 2.0 * w.V * (2 * b * S + L)
     for _ in range(3):
-        dsb.dsbcg_apply_A(h, dU, w.kappa, Xb, Y, precision=p)
+        dsb.dsbcg_apply_A(h, None, w.kappa, Xb, Y, precision=p)
+    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(calls):
+        dsb.dsbcg_apply_A(h, None, w.kappa, Xb, Y, precision=p, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    call_s = e0.elapsed_time(e1) / 1e3 / calls
     dsb.dsbcg_profile_enable(h, True)
     for _ in range(calls):
-        dsb.dsbcg_apply_A(h, dU, w.kappa, Xb, Y, precision=p)
+        dsb.dsbcg_apply_A(h, None, w.kappa, Xb, Y, precision=p)
     torch.cuda.synchronize()
     prof = dsb.dsbcg_profile_read(h)["wilson_stencil." + ("f32" if prec == "fp32" else "f64")]
     dsb.dsbcg_profile_enable(h, False)
     del Xb, Y
     return {"GBps": prof["bytes"] / (prof["ms"] * 1e-3) / 1e9,
             "avg_launch_us": 1e3 * prof["ms"] / prof["launches"], "columns": b,
-            "layout": "[V][4][3][b] (API)"}
+            "per_call_GBps": alg / call_s / 1e9, "per_call_us": 1e6 * call_s,
+            "algorithmic_bytes_per_call": alg,
+            "layout": "[V][4][3][b] (API) in and out; links staged once (dsbcg_stage_links)"}
 
 
 def grad_rate(dsb, prec, reps=3):
@@ -376,15 +398,25 @@ def grad_rate(dsb, prec, reps=3):
             "note": "backward = adjoint block solve + X_j recompute + dL/dU, dL/dB, dL/dsigma kernels"}
 
 
-def cpu_baseline(w, gpu_iters, steps, max_sites=1 << 17):
-    """The oracle on the host cores, on a bounded sample of the workload.
+def cpu_sample_one_thread(w, steps, max_sites):
+    """The oracle sample in a child process limited to one thread (OpenMP and
+    BLAS), as the paper's runs were sequential (Sec. 4).  Started before this
+    process touches the GPU."""
+    import subprocess
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        env[k] = "1"
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-sample-only", "--workload", w.name,
+           "--cpu-steps", str(steps), "--cpu-sample-sites", str(max_sites)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        return {"unavailable": r.stderr[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
-    The sample keeps the workload's m, shifts, kappa, link and right-hand-side
-    kinds and its x, y, z extents, and cuts the t extent so that the volume is
-    at most max_sites; it times the deflated QR of B and `steps` block steps.
-    The oracle's cost per site is independent of the volume, so the per-step
-    time is scaled by V / V_sample and extrapolated to the GPU's step count.
-    """
+
+def cpu_sample(w, steps, max_sites):
+    """Seconds per block step and for the deflated QR of B, scaled to the full
+    workload, of the oracle on a slab of the workload (see cpu_baseline)."""
     import dataclasses
     import numpy as np
     import oracle
@@ -405,17 +437,46 @@ def cpu_baseline(w, gpu_iters, steps, max_sites=1 << 17):
     oracle.dsbcg(op, Bm, ws.shifts, ws.tol, fixed_iters=steps)
     t1 = time.perf_counter()
     scale = w.V / ws.V
-    t_qr = (marks[0] - t0) * scale
-    t_step = (t1 - marks[0]) / steps * scale
-    est = t_qr + gpu_iters * t_step
-    return {"value": m * len(w.shifts) / est, "unit": "systems/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": (f"FP64 oracle (C stencil with OpenMP, numpy block algebra) on a "
-                       f"{'x'.join(map(str, ws.L))} slab of the {w.name} workload (same m, shifts, "
-                       f"kappa, field kinds): deflated QR of B + {steps} block steps in "
-                       f"{t1 - t0:.1f} s, scaled by V/V_sample = {scale:g} and extrapolated to "
-                       f"the {gpu_iters} block steps the GPU took"),
-            "sample_seconds": round(t1 - t0, 2), "s_per_block_step": t_step, "s_initial_qr": t_qr}
+    return {"s_initial_qr": (marks[0] - t0) * scale, "s_per_block_step": (t1 - marks[0]) / steps * scale,
+            "sample_seconds": round(t1 - t0, 2), "slab": list(ws.L), "steps": steps, "scale": scale,
+            "threads": oracle.max_threads()}
+
+
+def cpu_baseline(w, gpu_iters, steps, max_sites=1 << 17, one_thread=None):
+    """The oracle on the host cores, on a bounded sample of the workload.
+
+    The sample keeps the workload's m, shifts, kappa, link and right-hand-side
+    kinds and its x, y, z extents, and cuts the t extent so that the volume is
+    at most max_sites; it times the deflated QR of B and `steps` block steps.
+    The oracle's cost per site is independent of the volume, so the per-step
+    time is scaled by V / V_sample and extrapolated to the GPU's step count.
+    """
+    smp = cpu_sample(w, steps, max_sites)
+    ms = w.m * len(w.shifts)
+    est = smp["s_initial_qr"] + gpu_iters * smp["s_per_block_step"]
+    out = {"value": ms / est, "unit": "systems/s", "cores": smp["threads"],
+           "kind": "oracle",
+           "method": "extrapolated: timed on a slab sample, scaled by volume and by block-step count",
+           "sample": (f"FP64 oracle (C stencil with OpenMP, numpy block algebra) on a "
+                      f"{'x'.join(map(str, smp['slab']))} slab of the {w.name} workload (same m, "
+                      f"shifts, kappa, field kinds): deflated QR of B + {steps} block steps in "
+                      f"{smp['sample_seconds']:.1f} s, scaled by V/V_sample = {smp['scale']:g} and "
+                      f"extrapolated to the {gpu_iters} block steps the GPU took"),
+           "sample_seconds": smp["sample_seconds"], "s_per_block_step": smp["s_per_block_step"],
+           "s_initial_qr": smp["s_initial_qr"]}
+    if one_thread is not None:
+        if "unavailable" in one_thread:
+            out["one_thread"] = one_thread
+        else:
+            est1 = one_thread["s_initial_qr"] + gpu_iters * one_thread["s_per_block_step"]
+            out["one_thread"] = {
+                "value": ms / est1, "unit": "systems/s", "cores": one_thread["threads"],
+                "sample": (f"the same oracle with one thread (OpenMP and BLAS), "
+                           f"{'x'.join(map(str, one_thread['slab']))} slab, deflated QR + "
+                           f"{one_thread['steps']} block step(s) in {one_thread['sample_seconds']:.1f} s, "
+                           f"extrapolated the same way"),
+                "s_per_block_step": one_thread["s_per_block_step"]}
+    return out
 
 
 def main():
@@ -430,6 +491,18 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
               "multi-GPU form in this build", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_sample_only:
+        from paper_1205_0359_amd import inputs
+        print(json.dumps(cpu_sample(inputs.WORKLOADS[args.workload], args.cpu_steps,
+                                    args.cpu_sample_sites)), flush=True)
+        return
+    one_thread = None
+    if args.cpu_baseline:
+        # before this process touches the GPU: one block step on a 32^3 x 2 slab
+        log("[bench] CPU oracle sample, one thread")
+        from paper_1205_0359_amd import inputs
+        wl = inputs.WORKLOADS[args.workload]
+        one_thread = cpu_sample_one_thread(wl, 1, 2 * wl.L[0] * wl.L[1] * wl.L[2])
     import numpy as np
     import torch
     import paper_1205_0359_amd as dsb
@@ -446,6 +519,9 @@ def main():
     dB = torch.from_numpy(B).to("cuda")
     ceiling = copy_ceiling()
     h = dsb.Handle(w.L)
+    # the gauge field is staged once, outside the timed region, as a caller
+    # solving many right-hand-side blocks on one configuration would do
+    dsb.dsbcg_stage_links(h, dU)
 
     forms = [args.precision]
     if args.compare:
@@ -468,9 +544,9 @@ def main():
         rational = rational_rate(dsb, h, dU, dB, w, args.steps, args.warmup)
 
     # the stencil on the solve's block width
-    stencil = stencil_rate(dsb, h, dU, w, head["rank0"], args.precision, args.stencil_calls)
+    stencil = stencil_rate(dsb, h, w, head["rank0"], args.precision, args.stencil_calls)
     other = "fp64" if args.precision == "fp32" else "fp32"
-    stencil_other = stencil_rate(dsb, h, dU, w, head["rank0"], other, args.stencil_calls) if args.compare else None
+    stencil_other = stencil_rate(dsb, h, w, head["rank0"], other, args.stencil_calls) if args.compare else None
 
     # dominant kernel of the headline form (by time inside the timed region)
     kern = {k: v for k, v in head["kernels"].items() if v["ms_per_solve"] > 0}
@@ -494,7 +570,7 @@ def main():
     cpu = None
     if args.cpu_baseline:
         log("[bench] CPU oracle sample")
-        cpu = cpu_baseline(w, head["block_iters"], args.cpu_steps)
+        cpu = cpu_baseline(w, head["block_iters"], args.cpu_steps, one_thread=one_thread)
 
     line = {
         "metric": METRIC,

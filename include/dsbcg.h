@@ -147,8 +147,18 @@ void dsbcg_destroy(dsbcg_handle h);
  * allocated).  Synchronous. */
 int dsbcg_neighbors(dsbcg_handle h, int32_t *host_out);
 
+/* Stage the links once (Sec. 1: the gauge links U_mu(x) are the coefficients
+ * of the Wilson matrix): U is checked for NaN/Inf (DSBCG_ERR_NOT_HPD, as in
+ * dsbcg_solve) and converted to the FP64 and FP32 structure-of-arrays copies
+ * the kernels read, held by the handle (0.86 KB per site).  Afterwards every
+ * call below that takes U accepts U = NULL and uses the staged copy without
+ * converting it again; a call with U != NULL converts that U into the same
+ * buffers and the staged copy is gone.  Returns with `stream` synchronised. */
+int dsbcg_stage_links(dsbcg_handle h, const void *U, dsbcg_stream stream);
+
 /* Y = A X = D^H (D X) for m columns (1 <= m <= DSBCG_MAX_RHS).
- * U, X, Y: device, layouts above (X, Y are [V][4][3][m]); Y must not alias X.
+ * U, X, Y: device, layouts above (X, Y are [V][4][3][m]); Y must not alias X;
+ * U may be NULL after dsbcg_stage_links.
  * precision DSBCG_FP64 computes in FP64; DSBCG_FP32_RELIABLE rounds U and X
  * to FP32, applies the FP32 stencil and writes the FP32 result widened to
  * FP64.  Asynchronous on `stream`. */
@@ -156,12 +166,15 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
                   int32_t m, int32_t precision, dsbcg_stream stream);
 
 /* Y = D X (dagger = 0) or D^H X (dagger = 1), FP64, same layouts as
- * dsbcg_apply_A.  Asynchronous on `stream`. */
+ * dsbcg_apply_A (U may be NULL after dsbcg_stage_links).  Asynchronous on
+ * `stream`. */
 int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y,
                   int32_t m, int32_t dagger, dsbcg_stream stream);
 
 /* Solve (sigma_j I + A) X_j = B for j = 0..s-1 with DSBlockCG (Sec. 3).
- * U, B: device inputs; sigma: HOST array of s real shifts with sigma_j I + A
+ * U, B: device inputs (U may be NULL after dsbcg_stage_links; this and the
+ * other solve entry points then skip the link check and conversion);
+ * sigma: HOST array of s real shifts with sigma_j I + A
  * hpd; X: device output [s][V][4][3][m], fully written.  tol: target relative
  * residual ||b_l - (sigma_j + A) x_{l,j}|| <= tol ||b_l|| for every (l, j)
  * (Sec. 4).  opts may be NULL (defaults); stats may be NULL.
@@ -208,7 +221,8 @@ int dsbcg_solve_multi(dsbcg_handle h, const void *U, double kappa, const void *B
                       const double *sigma, int32_t s, double tol, const dsbcg_opts *opts,
                       void *X, dsbcg_stats *stats, dsbcg_stream stream);
 
-/* Backward of X_j = (sigma_j I + D^H D)^{-1} B given X_j and the adjoint
+/* Backward of X_j = (sigma_j I + D^H D)^{-1} B (U may be NULL after
+ * dsbcg_stage_links) given X_j and the adjoint
  * solutions Lambda_j = (sigma_j I + A)^{-1} G_j, G_j = dL/dRe X_j + i dL/dIm X_j
  * (both [s][V][4][3][m], device).  Since sigma_j I + A is hermitian,
  *   dL/dB       = sum_j Lambda_j                         (dB: device [V][4][3][m])

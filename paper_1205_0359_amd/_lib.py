@@ -89,6 +89,8 @@ def load():
     lib.dsbcg_neighbors.restype = ctypes.c_int
     lib.dsbcg_apply_A.argtypes = [P, P, dbl, P, P, i32, i32, P]
     lib.dsbcg_apply_A.restype = ctypes.c_int
+    lib.dsbcg_stage_links.argtypes = [P, P, P]
+    lib.dsbcg_stage_links.restype = ctypes.c_int
     lib.dsbcg_apply_D.argtypes = [P, P, dbl, P, P, i32, i32, P]
     lib.dsbcg_apply_D.restype = ctypes.c_int
     lib.dsbcg_solve.argtypes = [P, P, dbl, P, i32, ctypes.POINTER(ctypes.c_double), i32, dbl,
@@ -149,6 +151,13 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _links(U, h):
+    """Pointer to U, or NULL (the handle's staged links) when U is None."""
+    if U is None:
+        return None
+    return _dev(U, "U", (h.V, 4, 3, 3))
+
+
 def _dev(t, name, shape=None, dtype=None):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -201,12 +210,17 @@ def dsbcg_neighbors(h: Handle):
     return out
 
 
+def dsbcg_stage_links(h: Handle, U, stream=None):
+    """Check and convert U once; later calls may pass U=None to use this copy."""
+    _check(load().dsbcg_stage_links(h.ptr, _dev(U, "U", (h.V, 4, 3, 3)), _stream(stream)))
+
+
 def dsbcg_apply_A(h: Handle, U, kappa: float, X, Y=None, precision: int = DSBCG_FP64,
                   stream=None):
     """Y = A X = D^H D X; X, Y complex128 (V, 4, 3, m) device tensors."""
     torch = _torch()
     m = X.shape[-1]
-    pU = _dev(U, "U", (h.V, 4, 3, 3))
+    pU = _links(U, h)
     pX = _dev(X, "X", (h.V, 4, 3, m))
     if Y is None:
         Y = torch.empty_like(X)
@@ -220,7 +234,7 @@ def dsbcg_apply_D(h: Handle, U, kappa: float, X, Y=None, dagger: bool = False, s
     """Y = D X (or D^H X); FP64."""
     torch = _torch()
     m = X.shape[-1]
-    pU = _dev(U, "U", (h.V, 4, 3, 3))
+    pU = _links(U, h)
     pX = _dev(X, "X", (h.V, 4, 3, m))
     if Y is None:
         Y = torch.empty_like(X)
@@ -276,7 +290,7 @@ def _solve(fn, h: Handle, U, kappa, B, sigma, tol, X, stream, raise_not_converge
     m = B.shape[-1]
     sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(-1))
     s = len(sig)
-    pU = _dev(U, "U", (h.V, 4, 3, 3))
+    pU = _links(U, h)
     pB = _dev(B, "B", (s, h.V, 4, 3, m) if multi else (h.V, 4, 3, m))
     if X is None:
         X = torch.empty((s, h.V, 4, 3, m), dtype=torch.complex128, device=B.device)
@@ -327,7 +341,7 @@ def dsbcg_solve_rational(h: Handle, U, kappa: float, B, sigma, coef, c0: float, 
     s = len(sig)
     if len(cf) != s:
         raise ValueError("coef and sigma differ in length")
-    pU = _dev(U, "U", (h.V, 4, 3, 3))
+    pU = _links(U, h)
     pB = _dev(B, "B", (h.V, 4, 3, m))
     if Y is None:
         Y = torch.empty((h.V, 4, 3, m), dtype=torch.complex128, device=B.device)
@@ -352,7 +366,7 @@ def dsbcg_grad(h: Handle, U, kappa: float, sigma, X, Lam, want_U=True, want_B=Tr
     torch = _torch()
     s, V, _, _, m = X.shape
     sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(-1))
-    pU = _dev(U, "U", (h.V, 4, 3, 3))
+    pU = _links(U, h)
     pX = _dev(X, "X", (s, h.V, 4, 3, m))
     pL = _dev(Lam, "Lam", (s, h.V, 4, 3, m))
     dU = torch.empty((h.V, 4, 3, 3), dtype=torch.complex128, device=X.device) if want_U else None

@@ -109,6 +109,7 @@ struct dsbcg_ctx {
     std::vector<DevBuf> Vring, Vring32;                  // window rings of Lanczos blocks
     StepReport *rep_host = nullptr;
     int32_t *list_host = nullptr;
+    bool links_staged = false;  // Ul64 and Ul32 hold the links of dsbcg_stage_links
     int nwg_max = 2048;
 
     ~dsbcg_ctx() {
@@ -570,6 +571,22 @@ int check_finite_links(dsbcg_ctx *h, const void *U, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(&flag, &rep->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (flag) return fail(DSBCG_ERR_NOT_HPD, "U holds non-finite values");
+    return DSBCG_OK;
+}
+
+// Links of a call.  U != NULL: checked (optionally) and converted into the
+// handle's structure-of-arrays buffers, in FP64 and, with need32, FP32; this
+// replaces a copy staged by dsbcg_stage_links.  U == NULL: the staged copy
+// (both precisions), which must exist.
+int use_links(dsbcg_ctx *h, const void *U, bool need32, bool check, hipStream_t st) {
+    if (!U) {
+        if (!h->links_staged) return fail(DSBCG_ERR_ARG, "U is NULL and no links are staged on the handle");
+        return DSBCG_OK;
+    }
+    h->links_staged = false;
+    if (check) CHK(check_finite_links(h, U, st));
+    CHK(prepare_links(h, U, true, st));
+    if (need32) CHK(prepare_links(h, U, false, st));
     return DSBCG_OK;
 }
 
@@ -1253,7 +1270,8 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
 
 int check_field_args(dsbcg_handle h, const void *U, const void *X, const void *Y, int32_t m,
                      double kappa) {
-    if (!h || !U || !X || !Y) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (!h || !X || !Y) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (!U && !h->links_staged) return fail(DSBCG_ERR_ARG, "U is NULL and no links are staged on the handle");
     if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
     if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
     if (X == Y) return fail(DSBCG_ERR_ARG, "Y must not alias X");
@@ -1339,6 +1357,19 @@ int dsbcg_neighbors(dsbcg_handle h, int32_t *host_out) {
     return DSBCG_OK;
 }
 
+int dsbcg_stage_links(dsbcg_handle h, const void *U, dsbcg_stream stream) {
+    if (!h || !U) return fail(DSBCG_ERR_ARG, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    CHK(ensure_common(h));
+    h->links_staged = false;
+    CHK(check_finite_links(h, U, st));
+    CHK(prepare_links(h, U, true, st));
+    CHK(prepare_links(h, U, false, st));
+    HIPCHK(hipStreamSynchronize(st));
+    h->links_staged = true;
+    return DSBCG_OK;
+}
+
 int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y, int32_t m,
                   int32_t dagger, dsbcg_stream stream) {
     CHK(check_field_args(h, U, X, Y, m, kappa));
@@ -1346,7 +1377,7 @@ int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     const int64_t n = 12 * (int64_t)h->g.V;
     CHK(ensure_ws(h, h->Xin, (size_t)n * m * sizeof(zd)));
     CHK(ensure_ws(h, h->Yout, (size_t)n * m * sizeof(zd)));
-    CHK(prepare_links(h, U, true, st));
+    CHK(use_links(h, U, false, false, st));
     CHK(copy(h, m, api(X, m), cm(h->Xin.p, n, true), false, st));
     CHK(stencil(h, true, h->Ul64.p, kappa, h->Xin.p, h->Yout.p, m, dagger != 0, st));
     CHK(copy(h, m, cm(h->Yout.p, n, true), api(Y, m), false, st));
@@ -1365,7 +1396,13 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     CHK(ensure_ws(h, h->Xin, (size_t)n * m * esz));
     CHK(ensure_ws(h, h->Yout, (size_t)n * m * esz));
     CHK(ensure_ws(h, h->T, (size_t)n * m * esz));
-    CHK(prepare_links(h, U, f64, st));
+    if (U) {
+        // only the precision this call needs
+        h->links_staged = false;
+        CHK(prepare_links(h, U, f64, st));
+    } else {
+        CHK(use_links(h, U, false, false, st));
+    }
     CHK(copy(h, m, api(X, m), cm(h->Xin.p, n, f64), false, st));
     CHK(apply_A_cm(h, f64, f64 ? h->Ul64.p : h->Ul32.p, kappa, h->Xin.p, h->T.p, h->Yout.p, m, st));
     CHK(copy(h, m, cm(h->Yout.p, n, f64), api(Y, m), false, st));
@@ -1383,7 +1420,8 @@ namespace {
 // the options into *o.
 int solve_args(dsbcg_handle h, const void *U, const void *B, int32_t m, const double *sigma, int32_t s,
                double tol, double kappa, const void *X, const dsbcg_opts *opts, dsbcg_opts *o) {
-    if (!h || !U || !B || !sigma || !X) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (!h || !B || !sigma || !X) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (!U && !h->links_staged) return fail(DSBCG_ERR_ARG, "U is NULL and no links are staged on the handle");
     if (m < 1 || m > DSBCG_MAX_RHS) return fail(DSBCG_ERR_ARG, "m out of range");
     if (s < 1 || s > DSBCG_MAX_SHIFTS) return fail(DSBCG_ERR_ARG, "s out of range");
     if (!(tol > 0) || !std::isfinite(tol)) return fail(DSBCG_ERR_ARG, "tol must be > 0");
@@ -1431,9 +1469,7 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
     const int64_t n = 12 * (int64_t)h->g.V;
 
     CHK(ensure_common(h));
-    CHK(check_finite_links(h, U, st));
-    CHK(prepare_links(h, U, true, st));
-    if (o.precision == DSBCG_FP32_RELIABLE) CHK(prepare_links(h, U, false, st));
+    CHK(use_links(h, U, o.precision == DSBCG_FP32_RELIABLE, true, st));
 
     SolveStats stt;
     double main_max = 0.0;
@@ -1548,8 +1584,7 @@ int dsbcg_solve_rational(dsbcg_handle h, const void *U, double kappa, const void
         HIPCHK(hipStreamSynchronize(st));
         return status;
     }
-    CHK(check_finite_links(h, U, st));
-    CHK(prepare_links(h, U, true, st));
+    CHK(use_links(h, U, false, true, st));
     SolveStats stt;
     RatSpec rs{coef, c0, Y};
     const int status = solve_core(h, kappa, B, 0, m, sigma, s, tol, o, o.switch_at, nullptr, stt, st, &rs);
@@ -1570,7 +1605,9 @@ int dsbcg_solve_multi(dsbcg_handle h, const void *U, double kappa, const void *B
 
 int dsbcg_grad(dsbcg_handle h, const void *U, double kappa, const double *sigma, int32_t s, int32_t m,
                const void *X, const void *Lam, void *dU, void *dB, double *dsigma, dsbcg_stream stream) {
-    if (!h || !U || !sigma || !X || !Lam) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (!h || !sigma || !X || !Lam) return fail(DSBCG_ERR_ARG, "NULL argument");
+    if (dU && !U && !h->links_staged)
+        return fail(DSBCG_ERR_ARG, "U is NULL and no links are staged on the handle");
     if (m < 1 || m > DSBCG_MAX_RHS || s < 1 || s > DSBCG_MAX_SHIFTS)
         return fail(DSBCG_ERR_ARG, "m or s out of range");
     if (!std::isfinite(kappa)) return fail(DSBCG_ERR_ARG, "kappa not finite");
@@ -1582,7 +1619,7 @@ int dsbcg_grad(dsbcg_handle h, const void *U, double kappa, const double *sigma,
     CHK(ensure_ws(h, h->R1, blk));
     CHK(ensure_ws(h, h->R2, blk));
     CHK(ensure_ws(h, h->R3, blk));
-    if (dU) CHK(prepare_links(h, U, true, st));
+    if (dU) CHK(use_links(h, U, false, false, st));
     Ts ts{h, true, st, n};
     for (int j = 0; j < s; ++j) {
         const zd *Xj = (const zd *)X + (int64_t)j * n * m;
@@ -1645,3 +1682,4 @@ int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *P
 }
 
 }  // extern "C"
+

@@ -149,17 +149,57 @@ inline bool global_links(bool fp64, int nb) { return fp64 && nb >= 5 && nb <= 7;
 // faster than one launch, with bitwise equal results.  FP32 costs about the
 // same per column at every width and is not split.
 int stencil_chunk(bool fp64, int nb) { return (fp64 && nb > 7) ? 5 : nb; }
-template <typename R, bool DAG, bool RESID, int MAXT, bool GL>
+
+// Block order.  Workgroups are dealt to the 8 XCDs of the chip round robin
+// (workgroup q runs on XCD q mod 8), and each XCD has its own L2.  In the
+// plain order workgroup q owns sites 64 q .. 64 q + 63, so the y neighbours
+// one workgroup over sit in another XCD's cache.  The lockstep order
+// (LOCK) gives XCD k the tiles k tpx .. (k+1) tpx - 1 of 64 sites of every
+// t-slice and walks t: the workgroups an XCD runs at one time cover a block
+// of neighbouring tiles of one slice, and their x, y, z neighbours mostly
+// sit in the same L2.  The output goes out with non-temporal stores, which
+// keep it from displacing the inputs in L2.  Measured on 32^3 x 64, FP64,
+// 5 columns: 2.02 ms against 2.16 ms per pass, L2-to-fabric reads 11.7 GB
+// against 12.6 GB (the algorithmic reads are 3.2 GB); the same order for the
+// FP32 LDS-staged form was slower and is not used there.
+struct BlockOrder {
+    int32_t vs;     // sites per t-slice, Lx Ly Lz
+    int32_t ntile;  // tiles of 64 sites per slice
+    int32_t tpx;    // tiles per XCD
+};
+constexpr int kXcds = 8;
+inline BlockOrder lockstep_order(const Geom &g) {
+    BlockOrder o;
+    o.vs = g.L[0] * g.L[1] * g.L[2];
+    o.ntile = (o.vs + kSitesPerWG - 1) / kSitesPerWG;
+    o.tpx = (o.ntile + kXcds - 1) / kXcds;
+    return o;
+}
+inline int lockstep_blocks(const Geom &g) { return kXcds * lockstep_order(g).tpx * g.L[3]; }
+
+template <typename R, bool DAG, bool RESID, int MAXT, bool GL, bool LOCK>
 __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
                                                          R kappa, const cx<R> *__restrict__ in,
-                                                         cx<R> *__restrict__ out, int nb, ResidOut ro) {
+                                                         cx<R> *__restrict__ out, int nb, ResidOut ro,
+                                                         BlockOrder bo) {
     __shared__ cx<R> lf[9 * kSitesPerWG];
     __shared__ cx<R> lb[9 * kSitesPerWG];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;  // = column
     const int nwaves = blockDim.x >> 6;
-    const int x = blockIdx.x * kSitesPerWG + lane;
-    const bool valid = x < g.V && wave < nb;
+    int x;
+    bool inside;
+    if (LOCK) {
+        const int xcd = blockIdx.x % kXcds, q = blockIdx.x / kXcds;
+        const int t = q / bo.tpx, tile = xcd * bo.tpx + (q - t * bo.tpx);
+        const int xs = tile * kSitesPerWG + lane;
+        inside = tile < bo.ntile && t < g.L[3] && xs < bo.vs;
+        x = t * bo.vs + xs;
+    } else {
+        x = blockIdx.x * kSitesPerWG + lane;
+        inside = x < g.V;
+    }
+    const bool valid = inside && wave < nb;
     int c[4] = {0, 0, 0, 0};
     if (valid) site_coords(g, x, c);
     const int64_t n = 12 * (int64_t)g.V;
@@ -215,7 +255,13 @@ __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__
         for (int a = 0; a < 3; ++a) {
             const int64_t idx = (int64_t)(s * 3 + a) * g.V + x;
             const cx<R> v = col[idx];
-            oc[idx] = mk<R>(v.x - kappa * acc[s][a].x, v.y - kappa * acc[s][a].y);
+            const cx<R> r = mk<R>(v.x - kappa * acc[s][a].x, v.y - kappa * acc[s][a].y);
+            if (LOCK) {
+                __builtin_nontemporal_store(r.x, &oc[idx].x);
+                __builtin_nontemporal_store(r.y, &oc[idx].y);
+            } else {
+                oc[idx] = r;
+            }
         }
 }
 
@@ -236,23 +282,28 @@ hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, 
     const dim3 grid((g.V + kSitesPerWG - 1) / kSitesPerWG);
     const dim3 block(64 * nb);
     const ResidOut none{nullptr, nullptr, 0.0, nullptr};
+    const BlockOrder plain{0, 0, 0};
 #define DSBCG_W(R, D)                                                                              \
     do {                                                                                           \
         if (small_bound(nb))                                                                       \
-            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512, false>), grid, block, 0, st, g,    \
-                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
+            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512, false, false>), grid, block, 0, st, g, \
+                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none,   \
+                               plain);                                                             \
         else                                                                                       \
-            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 1024, false>), grid, block, 0, st, g,   \
-                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none); \
+            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 1024, false, false>), grid, block, 0, st, g, \
+                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none,   \
+                               plain);                                                             \
     } while (0)
     if (fp64 && global_links(fp64, nb)) {
-        // 5 to 7 columns: at most 448 threads
+        // 5 to 7 columns (at most 448 threads), lockstep block order
+        const dim3 lgrid((unsigned)lockstep_blocks(g));
+        const BlockOrder lo = lockstep_order(g);
         if (dagger)
-            hipLaunchKernelGGL((wilson_cm_kernel<double, true, false, 512, true>), grid, block, 0, st, g,
-                               (const zd *)Ul, kappa, (const zd *)in, (zd *)out, nb, none);
+            hipLaunchKernelGGL((wilson_cm_kernel<double, true, false, 512, true, true>), lgrid, block, 0, st, g,
+                               (const zd *)Ul, kappa, (const zd *)in, (zd *)out, nb, none, lo);
         else
-            hipLaunchKernelGGL((wilson_cm_kernel<double, false, false, 512, true>), grid, block, 0, st, g,
-                               (const zd *)Ul, kappa, (const zd *)in, (zd *)out, nb, none);
+            hipLaunchKernelGGL((wilson_cm_kernel<double, false, false, 512, true, true>), lgrid, block, 0, st, g,
+                               (const zd *)Ul, kappa, (const zd *)in, (zd *)out, nb, none, lo);
     } else if (fp64) {
         if (dagger) DSBCG_W(double, true);
         else DSBCG_W(double, false);
@@ -264,23 +315,26 @@ hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, 
     return hipGetLastError();
 }
 
-int wilson_resid_workgroups(const Geom &g) { return (int)((g.V + kSitesPerWG - 1) / kSitesPerWG); }
+int wilson_resid_workgroups(const Geom &g) { return lockstep_blocks(g); }
 
 hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const void *in, const void *b,
                               const void *x, double sigma, int nb, double *partials, hipStream_t st) {
     if (nb < 1 || nb > 16 || !partials) return hipErrorInvalidValue;
+    // lockstep block order for every width: the partial of a workgroup with
+    // no sites is zero
     const dim3 grid((unsigned)wilson_resid_workgroups(g));
     const dim3 block(64 * nb);
     const ResidOut ro{(const zd *)b, (const zd *)x, sigma, partials};
+    const BlockOrder lo = lockstep_order(g);
     if (global_links(true, nb))
-        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, true>), grid, block, 0, st, g,
-                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro);
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, true, true>), grid, block, 0, st, g,
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
     else if (small_bound(nb))
-        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, false>), grid, block, 0, st, g,
-                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro);
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, false, true>), grid, block, 0, st, g,
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
     else
-        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 1024, false>), grid, block, 0, st, g,
-                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro);
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 1024, false, true>), grid, block, 0, st, g,
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
     return hipGetLastError();
 }
 
