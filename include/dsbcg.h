@@ -165,6 +165,22 @@ int dsbcg_stage_links(dsbcg_handle h, const void *U, dsbcg_stream stream);
 int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y,
                   int32_t m, int32_t precision, dsbcg_stream stream);
 
+/* dsbcg_apply_A without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results (bit for bit) and errors as
+ * dsbcg_apply_A; U may be NULL after dsbcg_stage_links.  The column-major
+ * staging of X and Y, the intermediate D X and, when U is given, the
+ * converted links live in one fixed workspace per device of 128 MiB (held
+ * by every GPU the library runs on until the process ends), so a call needs
+ *     V * 36 * e  (only when U != NULL)  +  3 * 12 * V * m * e  bytes,
+ * e = 16 (FP64) or 8 (FP32), each part rounded up to 256 bytes; a larger call
+ * returns DSBCG_ERR_ARG and leaves Y untouched.  The handle must belong to
+ * the current device.  Every call on one GPU uses the same workspace: calls
+ * that overlap on one GPU (other streams or threads) race.  Asynchronous on
+ * `stream`; no hipMalloc, hipFree or allocating library routine is called. */
+int dsbcg_apply_A_noalloc(dsbcg_handle h, const void *U, double kappa, const void *X, void *Y,
+                          int32_t m, int32_t precision, dsbcg_stream stream);
+
 /* Y = D X (dagger = 0) or D^H X (dagger = 1), FP64, same layouts as
  * dsbcg_apply_A (U may be NULL after dsbcg_stage_links).  Asynchronous on
  * `stream`. */

@@ -6,11 +6,11 @@ the HIP library libdsbcg.so (C ABI: include/dsbcg.h); this package holds the
 ctypes binding, the seeded input generators and the build script.
 """
 from ._lib import (DSBCG_FP32_RELIABLE, DSBCG_FP64, DSBCGError, Handle, NotConvergedError,
-                   NotHPDError, dsbcg_apply_A, dsbcg_apply_D, dsbcg_link_grad, dsbcg_neighbors,
+                   NotHPDError, dsbcg_apply_A, dsbcg_apply_A_noalloc, dsbcg_apply_D, dsbcg_link_grad, dsbcg_neighbors,
                    dsbcg_profile_enable, dsbcg_profile_read, dsbcg_solve, dsbcg_solve_multi,
                    dsbcg_solve_rational, dsbcg_grad, dsbcg_stage_links, default_opts, load)
 
 __all__ = ["DSBCG_FP32_RELIABLE", "DSBCG_FP64", "DSBCGError", "Handle", "NotConvergedError",
-           "NotHPDError", "dsbcg_apply_A", "dsbcg_apply_D", "dsbcg_link_grad", "dsbcg_neighbors",
+           "NotHPDError", "dsbcg_apply_A", "dsbcg_apply_A_noalloc", "dsbcg_apply_D", "dsbcg_link_grad", "dsbcg_neighbors",
            "dsbcg_profile_enable", "dsbcg_profile_read", "dsbcg_solve", "dsbcg_solve_multi",
            "dsbcg_solve_rational", "dsbcg_grad", "dsbcg_stage_links", "default_opts", "load"]

@@ -91,6 +91,8 @@ def load():
     lib.dsbcg_apply_A.restype = ctypes.c_int
     lib.dsbcg_stage_links.argtypes = [P, P, P]
     lib.dsbcg_stage_links.restype = ctypes.c_int
+    lib.dsbcg_apply_A_noalloc.argtypes = [P, P, dbl, P, P, i32, i32, P]
+    lib.dsbcg_apply_A_noalloc.restype = ctypes.c_int
     lib.dsbcg_apply_D.argtypes = [P, P, dbl, P, P, i32, i32, P]
     lib.dsbcg_apply_D.restype = ctypes.c_int
     lib.dsbcg_solve.argtypes = [P, P, dbl, P, i32, ctypes.POINTER(ctypes.c_double), i32, dbl,
@@ -227,6 +229,17 @@ def dsbcg_apply_A(h: Handle, U, kappa: float, X, Y=None, precision: int = DSBCG_
     pY = _dev(Y, "Y", (h.V, 4, 3, m))
     _check(load().dsbcg_apply_A(h.ptr, pU, float(kappa), pX, pY, int(m), int(precision),
                                 _stream(stream)))
+    return Y
+
+
+def dsbcg_apply_A_noalloc(h: Handle, U, kappa: float, X, Y, precision: int = DSBCG_FP64,
+                          stream=None):
+    """Y = A X into the caller's Y with no device allocation by the library."""
+    m = X.shape[-1]
+    pX = _dev(X, "X", (h.V, 4, 3, m))
+    pY = _dev(Y, "Y", (h.V, 4, 3, m))
+    _check(load().dsbcg_apply_A_noalloc(h.ptr, _links(U, h), float(kappa), pX, pY, int(m), int(precision),
+                                        _stream(stream)))
     return Y
 
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdsbcg.so")
-SOURCES = ["stencil.hip", "blas.hip", "small.hip", "solver.hip", "grad.hip"]
+SOURCES = ["stencil.hip", "blas.hip", "small.hip", "solver.hip", "grad.hip", "noalloc.hip"]
 ARCH = os.environ.get("DSBCG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -26,6 +26,7 @@
 #include "../../include/dsbcg.h"
 #include "blas.hpp"
 #include "grad.hpp"
+#include "noalloc.hpp"
 #include "small.hpp"
 #include "stencil.hpp"
 
@@ -1339,6 +1340,12 @@ int dsbcg_create(const int32_t *L, dsbcg_handle *out) {
         delete h;
         return fail(DSBCG_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
+    // the workspace of dsbcg_apply_A_noalloc on this device
+    const int rc = noalloc_setup(h->device);
+    if (rc != DSBCG_OK) {
+        delete h;
+        return rc;
+    }
     *out = h;
     return DSBCG_OK;
 }
@@ -1683,3 +1690,15 @@ int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *P
 
 }  // extern "C"
 
+namespace dsbcg {
+
+void handle_view(dsbcg_handle h, Geom *g, int *device, const void **ul64, const void **ul32) {
+    *g = h->g;
+    *device = h->device;
+    *ul64 = h->links_staged ? h->Ul64.p : nullptr;
+    *ul32 = h->links_staged ? h->Ul32.p : nullptr;
+}
+
+int set_error(int code, const char *msg) { return fail(code, msg); }
+
+}  // namespace dsbcg
