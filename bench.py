@@ -243,7 +243,9 @@ def stored_traffic(kernel: str, digest: str):
 
 def run_form(dsb, h, dU, dB, w, prec, steps, warmup):
     import torch
-    kw = {"precision": dsb.DSBCG_FP32_RELIABLE if prec == "fp32" else dsb.DSBCG_FP64}
+    # a caller solving block after block keeps the workspace between solves
+    kw = {"precision": dsb.DSBCG_FP32_RELIABLE if prec == "fp32" else dsb.DSBCG_FP64,
+          "keep_workspace": 1}
     X = None
     for k in range(warmup):
         log(f"[bench] warmup {prec} {k + 1}/{warmup}")
@@ -266,9 +268,19 @@ def run_form(dsb, h, dU, dB, w, prec, steps, warmup):
     if worst > w.tol:
         raise RuntimeError(f"{prec}: true relative residual {worst:.3e} above {w.tol}")
     sec = t1 - t0
+    # one more solve that allocates its workspace and frees it at return (the
+    # default of the library), for comparison
+    dsb.dsbcg_release_workspace(h)
+    kw0 = dict(kw, keep_workspace=0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    X, _ = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, X=X, **kw0)
+    torch.cuda.synchronize()
+    fresh_ms = 1e3 * (time.perf_counter() - t2)
     return {
         "systems_per_s": w.m * len(w.shifts) * steps / sec,
         "ms_per_step": 1e3 * sec / steps,
+        "ms_solve_fresh_workspace": fresh_ms,
         "block_iters": stats[-1]["block_iters"],
         "mvms": stats[-1]["mvms"],
         "rank0": stats[-1]["rank0"],
@@ -296,18 +308,21 @@ def rational_rate(dsb, h, dU, dB, w, steps, warmup):
     Y = None
     for k in range(warmup):
         log(f"[bench] warmup partial-fraction fp64 {k + 1}/{warmup}")
-        Y, st = dsb.dsbcg_solve_rational(h, None, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y)
+        Y, st = dsb.dsbcg_solve_rational(h, None, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y,
+                                         keep_workspace=1)
     torch.cuda.synchronize()
     dsb.dsbcg_profile_enable(h, True)
     t0 = time.perf_counter()
     for k in range(steps):
-        Y, st = dsb.dsbcg_solve_rational(h, None, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y)
+        Y, st = dsb.dsbcg_solve_rational(h, None, w.kappa, dB, w.shifts, coef, 1.0, w.tol, Y=Y,
+                                         keep_workspace=1)
         log(f"[bench] partial-fraction fp64 step {k + 1}/{steps}: {st['block_iters']} block steps, "
             f"max est relres {st['est_relres'].max():.2e}")
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     prof = dsb.dsbcg_profile_read(h)
     dsb.dsbcg_profile_enable(h, False)
+    dsb.dsbcg_release_workspace(h)
     del Y
     torch.cuda.empty_cache()
     return {

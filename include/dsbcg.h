@@ -97,6 +97,15 @@ typedef struct {
     double switch_at;     /* FP32 form: the iteration runs in FP64 until every active estimated
                              relative residual is <= switch_at, then continues the same
                              recurrences with FP32 vectors (default min(1e-2, 1e5 * tol)) */
+    int32_t keep_workspace; /* 1 (default): the handle keeps the device workspace of a solve
+                             (the kept Lanczos blocks, allocated as the windows take them; P_j,
+                             allocated only when a window forms them; the column-major
+                             iterates and right-hand sides) for the next call, which then
+                             allocates nothing it already holds; free it with
+                             dsbcg_release_workspace.  0: the solve frees it before it returns
+                             (the staged links stay).  Allocating the workspace of the
+                             32^3 x 64, m = 8, s = 10 solve costs seconds, against 0.42 s
+                             for the solve itself */
 } dsbcg_opts;
 
 typedef struct {
@@ -135,12 +144,13 @@ void dsbcg_default_opts(dsbcg_opts *opts);
  * extent >= 2, volume < 2^31 / 12).  Binds the handle to the current device. */
 int dsbcg_create(const int32_t *L, dsbcg_handle *out);
 
-/* Release the handle and its workspace (NULL is ignored).  A solve keeps its
- * workspace for the next call; with the automatic window length the kept
- * Lanczos blocks can take about three quarters of the device memory that
- * was free at the solve, so release the handle (or cap opts.window) when
- * the memory is needed elsewhere. */
+/* Release the handle and its workspace (NULL is ignored). */
 void dsbcg_destroy(dsbcg_handle h);
+
+/* Free the device workspace a handle holds (after solves with
+ * opts.keep_workspace = 1, or the staging buffers of dsbcg_apply_A), keeping
+ * the staged links.  Synchronises the device. */
+int dsbcg_release_workspace(dsbcg_handle h);
 
 /* Export the neighbour table the kernels use: host_out[V][8] receives the
  * sites x+x^, x-x^, x+y^, x-y^, x+z^, x-z^, x+t^, x-t^ (host array, caller

@@ -46,7 +46,7 @@ class dsbcg_opts(ctypes.Structure):
                 ("tau_B", ctypes.c_double),
                 ("tau_W", ctypes.c_double), ("refine", ctypes.c_int32),
                 ("freeze", ctypes.c_int32), ("window", ctypes.c_int32),
-                ("switch_at", ctypes.c_double)]
+                ("switch_at", ctypes.c_double), ("keep_workspace", ctypes.c_int32)]
 
 
 class dsbcg_stats(ctypes.Structure):
@@ -89,6 +89,8 @@ def load():
     lib.dsbcg_neighbors.restype = ctypes.c_int
     lib.dsbcg_apply_A.argtypes = [P, P, dbl, P, P, i32, i32, P]
     lib.dsbcg_apply_A.restype = ctypes.c_int
+    lib.dsbcg_release_workspace.argtypes = [P]
+    lib.dsbcg_release_workspace.restype = ctypes.c_int
     lib.dsbcg_stage_links.argtypes = [P, P, P]
     lib.dsbcg_stage_links.restype = ctypes.c_int
     lib.dsbcg_apply_A_noalloc.argtypes = [P, P, dbl, P, P, i32, i32, P]
@@ -210,6 +212,11 @@ def dsbcg_neighbors(h: Handle):
     out = np.empty((h.V, 8), dtype=np.int32)
     _check(load().dsbcg_neighbors(h.ptr, out.ctypes.data_as(ctypes.c_void_p)))
     return out
+
+
+def dsbcg_release_workspace(h: Handle):
+    """Free the device workspace the handle holds (the staged links stay)."""
+    _check(load().dsbcg_release_workspace(h.ptr))
 
 
 def dsbcg_stage_links(h: Handle, U, stream=None):

@@ -144,7 +144,12 @@ __device__ inline void combine_rows(const TsArgs &a, const cx<R> *coef, int64_t 
 }
 
 // Register Gram: GRAM 0 none, 1 out^H out (upper triangle, mirrored), 2 L^H out,
-// 3 the diagonal of out^H out only (column norms); K inputs.
+// 3 the diagonal of out^H out only (column norms), 4 both L^H out and
+// out^H out (widths up to 5).  At width 5 the 40 complex FP64 accumulators
+// of gram 4 hold the kernel at one wave per SIMD; measured at 32^3 x 64 this
+// is faster than splitting the two blocks over a pair of waves that read the
+// same rows (165 against 136 ms of Gram/update kernels per FP64 solve) and
+// than a two-waves bound that spills (141 ms).  K inputs.
 template <typename R, int B, int K, int GRAM>
 __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
     if (a.skip && *a.skip) return;  // uniform: before any barrier
@@ -153,18 +158,21 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
     load_coefs<R, B>(a, coef);
     __syncthreads();
     constexpr int NG = GRAM == 0 ? 1 : B * B;
-    zd G[NG];
+    constexpr int NG2 = GRAM == 4 ? B * B : 1;  // out^H out next to L^H out
+    zd G[NG], G2[NG2];
 #pragma unroll
     for (int e = 0; e < NG; ++e) G[e] = mk<double>(0, 0);
+#pragma unroll
+    for (int e = 0; e < NG2; ++e) G2[e] = mk<double>(0, 0);
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
     const int64_t r1 = min(a.nrows, r0 + a.rows_per_wg);
     cx<R> *out = (cx<R> *)a.out;
-    const int bl = GRAM == 2 ? a.bl : 0;
+    const int bl = (GRAM == 2 || GRAM == 4) ? a.bl : 0;
     constexpr int RPT = RowGroup<R>::rows;
 #pragma unroll 1
     for (int64_t row = r0 + RPT * threadIdx.x; row < r1; row += 256 * RPT) {
         cx<R> l[B][RPT];
-        if (GRAM == 2) {
+        if (GRAM == 2 || GRAM == 4) {
             const cx<R> *Lp = (const cx<R> *)a.L + row;
 #pragma unroll
             for (int p = 0; p < B; ++p) {
@@ -198,7 +206,7 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
             } else if (GRAM == 3) {
 #pragma unroll
                 for (int q = 0; q < B; ++q) G[q * B + q].x += norm2(cvt<double>(o[i][q]));
-            } else if (GRAM == 2) {
+            } else if (GRAM == 2 || GRAM == 4) {
                 zd od[B];
 #pragma unroll
                 for (int q = 0; q < B; ++q) od[q] = cvt<double>(o[i][q]);
@@ -208,38 +216,50 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
 #pragma unroll
                     for (int q = 0; q < B; ++q) cmac_conj(G[p * B + q], lp, od[q]);
                 }
+                if (GRAM == 4)
+#pragma unroll
+                    for (int p = 0; p < B; ++p)
+#pragma unroll
+                        for (int q = p; q < B; ++q) cmac_conj(G2[p * B + q], od[p], od[q]);
             }
         }
     }
     if (GRAM == 0) return;
-    // wave reduction by butterflies, then across the four waves
+    // wave reduction by butterflies, then across the four waves; GRAM 4 runs
+    // this twice (L^H out into entries 0..255 of the workgroup's partials,
+    // then out^H out into 256..511)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int p = 0; p < B; ++p)
+    for (int part = 0; part < (GRAM == 4 ? 2 : 1); ++part) {
+        const int gm = GRAM == 4 ? (part ? 1 : 2) : GRAM;  // the mode of this part
+        if (part) __syncthreads();                          // red is reused
 #pragma unroll
-        for (int q = 0; q < B; ++q) {
-            if ((GRAM == 1 && q < p) || (GRAM == 3 && q != p)) continue;
-            zd v = G[p * B + q];
+        for (int p = 0; p < B; ++p)
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                v.x += __shfl_xor(v.x, off, 64);
-                v.y += __shfl_xor(v.y, off, 64);
+            for (int q = 0; q < B; ++q) {
+                if ((gm == 1 && q < p) || (gm == 3 && q != p)) continue;
+                zd v = (GRAM == 4 && part) ? G2[(p * B + q) % NG2] : G[p * B + q];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    v.x += __shfl_xor(v.x, off, 64);
+                    v.y += __shfl_xor(v.y, off, 64);
+                }
+                if (lane == 0) red[wave][p * B + q] = v;
             }
-            if (lane == 0) red[wave][p * B + q] = v;
+        __syncthreads();
+        if (threadIdx.x < B * B) {
+            int p = threadIdx.x / B, q = threadIdx.x - p * B;
+            const bool mirror = gm == 1 && q < p;
+            const int e = mirror ? q * B + p : p * B + q;
+            zd s = mk<double>(0, 0);
+            if (gm != 3 || p == q) {
+                s = red[0][e];
+                s = s + red[1][e];
+                s = s + red[2][e];
+                s = s + red[3][e];
+            }
+            a.partials[(int64_t)blockIdx.x * kPartialStride + 256 * part + p * 16 + q] = mirror ? conj(s) : s;
         }
-    __syncthreads();
-    if (threadIdx.x < B * B) {
-        int p = threadIdx.x / B, q = threadIdx.x - p * B;
-        const bool mirror = GRAM == 1 && q < p;
-        const int e = mirror ? q * B + p : p * B + q;
-        zd s = mk<double>(0, 0);
-        if (GRAM != 3 || p == q) {
-            s = red[0][e];
-            s = s + red[1][e];
-            s = s + red[2][e];
-            s = s + red[3][e];
-        }
-        a.partials[(int64_t)blockIdx.x * 256 + p * 16 + q] = mirror ? conj(s) : s;
     }
 }
 
@@ -259,17 +279,18 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
     __shared__ cx<R> coef[3 * B * B];
     __shared__ cx<R> so[B * kTileRows];
     __shared__ cx<R> sl[B * kTileRows];
-    __shared__ zd red[4][64];
+    __shared__ zd red[8][64];
     load_coefs<R, B>(a, coef);
     const int t = threadIdx.x;
-    const int bl = (a.gram == 2) ? a.bl : a.bout;  // gram 3 (diagonal) runs as gram 1
+    const bool withL = a.gram == 2 || a.gram == 4;  // gram 4: a.bl == a.bout (checked by ts_run)
+    const int bl = withL ? a.bl : a.bout;           // gram 3 (diagonal) runs as gram 1
     const int nbq = (a.bout + 1) / 2, nbp = (bl + 1) / 2;
     const int nblk = nbp * nbq;
     const int blk = t & 63, half = t >> 6;
     const int bp = (blk < nblk) ? blk / nbq : 0, bq = (blk < nblk) ? blk - (blk / nbq) * nbq : 0;
-    zd G[2][2];
+    zd G[2][2], G2[2][2];  // G2: out^H out of gram 4
     for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) G[u][v] = mk<double>(0, 0);
+        for (int v = 0; v < 2; ++v) G[u][v] = G2[u][v] = mk<double>(0, 0);
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
     const int64_t r1 = min(a.nrows, r0 + a.rows_per_wg);
     cx<R> *out = (cx<R> *)a.out;
@@ -286,7 +307,7 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
                 if (out && q < a.bout) out[q * a.cso + row] = o[q];
                 so[q * kTileRows + t] = o[q];
             }
-            if (a.gram == 2) {
+            if (withL) {
                 const cx<R> *Lp = (const cx<R> *)a.L + row;
 #pragma unroll
                 for (int p = 0; p < B; ++p) {
@@ -296,12 +317,12 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
             }
         } else {
             for (int q = 0; q < B; ++q) so[q * kTileRows + t] = mk<R>(0, 0);
-            if (a.gram == 2)
+            if (withL)
                 for (int p = 0; p < B; ++p) sl[p * kTileRows + t] = mk<R>(0, 0);
         }
         __syncthreads();
         if (a.gram && blk < nblk) {
-            const cx<R> *L = (a.gram == 2) ? sl : so;
+            const cx<R> *L = withL ? sl : so;
             const int p0 = 2 * bp, q0 = 2 * bq;
             for (int r = half * 64; r < half * 64 + 64 && r < kTileRows; ++r) {
                 const zd l0 = cvt<double>(L[p0 * kTileRows + r]);
@@ -312,6 +333,14 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
                 cmac_conj(G[0][1], l0, y1);
                 cmac_conj(G[1][0], l1, y0);
                 cmac_conj(G[1][1], l1, y1);
+                if (a.gram == 4) {
+                    const zd o0 = cvt<double>(so[p0 * kTileRows + r]);
+                    const zd o1 = cvt<double>(so[(p0 + 1) * kTileRows + r]);
+                    cmac_conj(G2[0][0], o0, y0);
+                    cmac_conj(G2[0][1], o0, y1);
+                    cmac_conj(G2[1][0], o1, y0);
+                    cmac_conj(G2[1][1], o1, y1);
+                }
             }
         }
         __syncthreads();
@@ -320,16 +349,23 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
     // combine the two row halves, then write the blocks
     if (half == 1 && blk < nblk)
         for (int u = 0; u < 2; ++u)
-            for (int v = 0; v < 2; ++v) red[u * 2 + v][blk] = G[u][v];
+            for (int v = 0; v < 2; ++v) {
+                red[u * 2 + v][blk] = G[u][v];
+                red[4 + u * 2 + v][blk] = G2[u][v];
+            }
     __syncthreads();
     if (half == 0 && blk < nblk) {
         const int p0 = 2 * bp, q0 = 2 * bq;
         for (int u = 0; u < 2; ++u)
             for (int v = 0; v < 2; ++v) {
                 const int p = p0 + u, q = q0 + v;
-                if (p < bl && q < a.bout)
-                    a.partials[(int64_t)blockIdx.x * 256 + p * 16 + q] =
+                if (p < bl && q < a.bout) {
+                    a.partials[(int64_t)blockIdx.x * kPartialStride + p * 16 + q] =
                         (blockDim.x > 64) ? G[u][v] + red[u * 2 + v][blk] : G[u][v];
+                    if (a.gram == 4)
+                        a.partials[(int64_t)blockIdx.x * kPartialStride + 256 + p * 16 + q] =
+                            (blockDim.x > 64) ? G2[u][v] + red[4 + u * 2 + v][blk] : G2[u][v];
+                }
             }
     }
 }
@@ -344,6 +380,12 @@ void ts_launch_reg(const TsArgs &a, int nwg, hipStream_t st) {
         }
         if (a.gram == 2) {
             hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 2>), dim3(nwg), dim3(256), 0, st, a);
+            return;
+        }
+    }
+    if constexpr (B <= 5) {
+        if (a.gram == 4) {
+            hipLaunchKernelGGL((ts_reg_kernel<R, B, K, 4>), dim3(nwg), dim3(256), 0, st, a);
             return;
         }
     }
@@ -381,13 +423,15 @@ hipError_t ts_run(bool fp64, TsArgs a, int max_wg, int *nwg_out, hipStream_t st)
     if (a.K < 1 || a.K > 3 || a.bout < 1 || a.bout > kMaxW) return hipErrorInvalidValue;
     for (int k = 0; k < a.K; ++k)
         if (a.bx[k] < 0 || a.bx[k] > kMaxW) return hipErrorInvalidValue;
-    if (a.gram == 2 && (a.bl < 1 || a.bl > kMaxW)) return hipErrorInvalidValue;
+    if ((a.gram == 2 || a.gram == 4) && (a.bl < 1 || a.bl > kMaxW)) return hipErrorInvalidValue;
+    if (a.gram == 4 && (a.bl != a.bout || a.out)) return hipErrorInvalidValue;
     // register kernel: every input, output and L width within w <= 6, or
     // w <= 8 without a full Gram
     int w = a.bout;
     for (int k = 0; k < a.K; ++k) w = std::max(w, a.bx[k]);
-    if (a.gram == 2) w = std::max(w, a.bl);
-    const bool reg = w <= 6 || (w <= 8 && (a.gram == 0 || a.gram == 3));
+    if (a.gram == 2 || a.gram == 4) w = std::max(w, a.bl);
+    // gram 4 keeps two Gram blocks in registers: widths up to 5
+    const bool reg = a.gram == 4 ? w <= 5 : (w <= 6 || (w <= 8 && (a.gram == 0 || a.gram == 3)));
     // the FP32 register kernel moves two rows per thread: even row counts,
     // column strides and block offsets
     if (reg && !fp64) {
@@ -395,7 +439,7 @@ hipError_t ts_run(bool fp64, TsArgs a, int max_wg, int *nwg_out, hipStream_t st)
         for (int k = 0; k < a.K; ++k)
             if ((a.cs[k] & 1) || ((uintptr_t)a.X[k] & 15)) return hipErrorInvalidValue;
         if (a.out && ((a.cso & 1) || ((uintptr_t)a.out & 15))) return hipErrorInvalidValue;
-        if (a.gram == 2 && ((a.csl & 1) || ((uintptr_t)a.L & 15))) return hipErrorInvalidValue;
+        if ((a.gram == 2 || a.gram == 4) && ((a.csl & 1) || ((uintptr_t)a.L & 15))) return hipErrorInvalidValue;
     }
     const int tile = reg ? (fp64 ? 256 : 512) : (fp64 ? TileRows<double>::value : TileRows<float>::value);
     int64_t tiles = (a.nrows + tile - 1) / tile;
@@ -416,7 +460,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const zd *__restrict__ part
     __shared__ zd red[256];
     const int e = blockIdx.x;  // element index p*16+q
     zd s = mk<double>(0, 0);
-    for (int w = threadIdx.x; w < nwg; w += 256) s = s + partials[(int64_t)w * 256 + e];
+    for (int w = threadIdx.x; w < nwg; w += 256) s = s + partials[(int64_t)w * kPartialStride + e];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -426,8 +470,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const zd *__restrict__ part
     if (threadIdx.x == 0) out[e] = red[0];
 }
 
-hipError_t reduce_partials(const zd *partials, int nwg, int nelem, zd *out, hipStream_t st) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(nelem), dim3(256), 0, st, partials, nwg, out);
+hipError_t reduce_partials(const zd *partials, int nwg, int nelem, zd *out, hipStream_t st, int off) {
+    if (off < 0 || off + nelem > kPartialStride) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reduce_kernel, dim3(nelem), dim3(256), 0, st, partials + off, nwg, out);
     return hipGetLastError();
 }
 

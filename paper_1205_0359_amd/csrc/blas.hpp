@@ -11,6 +11,7 @@
 namespace dsbcg {
 
 constexpr int kMaxW = 16;  // largest block width (right-hand sides, shifts)
+constexpr int kPartialStride = 512;  // partial Gram entries per workgroup (two 16 x 16 blocks)
 
 struct TsArgs {
     int64_t nrows;
@@ -23,11 +24,12 @@ struct TsArgs {
     void *out;               // optional store of the combination
     int64_t cso;
     int gram;                // 0: none, 1: partial out^H out, 2: partial L^H out,
-                             // 3: diagonal of out^H out only
+                             // 3: diagonal of out^H out only, 4: both L^H out (partial
+                             // entries 0..255 of the workgroup) and out^H out (256..511)
     const void *L;
     int64_t csl;
     int bl;
-    zd *partials;            // [nwg][16*16] FP64 partial Gram matrices
+    zd *partials;            // [nwg][kPartialStride] FP64 partial Gram matrices (16 x 16 each)
     int64_t rows_per_wg;
     const int32_t *skip;     // device flag or NULL: when set the launch does nothing
 };
@@ -36,8 +38,8 @@ struct TsArgs {
 // whose partials must be reduced (at most max_wg).
 hipError_t ts_run(bool fp64, TsArgs a, int max_wg, int *nwg, hipStream_t st);
 
-// out[e] = sum_w partials[w][e] for e < nelem, summed in a fixed order.
-hipError_t reduce_partials(const zd *partials, int nwg, int nelem, zd *out, hipStream_t st);
+// out[e] = sum_w partials[w][off + e] for e < nelem, summed in a fixed order.
+hipError_t reduce_partials(const zd *partials, int nwg, int nelem, zd *out, hipStream_t st, int off = 0);
 
 // A lattice field of `cols` columns in one of two layouts:
 //   kApi: [V][12][ld] with the columns at col0 .. col0+cols-1 of each row

@@ -477,15 +477,17 @@ hipError_t small_prep_alpha(SmallState *st, const zd *alpha_raw, hipStream_t str
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepReport *rep,
                                                           const zd *__restrict__ alpha_raw,
-                                                          const zd *__restrict__ G, double tau_W) {
+                                                          const zd *__restrict__ G, double tau_W,
+                                                          const zd *__restrict__ Gref) {
     // the inputs go to LDS with every lane, the sequential factorisation
     // then runs on LDS only (thread 0), and the results leave in parallel
     __shared__ zd Gs[256], R[256], C1s[256];
-    __shared__ double nrm[2];
+    __shared__ double nrm[2], gref[16];
     __shared__ int piv[16], nks, skip;
     const int t = threadIdx.x;
     const int b = st->b, bp = st->bp;
     (void)alpha_raw;
+    if (t < 16) gref[t] = (Gref ? Gref : G)[t * 16 + t].x;
     // ||T||_est from alpha_i and beta_i
     double na = 0.0, nb = 0.0;
     for (int e = t; e < 256; e += 64) {
@@ -513,8 +515,8 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepRe
         const double thr = tau_W * test;
         int nk = 0, unresolved = 0;
         for (int k = 0; k < b; ++k) {
-            const double gkk = Gs[k * 16 + k].x;
-            double d = gkk;
+            const double gkk = fmax(Gs[k * 16 + k].x, gref[k]);  // scale of the rounding of d
+            double d = Gs[k * 16 + k].x;
             for (int r = 0; r < nk; ++r) {
                 zd v = Gs[piv[r] * 16 + k];
                 for (int q = 0; q < r; ++q) v = v - conj(R[q * 16 + piv[r]]) * R[q * 16 + k];
@@ -582,9 +584,82 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepRe
 }
 
 hipError_t small_chol_deflate(SmallState *st, StepReport *rep, const zd *alpha_raw, const zd *G,
-                              double tau_W, hipStream_t stream) {
+                              double tau_W, hipStream_t stream, const zd *Gref) {
     hipLaunchKernelGGL(chol_deflate_kernel, dim3(1), dim3(64), 0, stream, st, rep, alpha_raw, G,
-                       tau_W);
+                       tau_W, Gref);
+    return hipGetLastError();
+}
+
+// G = G' - M^H alpha - alpha^H M + alpha^H alpha, hermitised (b x b).
+__global__ __launch_bounds__(256) void lanczos_gram_kernel(const SmallState *st, const zd *__restrict__ M,
+                                                           const zd *__restrict__ Gp, zd *__restrict__ G) {
+    __shared__ zd Ms[256], As[256], NA[256], T[256];
+    const int t = threadIdx.x;
+    const int b = st->b;
+    Ms[t] = M[t];
+    As[t] = st->alpha[t];
+    __syncthreads();
+    const int r = t / 16, c = t - r * 16;
+    // N alpha
+    zd na = mk<double>(0, 0);
+    if (r < b && c < b)
+        for (int k = 0; k < b; ++k) na = na + st->Nv[r * 16 + k] * As[k * 16 + c];
+    NA[t] = na;
+    __syncthreads();
+    zd v = mk<double>(0, 0);
+    if (r < b && c < b) {
+        v = Gp[t];
+        for (int k = 0; k < b; ++k) {
+            // (M^H alpha)_{rc} = sum_k conj(M_kr) alpha_kc, (alpha^H M)_{rc} = sum_k conj(alpha_kr) M_kc
+            v = v - conj(Ms[k * 16 + r]) * As[k * 16 + c] - conj(As[k * 16 + r]) * Ms[k * 16 + c] +
+                conj(As[k * 16 + r]) * NA[k * 16 + c];
+        }
+    }
+    T[t] = v;
+    __syncthreads();
+    const zd w = conj(T[c * 16 + r]);
+    G[t] = mk<double>(0.5 * (v.x + w.x), 0.5 * (v.y + w.y));
+}
+
+hipError_t small_lanczos_gram(const SmallState *st, const zd *M, const zd *Gp, zd *G, hipStream_t stream) {
+    hipLaunchKernelGGL(lanczos_gram_kernel, dim3(1), dim3(256), 0, stream, st, M, Gp, G);
+    return hipGetLastError();
+}
+
+__global__ void set_nv_kernel(SmallState *st, const zd *__restrict__ G) {
+    const int b = st->b;
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        const int r = e / 16, c = e - r * 16;
+        st->Nv[e] = (r < b && c < b) ? G[e] : mk<double>(0, 0);
+    }
+}
+
+hipError_t small_set_nv(SmallState *st, const zd *G, hipStream_t stream) {
+    hipLaunchKernelGGL(set_nv_kernel, dim3(1), dim3(256), 0, stream, st, G);
+    return hipGetLastError();
+}
+
+// cB[0] = C1, cB[1] = coef[1] C1 (-alpha C1), cB[2] = coef[0] C1 (-beta^H C1).
+__global__ __launch_bounds__(256) void basis_coefs_kernel(SmallState *st) {
+    __shared__ zd C1s[256];
+    const int t = threadIdx.x;
+    if (st->redo) return;  // uniform: the basis is formed column by column instead
+    const int b = st->b;
+    C1s[t] = st->C1[t];
+    __syncthreads();
+    const int r = t / 16, c = t - r * 16;
+    zd va = mk<double>(0, 0), vb = mk<double>(0, 0);
+    for (int k = 0; k < b; ++k) {
+        va = va + st->coef[1][r * 16 + k] * C1s[k * 16 + c];
+        vb = vb + st->coef[0][r * 16 + k] * C1s[k * 16 + c];
+    }
+    st->cB[0][t] = C1s[t];
+    st->cB[1][t] = va;
+    st->cB[2][t] = vb;
+}
+
+hipError_t small_basis_coefs(SmallState *st, hipStream_t stream) {
+    hipLaunchKernelGGL(basis_coefs_kernel, dim3(1), dim3(256), 0, stream, st);
     return hipGetLastError();
 }
 
@@ -595,7 +670,7 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
                                                      const zd *__restrict__ G2, double tol,
                                                      int freeze, const int32_t *__restrict__ list,
                                                      int nact) {
-    __shared__ zd R2[256], BN[256], G2s[256], C1s[256], R1s[256];
+    __shared__ zd R2[256], BN[256], G2s[256], R1s[256];
     __shared__ int fail;
     if (st->redo) return;  // uniform: the QR of this step is redone first
     const int t = threadIdx.x;
@@ -605,7 +680,6 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
     // inputs to LDS with every lane; the sequential part below reads LDS only
     for (int e = t; e < 256; e += blockDim.x) {
         G2s[e] = skip ? mk<double>(0, 0) : G2[e];
-        C1s[e] = st->C1[e];
         R1s[e] = st->R1[e];
         R2[e] = mk<double>(0, 0);
     }
@@ -632,15 +706,15 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
             }
         }
         if (fail) atomicOr(&rep->flags, kFlagQR2);
-        // Rinv = C1 R2^{-1}: rows of C1 solved against upper-triangular R2
-        for (int r = 0; r < b; ++r) {
+        // R2inv = R2^{-1}: rows of I solved against upper-triangular R2
+        for (int r = 0; r < 16; ++r) {
             zd x[16];
             for (int c = 0; c < nk; ++c) {
-                zd v = C1s[r * 16 + c];
+                zd v = (r == c) ? mk<double>(1, 0) : mk<double>(0, 0);
                 for (int q = 0; q < c; ++q) v = v - x[q] * R2[q * 16 + c];
                 x[c] = zdivr(v, R2[c * 16 + c].x);
             }
-            for (int c = 0; c < 16; ++c) st->Rinv[r * 16 + c] = (c < nk) ? x[c] : mk<double>(0, 0);
+            for (int c = 0; c < 16; ++c) st->R2inv[r * 16 + c] = (r < nk && c < nk) ? x[c] : mk<double>(0, 0);
         }
         // beta_{i+1} = R2 R1 (nk x b)
         for (int r = 0; r < 16; ++r)
@@ -674,6 +748,10 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
     __syncthreads();
     for (int e = t; e < 256; e += 256) {
         const int r = e / 16, c = e - r * 16;
+        // Gram of V_{i+1} as stored: the measured one when it was not
+        // re-orthonormalised (entries past the new width are zero)
+        st->Nv[e] = skip ? ((r < nk && c < nk) ? G2[e] : mk<double>(0, 0))
+                         : ((r == c && r < nk) ? mk<double>(1, 0) : mk<double>(0, 0));
         st->betanext[e] = BN[e];
         st->beta[e] = BN[e];
         // -beta_{i+1}^H (b x bnew): coefficient of V_i in the next step
@@ -821,6 +899,7 @@ __global__ void init_shifts_kernel(SmallState *st, StepReport *rep, int m1, int 
     st->test = 0.0;
     st->redo = 0;
     st->skip_qr2 = 0;
+    for (int e = 0; e < 256; ++e) st->Nv[e] = mk<double>((e / 16 == e % 16) ? 1.0 : 0.0, 0.0);
     for (int e = 0; e < 256; ++e) st->beta[e] = mk<double>(0, 0);
     for (int j = 0; j < s; ++j) {
         st->sigma[j] = sh.sigma[j];

@@ -17,7 +17,12 @@ struct SmallState {
     zd betanext[256];    // beta_{i+1} (bnew x b)
     zd R1[256];          // first-pass Cholesky factor of W^H W, kept rows (bnew x b)
     zd C1[256];          // E_K R_KK^{-1}                       (b x bnew)
-    zd Rinv[256];        // E_K (R2 R_KK)^{-1}                   (b x bnew)
+    zd R2inv[256];       // R2^{-1} of the second CholQR pass (bnew x bnew; I when skipped)
+    zd Nv[256];          // V_i^H V_i of the current block as stored (b x b): the Gram of the
+                         // basis update when its second pass was skipped, else I
+    zd cB[3][256];       // coefficients of the basis update
+                         //   V' = W C1 - V_i alpha_i C1 - V_{i-1} beta_i^H C1:
+                         //   [0] C1, [1] -alpha_i C1, [2] -beta_i^H C1
     zd rho[kS * kStack]; // R factor of the deflated QR of the stacked right-hand sides,
                          // row r, stacked column c at r * kStack + c  (m1 x M)
     zd coef[4][256];     // scratch coefficient matrices for the block kernels
@@ -135,7 +140,26 @@ constexpr double kResolve = 1e-10;
 // Smallest drop threshold tau_W of block steps run with FP32 vectors.
 constexpr double kTauW32 = 1e-5;
 hipError_t small_chol_deflate(SmallState *st, StepReport *rep, const zd *alpha_raw, const zd *G,
-                              double tau_W, hipStream_t stream);
+                              double tau_W, hipStream_t stream, const zd *Gref = nullptr);
+
+// Gram of the orthogonalised block from the quantities of one pass over
+// W' = W - V_{i-1} beta_i^H: with M = V_i^H W' (alpha_i = herm(M) already in
+// the state), G' = W'^H W' and N = V_i^H V_i (Nv), the Gram of
+// W'' = W' - V_i alpha_i is exactly
+//   W''^H W'' = G' - M^H alpha_i - alpha_i^H M + alpha_i^H N alpha_i.
+// N is the Gram of V_i as stored, measured when V_i was written: taking it
+// for I would feed the basis's departure from orthonormality into the next
+// Gram, amplified by about ||alpha||^2 / ||beta||^2 every step.  The rounding
+// of the result is of the order of the entries of G', so small_chol_deflate
+// takes G' as the reference scale of its resolution rule (Gref).  Writes the
+// b x b result to G.
+hipError_t small_lanczos_gram(const SmallState *st, const zd *M, const zd *Gp, zd *G, hipStream_t stream);
+
+// Nv = G (the b x b Gram of V_i as stored, e.g. after its rounding to FP32).
+hipError_t small_set_nv(SmallState *st, const zd *G, hipStream_t stream);
+
+// cB[0..2] from C1, alpha_i and beta_i (after small_chol_deflate).
+hipError_t small_basis_coefs(SmallState *st, hipStream_t stream);
 
 // Column-by-column deflated QR of W (classical Gram-Schmidt applied twice,
 // column order, the rule of the initial QR with the absolute threshold
@@ -153,9 +177,10 @@ struct WqrKept {
 };
 hipError_t small_wqr_end(SmallState *st, StepReport *rep, int nk, WqrKept kept, hipStream_t stream);
 
-// Second pass: R2 from G2 = Q1^H Q1, beta_{i+1} = R2 R1, C_j = -beta_{i+1} M_{j,i}
-// (= Z_{j,i+1}), estimated residuals and freezing; rotates b, bp.  Does
-// nothing while st->redo is set.
+// Second pass: R2 from G2 = Q1^H Q1 (Q1 = W'' C1, the basis update as
+// stored), R2inv = R2^{-1}, beta_{i+1} = R2 R1, C_j = -beta_{i+1} M_{j,i}
+// (= Z_{j,i+1}), estimated residuals and freezing; Nv = G2 when the second
+// pass is skipped, else I; rotates b, bp.  Does nothing while st->redo is set.
 hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double tol, int freeze,
                         const int32_t *shift_list, int nact, hipStream_t stream);
 

@@ -242,6 +242,22 @@ void release_rings(dsbcg_ctx *h) {
         }
 }
 
+// Every device buffer of the handle except the staged links, the small
+// algebra state and the partial sums (dsbcg_release_workspace, and the end of
+// a solve without opts.keep_workspace).
+void release_workspace(dsbcg_ctx *h) {
+    release_rings(h);
+    DevBuf *big[] = {&h->V0, &h->T, &h->W, &h->P[0], &h->P[1], &h->X, &h->T32, &h->W32, &h->P32[0],
+                     &h->P32[1], &h->Bint, &h->Q, &h->wbuf, &h->R0, &h->R1, &h->R2, &h->R3, &h->Rres,
+                     &h->Xref, &h->Xin, &h->Yout, &h->Ycm, &h->Xrat, &h->rpart, &h->wtable, &h->colptr};
+    for (DevBuf *b : big)
+        if (b->p) {
+            (void)hipFree(b->p);
+            b->p = nullptr;
+            b->bytes = 0;
+        }
+}
+
 // ensure() for per-solve workspace: on a failed allocation the window rings
 // are released and the allocation is tried once more.
 int ensure_ws(dsbcg_ctx *h, DevBuf &b, size_t bytes) {
@@ -252,7 +268,7 @@ int ensure_ws(dsbcg_ctx *h, DevBuf &b, size_t bytes) {
 }
 
 int ensure_common(dsbcg_ctx *h) {
-    CHK(ensure(h->partials, (size_t)h->nwg_max * 256 * sizeof(zd)));
+    CHK(ensure(h->partials, (size_t)h->nwg_max * kPartialStride * sizeof(zd)));
     CHK(ensure(h->red, 8 * 256 * sizeof(zd)));
     CHK(ensure(h->list, 64 * sizeof(int32_t)));
     CHK(ensure(h->st, sizeof(SmallState)));
@@ -290,20 +306,26 @@ struct Ts {
         double per_row = 0;
         for (int k = 0; k < a.K; ++k) per_row += a.bx[k];
         if (a.out) per_row += a.bout;
-        if (a.gram == 2) per_row += a.bl;
+        if (a.gram == 2 || a.gram == 4) per_row += a.bl;
         const double bytes = per_row * (double)nrows * (fp64 ? sizeof(zd) : sizeof(zf));
         int nwg = 0;
         PROF_LAUNCH(h, prof_cls(kProfBlock, fp64), bytes, st, ts_run(fp64, a, h->nwg_max, &nwg, st));
         if (nwg_out) *nwg_out = nwg;
         return DSBCG_OK;
     }
-    // run + reduce of rows p < rows_used into red slot k
+    // run + reduce of rows p < rows_used into red slot k (gram 4: L^H out
+    // into slot k, out^H out into slot k + 1)
     int run_reduce(TsArgs a, int rows_used, int k) {
         int nwg = 0;
         CHK(run(a, &nwg));
-        if (rows_used > 0)
+        if (rows_used > 0) {
             PROF_LAUNCH(h, kProfSmall, 0.0, st,
                         reduce_partials((zd *)h->partials.p, nwg, rows_used * 16, red_slot(h, k), st));
+            if (a.gram == 4)
+                PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                            reduce_partials((zd *)h->partials.p, nwg, rows_used * 16, red_slot(h, k + 1), st,
+                                            256));
+        }
         return DSBCG_OK;
     }
 };
@@ -758,14 +780,25 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     const size_t b64 = (size_t)n * wmax * sizeof(zd), b32 = (size_t)n * wmax * sizeof(zf);
     CHK(ensure_ws(h, h->T, b64));
     CHK(ensure_ws(h, h->W, b64));
-    CHK(ensure_ws(h, h->P[0], b64 * s));
-    CHK(ensure_ws(h, h->P[1], b64 * s));
     if (form32) {
         CHK(ensure_ws(h, h->T32, b32));
         CHK(ensure_ws(h, h->W32, b32));
-        CHK(ensure_ws(h, h->P32[0], b32 * s));
-        CHK(ensure_ws(h, h->P32[1], b32 * s));
     }
+    // the P_j buffers (s blocks of the widest width, two per precision) are
+    // allocated when a window first forms or reads them: a solve that one
+    // window covers never does
+    // (plain ensure: the window rings hold live blocks by then and must not
+    // be released to make room)
+    auto ensure_p = [&](bool f64s) -> int {
+        if (f64s) {
+            CHK(ensure(h->P[0], b64 * s));
+            CHK(ensure(h->P[1], b64 * s));
+        } else {
+            CHK(ensure(h->P32[0], b32 * s));
+            CHK(ensure(h->P32[1], b32 * s));
+        }
+        return DSBCG_OK;
+    };
     CHK(ensure(h->wcoef, wincoef_bytes()));
     CHK(ensure(h->wlist, 64 * sizeof(int32_t)));
     const WinCoef WC = wincoef_at(h->wcoef.p);
@@ -809,12 +842,22 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         }
     if ((int)h->Vring.size() < nring64) h->Vring.resize(nring64);
     if ((int)h->Vring32.size() < nring32) h->Vring32.resize(nring32);
-    for (int k = 1; k < nring64; ++k) CHK(ensure(h->Vring[k], b64));
-    for (int k = 0; k < nring32; ++k) CHK(ensure(h->Vring32[k], b32));
-    std::vector<void *> ring64(nring64), ring32(nring32);
+    // slots are allocated when a step first takes them (slot_in), so a solve
+    // holds only the blocks its windows keep
+    std::vector<void *> ring64(nring64, nullptr), ring32(nring32, nullptr);
     ring64[0] = h->V0.p;
-    for (int k = 1; k < nring64; ++k) ring64[k] = h->Vring[k].p;
-    for (int k = 0; k < nring32; ++k) ring32[k] = h->Vring32[k].p;
+    auto slot_in = [&](bool f64s, int k) -> int {
+        if (f64s) {
+            if (!ring64[k]) {
+                CHK(ensure(h->Vring[k], b64));
+                ring64[k] = h->Vring[k].p;
+            }
+        } else if (!ring32[k]) {
+            CHK(ensure(h->Vring32[k], b32));
+            ring32[k] = h->Vring32[k].p;
+        }
+        return DSBCG_OK;
+    };
     // coefficient tables and window column pointers, sized for the longest
     // window (FP64 part and FP32 part each get their own region)
     const int kwin = std::min((int)kWinMax, K64 + (form32 ? K32 : 0));
@@ -884,6 +927,11 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             release(i);
             wset = act;
             return DSBCG_OK;
+        }
+        if (need_p || i0 >= 1) {
+            // P_{j,i0} is read or P_{j,end} formed
+            CHK(ensure_p(true));
+            if (lo || sw > 0) CHK(ensure_p(false));
         }
         // the last window of the solve also writes its shifts' X_j to the caller
         zd *xapi = (!need_p && !rmode && Xapi) ? (zd *)Xapi : nullptr;
@@ -1091,9 +1139,22 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             // previous step hands over P_{j,i-1} in FP32.
             free32.clear();
             for (int k = nring32 - 1; k >= 2; --k) free32.push_back(k);
+            CHK(slot_in(false, 1));
             CHK(copy(h, b, cm(ring64[v64[i]], n, true), cm(ring32[1], n, false), false, st));
             v32[i] = 1;
+            {
+                // the Gram of V_i as rounded to FP32 (slot 3) for the next Gram correction
+                Ts ts32{h, false, st, n};
+                TsArgs a = ts_args(n);
+                a.K = 1;
+                a.X[0] = ring32[1]; a.bx[0] = b; a.C[0] = nullptr;
+                a.bout = b;
+                a.gram = 1;
+                CHK(ts32.run_reduce(a, b, 3));
+                PROF_LAUNCH(h, kProfSmall, 0.0, st, small_set_nv(S, red_slot(h, 3), st));
+            }
             if (i > 1) {
+                CHK(slot_in(false, 0));
                 CHK(copy(h, bp, cm(ring64[v64[i - 1]], n, true), cm(ring32[0], n, false), false, st));
                 v32[i - 1] = 0;
             } else {
@@ -1102,6 +1163,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             if (i0 < i - 1) {
                 sw = i;
             } else if (i > 1) {
+                CHK(ensure_p(false));
                 for (int j : act)
                     CHK(copy(h, bp, cm((zd *)h->P[pcur].p + (int64_t)j * n * wmax, n, true),
                              cm((zf *)h->P32[pcur].p + (int64_t)j * n * wmax, n, false), false, st));
@@ -1125,24 +1187,29 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             break;
         }
         (lo ? v32 : v64)[i + 1] = fl.back();
+        CHK(slot_in(!lo, fl.back()));
         fl.pop_back();
         void *Vc = ring(i), *Vp = i > 1 ? ring(i - 1) : ring(i), *Vn = ring(i + 1);
         void *T = lo ? h->T32.p : h->T.p, *Wb = lo ? h->W32.p : h->W.p;
         const void *Ul = lo ? h->Ul32.p : h->Ul64.p;
     // W = A V_i
         CHK(apply_A_cm(h, f64, Ul, kappa, Vc, T, Wb, b, st));
-        // alpha_i = V_i^H (W - V_{i-1} beta_i^H)
+        // One pass over W, V_{i-1}, V_i: W' = W - V_{i-1} beta_i^H (not stored),
+        // M = V_i^H W' (slot 0) and G' = W'^H W' (slot 1).
+        const double col_bytes = (double)n * (f64 ? sizeof(zd) : sizeof(zf));
         {
             TsArgs a = ts_args(n);
             a.K = (i > 1) ? 2 : 1;
             a.X[0] = Wb; a.bx[0] = b; a.C[0] = nullptr;
             a.X[1] = Vp; a.bx[1] = bp; a.C[1] = coef_slot(h, 0);
             a.bout = b;
-            a.gram = 2; a.L = Vc; a.bl = b;
+            a.gram = 4; a.L = Vc; a.bl = b;
             CHK(ts.run_reduce(a, b, 0));
         }
-        // hermitised alpha_i, -alpha_i as a coefficient
+        // alpha_i = herm(M), -alpha_i as a coefficient; the Gram of
+        // W'' = W' - V_i alpha_i from M, G' and alpha_i (slot 2)
         PROF_LAUNCH(h, kProfSmall, 0.0, st, small_prep_alpha(S, red_slot(h, 0), st));
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_lanczos_gram(S, red_slot(h, 0), red_slot(h, 1), red_slot(h, 2), st));
         // per-shift coefficients and the window recurrences
         for (size_t q = 0; q < act.size(); ++q) h->list_host[q] = act[q];
         HIPCHK(hipMemcpyAsync(h->list.p, h->list_host, act.size() * sizeof(int32_t) + 4,
@@ -1161,66 +1228,81 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             PROF_LAUNCH(h, kProfSmall, 0.0, st,
                         small_window_update(S, rep, WC, wsp, (const int32_t *)h->list.p, (int)act.size(), st));
         }
-        // W <- W - V_i alpha_i - V_{i-1} beta_i^H  and  G1 = W^H W
+        // first CholQR pass with deflation on the Gram of W''
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 2), lo ? tau32 : o.tau_W, st,
+                                       red_slot(h, 1)));
+        PROF_LAUNCH(h, kProfSmall, 0.0, st, small_basis_coefs(S, st));
+        // V' = W'' C1 = W C1 - V_i alpha_i C1 - V_{i-1} beta_i^H C1 into V_{i+1}'s
+        // slot, with its Gram G2 = V'^H V' (slot 3) from the values stored:
+        // the first bnew columns are the new block (the others are zero and
+        // never read).  Skipped on the device when the step's QR has to be
+        // redone column by column.
         {
             TsArgs a = ts_args(n);
             a.K = (i > 1) ? 3 : 2;
-            a.X[0] = Wb; a.bx[0] = b; a.C[0] = nullptr;
-            a.X[1] = Vc; a.bx[1] = b; a.C[1] = coef_slot(h, 1);
-            a.X[2] = Vp; a.bx[2] = bp; a.C[2] = coef_slot(h, 0);
-            a.bout = b;
-            a.out = Wb;
-            a.gram = 1;
-            CHK(ts.run_reduce(a, b, 1));
-        }
-        // first CholQR pass with deflation
-        PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                    small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 1), lo ? tau32 : o.tau_W, st));
-        // second pass: G2 = (W C1)^H (W C1); C1 has zero columns past the new
-        // width.  Skipped on the device when the first pass sets skip_qr2.
-        {
-            TsArgs a = ts_args(n);
-            a.K = 1;
-            a.X[0] = Wb; a.bx[0] = b; a.C[0] = S->C1;
-            a.bout = b;
-            a.gram = 1;
-            a.skip = &S->skip_qr2;
-            CHK(ts.run_reduce(a, b, 2));
-        }
-        PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                    small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
-                                 (int)act.size(), st));
-        // V_{i+1} = W Rinv: the first bnew columns are the new block (the
-        // others are zero and never read).  Skipped on the device when the
-        // step's QR has to be redone column by column.
-        {
-            TsArgs a = ts_args(n);
-            a.K = 1;
-            a.X[0] = Wb; a.bx[0] = b; a.C[0] = S->Rinv;
+            a.X[0] = Wb; a.bx[0] = b; a.C[0] = S->cB[0];
+            a.X[1] = Vc; a.bx[1] = b; a.C[1] = S->cB[1];
+            a.X[2] = Vp; a.bx[2] = bp; a.C[2] = S->cB[2];
             a.bout = b;
             a.out = Vn;
+            a.gram = 1;
             a.skip = &S->redo;
+            CHK(ts.run_reduce(a, b, 3));
+        }
+        // second CholQR pass, only when the kept columns are ill-conditioned
+        // (skipped on the device otherwise): V_{i+1} = V' R2^{-1}, R2 from G2
+        PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                    small_finish(S, rep, red_slot(h, 3), tol, o.freeze, (const int32_t *)h->list.p,
+                                 (int)act.size(), st));
+        {
+            TsArgs a = ts_args(n);
+            a.K = 1;
+            a.X[0] = Vn; a.bx[0] = b; a.C[0] = S->R2inv;
+            a.bout = b;
+            a.out = Vn;  // in place: every thread reads its rows before writing them
+            a.skip = &S->skip_qr2;
             CHK(ts.run(a, nullptr));
         }
         CHK(read_report(h, st));
         if (h->prof && h->rep_host->skip_qr2) {
             // the second-pass launch returned at once: it moved no data
             const int cls = prof_cls(kProfBlock, f64);
-            h->prof_bytes[cls] -= (double)b * n * (f64 ? sizeof(zd) : sizeof(zf));
+            h->prof_bytes[cls] -= 2.0 * b * col_bytes;
             h->prof_launches[cls] -= 1;
         }
         if (h->rep_host->flags & kFlagRedoQR) {
             // a drop decision below the resolution of the Gram matrix: the
-            // skipped scaling moved no data; redo the QR of W column by column
+            // skipped basis update moved no data; form W'' and redo its QR
+            // column by column
             if (h->prof) {
                 const int cls = prof_cls(kProfBlock, f64);
-                h->prof_bytes[cls] -= 2.0 * b * n * (f64 ? sizeof(zd) : sizeof(zf));
+                h->prof_bytes[cls] -= (3.0 * b + bp) * col_bytes;
                 h->prof_launches[cls] -= 1;
+            }
+            {
+                TsArgs a = ts_args(n);
+                a.K = (i > 1) ? 3 : 2;
+                a.X[0] = Wb; a.bx[0] = b; a.C[0] = nullptr;
+                a.X[1] = Vc; a.bx[1] = b; a.C[1] = coef_slot(h, 1);
+                a.X[2] = Vp; a.bx[2] = bp; a.C[2] = coef_slot(h, 0);
+                a.bout = b;
+                a.out = Wb;
+                CHK(ts.run(a, nullptr));
             }
             int nk = 0;
             CHK(redo_wqr(h, f64, Wb, Vn, b, lo ? tau32 : o.tau_W, st, &nk));
+            if (nk > 0) {
+                // Gram of the new block as stored (slot 3), kept for the next step
+                TsArgs a = ts_args(n);
+                a.K = 1;
+                a.X[0] = Vn; a.bx[0] = nk; a.C[0] = nullptr;
+                a.bout = nk;
+                a.gram = 1;
+                CHK(ts.run_reduce(a, nk, 3));
+            }
             PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                        small_finish(S, rep, red_slot(h, 2), tol, o.freeze, (const int32_t *)h->list.p,
+                        small_finish(S, rep, red_slot(h, 3), tol, o.freeze, (const int32_t *)h->list.p,
                                      (int)act.size(), st));
             CHK(read_report(h, st));
             stt.qr_redone += 1;
@@ -1295,6 +1377,7 @@ void dsbcg_default_opts(dsbcg_opts *o) {
     o->freeze = 1;
     o->switch_at = -1.0;  // resolved to min(1e-2, 1e5 * tol)
     o->window = 0;        // automatic window length
+    o->keep_workspace = 1;
 }
 
 const char *dsbcg_last_error(void) { return g_err.c_str(); }
@@ -1557,16 +1640,36 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
 
 extern "C" {
 
+// Releases the solve workspace on every return of a solve entry point unless
+// the caller asked to keep it (opts->keep_workspace).
+struct WorkspaceScope {
+    dsbcg_ctx *h;
+    bool keep;
+    WorkspaceScope(dsbcg_ctx *hh, const dsbcg_opts *opts) : h(hh), keep(!opts || opts->keep_workspace) {}
+    ~WorkspaceScope() {
+        if (h && !keep) release_workspace(h);
+    }
+};
+
 int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
                 const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
                 dsbcg_stats *stats, dsbcg_stream stream) {
+    WorkspaceScope ws(h, opts);
     return solve_checked(h, U, kappa, B, 0, m, sigma, s, tol, opts, X, stats, (hipStream_t)stream);
+}
+
+int dsbcg_release_workspace(dsbcg_handle h) {
+    if (!h) return fail(DSBCG_ERR_ARG, "NULL handle");
+    HIPCHK(hipDeviceSynchronize());
+    release_workspace(h);
+    return DSBCG_OK;
 }
 
 int dsbcg_solve_rational(dsbcg_handle h, const void *U, double kappa, const void *B, int32_t m,
                          const double *sigma, const double *coef, int32_t s, double c0, double tol,
                          const dsbcg_opts *opts, void *Y, dsbcg_stats *stats, dsbcg_stream stream) {
     hipStream_t st = (hipStream_t)stream;
+    WorkspaceScope ws(h, opts);
     dsbcg_opts o;
     CHK(solve_args(h, U, B, m, sigma, s, tol, kappa, Y, opts, &o));
     if (!coef) return fail(DSBCG_ERR_ARG, "NULL argument");
@@ -1606,6 +1709,7 @@ int dsbcg_solve_multi(dsbcg_handle h, const void *U, double kappa, const void *B
                       const double *sigma, int32_t s, double tol, const dsbcg_opts *opts, void *X,
                       dsbcg_stats *stats, dsbcg_stream stream) {
     if (!h) return fail(DSBCG_ERR_ARG, "NULL handle");
+    WorkspaceScope ws(h, opts);
     return solve_checked(h, U, kappa, B, 12 * (int64_t)h->g.V * m, m, sigma, s, tol, opts, X, stats,
                          (hipStream_t)stream);
 }

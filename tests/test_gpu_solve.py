@@ -310,3 +310,35 @@ def test_fp64_form_full_size_32x32x32x64():
         on_sites = np.sqrt((np.abs(R) ** 2).sum(axis=(0, 1, 2)))
         assert np.all(on_sites <= w.tol * bnorm), j
         del Xh
+
+
+def test_workspace_kept_by_default_and_released_on_request():
+    """A solve with keep_workspace = 0 frees its device workspace at return; by
+    default the handle keeps it, and dsbcg_release_workspace frees it.  The
+    results are the same."""
+    import torch
+    w = inputs.WORKLOADS["smooth16^4_m4_s6_grad"]
+    announce("workspace", w.name)
+    U, B = w.make()
+    h = dsb.Handle(w.L)
+    dU, dB = dev(U), dev(B)
+    dsb.dsbcg_stage_links(h, dU)
+    X = torch.empty((len(w.shifts), w.V, 4, 3, w.m), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    X1, s1 = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, X=X, keep_workspace=0)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    x1 = host(X1).copy()
+    X2, s2 = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, X=X)
+    torch.cuda.synchronize()
+    free2 = torch.cuda.mem_get_info()[0]
+    assert np.array_equal(host(X2), x1) and s1["block_iters"] == s2["block_iters"]
+    dsb.dsbcg_release_workspace(h)
+    torch.cuda.synchronize()
+    free3 = torch.cuda.mem_get_info()[0]
+    # the iterates alone are s * 12 V m complex128 = 201 MB
+    held = 12 * w.V * w.m * len(w.shifts) * 16
+    assert free0 - free1 < 64 << 20, (free0, free1)
+    assert free1 - free2 > held, (free1, free2)
+    assert free0 - free3 < 64 << 20, (free0, free3)
