@@ -63,8 +63,14 @@ def parse():
     p.add_argument("--summarize-stats", metavar="STATS_DIR",
                    help="print a per-class summary of a rocprofv3 --kernel-trace --stats CSV run, "
                         "then exit")
+    p.add_argument("--switch-sweep", metavar="VALUES",
+                   help="comma-separated switch_at values: time the FP32 form at each, without and "
+                        "with the FP64 re-solve, print one JSON line per value and exit")
+    p.add_argument("--summarize-counters", metavar="PMC_DIR",
+                   help="print per-kernel averages of every counter of a rocprofv3 --pmc CSV run "
+                        "(with the dispatch durations of that run), then exit")
     p.add_argument("--command", default="", help="command line recorded with --ingest-counters / "
-                                                 "--summarize-stats")
+                                                 "--summarize-stats / --summarize-counters")
     p.add_argument("--cpu-sample-only", action="store_true",
                    help="time the oracle sample with the threads the environment gives it, print "
                         "its JSON and exit (run by the benchmark itself as a 1-thread child)")
@@ -164,6 +170,35 @@ def ingest_counters(fetch_dir, write_dir, command):
     with open(path, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
     print(json.dumps(rec, indent=1, sort_keys=True))
+
+
+def summarize_counters(pmc_dir, command):
+    """Per kernel (name) and counter: the average value per dispatch and the
+    average dispatch duration under counter collection, as a markdown table."""
+    disp = {}
+    for r in _csv_rows(pmc_dir, "counter_collection.csv"):
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        e = disp.setdefault(d, {"name": r.get("Kernel_Name", ""), "c": {},
+                                "ns": float(r["End_Timestamp"]) - float(r["Start_Timestamp"])})
+        cn = r.get("Counter_Name")
+        e["c"][cn] = e["c"].get(cn, 0.0) + float(r.get("Counter_Value", 0) or 0)
+    per = {}
+    for e in disp.values():
+        if kernel_class(e["name"]) is None:
+            continue
+        k = per.setdefault(e["name"], {"n": 0, "ns": 0.0, "c": {}})
+        k["n"] += 1
+        k["ns"] += e["ns"]
+        for cn, v in e["c"].items():
+            k["c"][cn] = k["c"].get(cn, 0.0) + v
+    names = sorted({cn for k in per.values() for cn in k["c"]})
+    lines = [f"command: {command}", "", "| kernel | class | dispatches | avg us (profiled) | " +
+             " | ".join(names) + " |", "|---|---|---|---|" + "---|" * len(names)]
+    for name, k in sorted(per.items(), key=lambda kv: -kv[1]["ns"]):
+        short = name if len(name) < 80 else name[:77] + "..."
+        vals = " | ".join(f"{k['c'].get(cn, 0.0) / k['n']:.4g}" for cn in names)
+        lines.append(f"| `{short}` | {kernel_class(name)} | {k['n']} | {k['ns'] / k['n'] / 1e3:.1f} | {vals} |")
+    print("\n".join(lines))
 
 
 def summarize_stats(stats_dir, command):
@@ -494,6 +529,33 @@ def cpu_baseline(w, gpu_iters, steps, max_sites=1 << 17, one_thread=None):
     return out
 
 
+def switch_sweep(dsb, h, dB, w, values):
+    """The FP32 form with FP32 vectors from switch_at on: per value, the run
+    without re-solves (largest FP64 true relative residual after the main
+    phase, the steps run in FP32, time) and with them (re-solve block steps,
+    time, final residual)."""
+    import torch
+    for v in values:
+        out = {"switch_at": v}
+        for refine in (0, 1):
+            kw = {"precision": dsb.DSBCG_FP32_RELIABLE, "switch_at": v, "refine": refine,
+                  "keep_workspace": 1}
+            X, st = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, raise_not_converged=False, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, st = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, X=X, raise_not_converged=False, **kw)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            tag = "refine" if refine else "main"
+            out[tag] = {"ms": round(ms, 1), "block_iters": st["block_iters"], "switch_iter": st["switch_iter"],
+                        "fp32_steps": (st["block_iters"] - st["switch_iter"] + 1) if st["switch_iter"] else 0,
+                        "main_relres_max": st["main_relres_max"], "refine_iters": st["refine_iters"],
+                        "true_relres_max": float(st["true_relres"].max()),
+                        "est_relres_max": float(st["est_relres"].max()), "status": st["status"]}
+            del X
+        print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.ingest_counters:
@@ -501,6 +563,9 @@ def main():
         return
     if args.summarize_stats:
         summarize_stats(args.summarize_stats, args.command)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.command)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
@@ -537,6 +602,9 @@ def main():
     # the gauge field is staged once, outside the timed region, as a caller
     # solving many right-hand-side blocks on one configuration would do
     dsb.dsbcg_stage_links(h, dU)
+    if args.switch_sweep:
+        switch_sweep(dsb, h, dB, w, [float(v) for v in args.switch_sweep.split(",")])
+        return
 
     forms = [args.precision]
     if args.compare:

@@ -85,8 +85,10 @@ typedef struct {
                              times the column's squared norm while the threshold lies below
                              that level) the step's QR is redone by classical Gram-Schmidt
                              applied twice, column by column, as for B */
-    int32_t refine;       /* 1: after the main phase, re-solve (FP64) the shifts whose true
-                             residual misses tol (default 1) */
+    int32_t refine;       /* 1: after the main phase, re-solve the shifts whose true residual
+                             misses tol, (sigma_j + A) E = R_j, X_j += E (default 1); in the FP32
+                             form the first round of re-solves runs with FP32 vectors, a second
+                             round (if needed) in FP64 */
     int32_t freeze;       /* 1: stop updating a system once its estimate reaches tol (default 1) */
     int32_t window;       /* per-shift update window: the Lanczos blocks of up to `window`
                              block steps are kept and X_j (and P_j, if the iteration goes on)
@@ -225,7 +227,7 @@ int dsbcg_solve(dsbcg_handle h, const void *U, double kappa, const void *B, int3
  *     estimated residuals of the method (Sec. 3): stats->true_relres is filled
  *     with -1 (not formed) and main_relres_max is -1.
  *   DSBCG_FP32_RELIABLE: the checked solve of dsbcg_solve (FP64 true
- *     residuals, FP64 re-solve of shifts that miss tol) into a workspace of
+ *     residuals, re-solves of shifts that miss tol) into a workspace of
  *     s*V*12*m complex128, then the sum.
  * A frozen or converged system contributes its final iterate.  Returns with
  * `stream` synchronised; errors as dsbcg_solve (ERR_NOT_CONVERGED leaves the

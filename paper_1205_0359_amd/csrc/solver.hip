@@ -1603,7 +1603,10 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
                 for (int l = 0; l < m; ++l) worst = std::max(worst, tr[j * m + l]);
                 if (worst <= tol) continue;
                 any = true;
-                // residual block R_j, then (sigma_j + A) E = R_j in FP64 and X_j += E
+                // residual block R_j, then (sigma_j + A) E = R_j and X_j += E.  The
+                // first round of the FP32 form solves with FP32 vectors from the
+                // start: it only has to reduce R_j by a small factor, far above
+                // the FP32 residual gap; a second round runs in FP64.
                 CHK(ensure_ws(h, h->Rres, (size_t)n * m * sizeof(zd)));
                 CHK(ensure_ws(h, h->Xref, (size_t)n * m * sizeof(zd)));
                 std::vector<double> tmp((size_t)s * m);
@@ -1612,12 +1615,14 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
                 for (int l = 0; l < m; ++l)
                     if (tr[j * m + l] > 0) ratio = std::min(ratio, 1.0 / tr[j * m + l]);
                 dsbcg_opts ro = o;
-                ro.precision = DSBCG_FP64;
+                const bool r32 = o.precision == DSBCG_FP32_RELIABLE && round == 0;
+                ro.precision = r32 ? DSBCG_FP32_RELIABLE : DSBCG_FP64;
                 ro.fixed_iters = 0;
                 ro.tau_B = 0.1 * tol;
                 SolveStats rs;
                 const double rtol = std::max(0.5 * tol * ratio, 1e-15);
-                int rc = solve_core(h, kappa, h->Rres.p, 0, m, &sigma[j], 1, rtol, ro, 0.0, h->Xref.p, rs, st, nullptr);
+                int rc = solve_core(h, kappa, h->Rres.p, 0, m, &sigma[j], 1, rtol, ro, r32 ? 2.0 : 0.0, h->Xref.p,
+                                    rs, st, nullptr);
                 if (rc != DSBCG_OK && rc != DSBCG_ERR_NOT_CONVERGED) return rc;
                 stt.refine_iters += rs.block_iters;
                 stt.mvms += rs.mvms;

@@ -96,8 +96,8 @@ def test_autograd_trace_loss_against_oracle(prec):
 
 
 def test_autograd_link_gradient_finite_differences():
-    """Central differences of the loss on 16 random link entries (real and imaginary
-    parts), each loss evaluated with FP64 solves to 1e-13."""
+    """Central differences of the loss on 32 random link entries (real or imaginary
+    part), each loss evaluated with FP64 solves to 1e-13."""
     import torch
     L, kappa = (4, 4, 4, 4), 0.12
     announce("autograd FD", L)
@@ -112,7 +112,7 @@ def test_autograd_link_gradient_finite_differences():
 
     rng = inputs.rng_for(893, 3)
     eps = 1e-5
-    for _ in range(16):
+    for _ in range(32):
         idx = (rng.integers(0, 256), rng.integers(0, 4), rng.integers(0, 3), rng.integers(0, 3))
         unit = 1.0 if rng.integers(0, 2) == 0 else 1j
         Up, Um = U.copy(), U.copy()

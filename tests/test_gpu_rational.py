@@ -17,7 +17,7 @@ import oracle
 from paper_1205_0359_amd import inputs
 import paper_1205_0359_amd as dsb
 
-from gpu_util import announce, dev, host, rel_fro
+from gpu_util import announce, dev, host, rel_fro, rel_max
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +60,7 @@ def test_fixed_iterations_match_oracle(window):
     Y, st = _rational(L, U, kappa, B, sig, COEF4, 0.7, 1e-30, fixed_iters=k, window=window)
     assert st["block_iters"] == k and st["rank0"] == m
     assert rel_fro(Y.reshape(n, m), want) <= 1e-10
+    assert rel_max(Y.reshape(n, m), want) <= 1e-10
     np.testing.assert_allclose(st["est_relres"], ref.est, rtol=1e-8, atol=1e-14)
     assert np.all(st["true_relres"] == -1.0) and st["main_relres_max"] == -1.0
 
@@ -77,6 +78,7 @@ def test_fixed_iterations_ragged_rows():
     Y, st = _rational(L, U, kappa, B, sig, COEF4[:3], -0.4, 1e-30, fixed_iters=k, window=3)
     assert st["block_iters"] == k
     assert rel_fro(Y.reshape(n, m), want) <= 1e-10
+    assert rel_max(Y.reshape(n, m), want) <= 1e-10
 
 
 @pytest.mark.parametrize("window", [0, 2])

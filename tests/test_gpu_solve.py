@@ -11,7 +11,7 @@ import oracle
 from paper_1205_0359_amd import inputs
 import paper_1205_0359_amd as dsb
 
-from gpu_util import announce, dev, host, rel_fro
+from gpu_util import announce, dev, host, rel_fro, rel_max
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +58,7 @@ def test_fixed_iteration_parity_fp64(L, m, sig, k, kind):
     for j in range(len(sig)):
         got = X[j].reshape(n, m)
         assert rel_fro(got, ref.X[j]) <= 1e-10, j
+        assert rel_max(got, ref.X[j]) <= 1e-10, j
     np.testing.assert_allclose(st["est_relres"], ref.est, rtol=1e-8, atol=1e-14)
 
 
@@ -74,6 +75,7 @@ def test_window_lengths_fixed_iterations(window):
     X, st = _gpu_solve(L, U, kappa, B, sig, 1e-30, fixed_iters=k, window=window)
     for j in range(len(sig)):
         assert rel_fro(X[j].reshape(n, m), ref.X[j]) <= 1e-10, j
+        assert rel_max(X[j].reshape(n, m), ref.X[j]) <= 1e-10, j
 
 
 def test_window_with_freezing():
@@ -237,6 +239,7 @@ def test_wide_outputs_over_several_windows(m, s, window):
     assert st["block_iters"] == k
     for j in range(s):
         assert rel_fro(X[j].reshape(n, m), ref.X[j]) <= 1e-10, j
+        assert rel_max(X[j].reshape(n, m), ref.X[j]) <= 1e-10, j
 
 
 def test_mvm_ordering_of_table_1_through_the_library():
