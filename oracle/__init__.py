@@ -7,7 +7,9 @@ computes, written from the paper and sharing no code with the HIP library:
   * ``wilson_oracle.c``  the Wilson-Dirac operator D, D^H, A = D^H D, the
     neighbour table and the link derivative (C, loops over sites);
   * ``dsbcg.py``         the deflated shifted block CG method in block form
-    (numpy), following Sec. 3 of the paper.
+    (numpy), following Sec. 3 of the paper;
+  * ``vectorwise.py``    the same method stopping each system at its own
+    Lanczos vector, from the dense definition of the k-th iterate (eq. (3.2)).
 
 Every function is pinned by CPU tests against facts fixed outside the oracle
 (closed forms, textbook special cases, dense solves).
@@ -20,5 +22,6 @@ __all__ = ["apply_D", "apply_A", "apply_D_sites", "apply_A_sites", "neighbors", 
            "link_grad", "max_threads", "load", "dsbcg", "deflated_qr", "true_relres",
            "partial_fraction", "NotHPD", "Result"]
 from .grad import adjoint_gradients  # noqa: E402
+from .vectorwise import dsbcg_vectorwise, stage_solution, VectorResult  # noqa: E402
 
-__all__.append("adjoint_gradients")
+__all__ += ["adjoint_gradients", "dsbcg_vectorwise", "stage_solution", "VectorResult"]
