@@ -54,6 +54,9 @@ def parse():
     p.add_argument("--rational", action="store_true", default=True,
                    help="also time the FP64 partial-fraction form on the same workload")
     p.add_argument("--no-rational", dest="rational", action="store_false")
+    p.add_argument("--vector-stop", action="store_true", default=True,
+                   help="also time the headline form with vector-wise stopping (default on)")
+    p.add_argument("--no-vector-stop", dest="vector_stop", action="store_false")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run a plain 1 GiB device copy (the reference kernel for "
                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -274,6 +277,36 @@ def stored_traffic(kernel: str, digest: str):
     if not ent or ent.get("source_digest") != digest:
         return None
     return ent.get("bytes_per_launch")
+
+
+def vector_stop_rate(dsb, h, dB, w, prec, steps):
+    """The headline form with vector-wise stopping (opts.vector_stop = 1): time
+    per solve, and the Lanczos-vector count at which the last system stopped
+    against the block count."""
+    import numpy as np
+    import torch
+    kw = {"precision": dsb.DSBCG_FP32_RELIABLE if prec == "fp32" else dsb.DSBCG_FP64,
+          "keep_workspace": 1, "vector_stop": 1}
+    X, st = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X, st = dsb.dsbcg_solve(h, None, w.kappa, dB, w.shifts, w.tol, X=X, **kw)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    worst = float(st["true_relres"].max())
+    if worst > w.tol:
+        raise RuntimeError(f"vector-wise stopping: true relative residual {worst:.3e} above {w.tol}")
+    fz = np.asarray(st["frozen_at"])
+    width_end = st["widths"][-1] if st["widths"] else 0
+    bounds = np.cumsum(st["widths"])
+    log(f"[bench] vector-wise stopping: {1e3 * sec / steps:.1f} ms per solve, "
+        f"mvms {st['mvms']} -> {st['mvms_vector']}")
+    del X
+    return {"ms_per_step": 1e3 * sec / steps, "systems_per_s": w.m * len(w.shifts) * steps / sec,
+            "mvms": st["mvms"], "mvms_vector": st["mvms_vector"],
+            "systems_stopped_inside_a_block": int(((fz > 0) & ~np.isin(fz, bounds)).sum()),
+            "last_block_width": width_end, "max_true_relres": worst, "steps": steps}
 
 
 def run_form(dsb, h, dU, dB, w, prec, steps, warmup):
@@ -622,6 +655,11 @@ def main():
             results[prec] = {"unavailable": str(e)}
     head = results[args.precision]
 
+    vstop = None
+    if args.vector_stop:
+        vstop = vector_stop_rate(dsb, h, dB, w, args.precision, max(1, min(args.steps, 3)))
+        torch.cuda.empty_cache()
+
     rational = None
     if args.rational:
         rational = rational_rate(dsb, h, dU, dB, w, args.steps, args.warmup)
@@ -679,6 +717,7 @@ def main():
         "cpu_baseline": cpu,
         "grad": grad,
         "partial_fraction": rational,
+        "vector_stop": vstop,
         "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()},
     }
     print(json.dumps(line), flush=True)

@@ -108,6 +108,16 @@ typedef struct {
                              (the staged links stay).  Allocating the workspace of the
                              32^3 x 64, m = 8, s = 10 solve costs seconds, against 0.42 s
                              for the solve itself */
+    int32_t vector_stop;  /* 1: stopping granularity of one Lanczos vector (Sec. 3: the iterates
+                             advance one basis vector at a time, X^(k) = X^(k-1) + p^(k) u^(k) /
+                             d^(k)): inside every block step the residual estimates of the
+                             Galerkin iterates on the first K + r basis vectors (K before the
+                             block, r = 1..b) are formed from the block's small matrices, and a
+                             system stops at the first r whose estimate is <= tol, keeping that
+                             iterate.  Needs freeze = 1.  The block step still applies A to all
+                             its b vectors, so the saving is in the iterate, not in time; see
+                             dsbcg_stats.mvms_vector.  0 (default): systems stop at block
+                             boundaries */
 } dsbcg_opts;
 
 typedef struct {
@@ -137,6 +147,14 @@ typedef struct {
     int32_t widths_len;
     int32_t qr_redone;        /* block steps whose deflated QR was redone column by column
                                  (see dsbcg_opts.tau_W) */
+    int64_t mvms_vector;      /* main phase: the number of Lanczos vectors through the stage at
+                                 which the last system stopped, i.e. the applications of A the
+                                 vector-wise process of Sec. 3 needs (every vector of the run
+                                 when some system never stopped); equals the block count of the
+                                 stopping step's end unless opts.vector_stop = 1 */
+    int32_t *frozen_at;       /* host [s*m] (index j*m + l) or NULL: main phase, the number of
+                                 Lanczos vectors through the stage at which (l, j) stopped (0:
+                                 it never stopped, or its column of B is zero) */
 } dsbcg_stats;
 
 /* Fill opts with the defaults listed above. */

@@ -46,7 +46,8 @@ class dsbcg_opts(ctypes.Structure):
                 ("tau_B", ctypes.c_double),
                 ("tau_W", ctypes.c_double), ("refine", ctypes.c_int32),
                 ("freeze", ctypes.c_int32), ("window", ctypes.c_int32),
-                ("switch_at", ctypes.c_double), ("keep_workspace", ctypes.c_int32)]
+                ("switch_at", ctypes.c_double), ("keep_workspace", ctypes.c_int32),
+                ("vector_stop", ctypes.c_int32)]
 
 
 class dsbcg_stats(ctypes.Structure):
@@ -59,7 +60,8 @@ class dsbcg_stats(ctypes.Structure):
                 ("est_relres", ctypes.POINTER(ctypes.c_double)),
                 ("true_relres", ctypes.POINTER(ctypes.c_double)),
                 ("widths", ctypes.POINTER(ctypes.c_int32)), ("widths_len", ctypes.c_int32),
-                ("qr_redone", ctypes.c_int32)]
+                ("qr_redone", ctypes.c_int32), ("mvms_vector", ctypes.c_int64),
+                ("frozen_at", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -287,7 +289,10 @@ def _new_stats(s, m):
     st.true_relres = true.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     st.widths = widths.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     st.widths_len = _MAX_WIDTHS
+    frozen = np.zeros(s * m, dtype=np.int32)
+    st.frozen_at = frozen.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     st._widths_buf = widths  # kept alive with the struct
+    st._frozen_buf = frozen
     return st, est, true
 
 
@@ -300,6 +305,7 @@ def _stats_dict(code, st, est, true, s, m):
         "reliable_updates": st.reliable_updates, "refine_iters": st.refine_iters,
         "final_width": st.final_width, "switch_iter": st.switch_iter, "qr2_skipped": st.qr2_skipped,
         "main_relres_max": st.main_relres_max, "mvms": int(st.mvms),
+        "mvms_vector": int(st.mvms_vector), "frozen_at": st._frozen_buf.reshape(s, m).T.copy(),
         "est_relres": est.reshape(s, m).T.copy(), "true_relres": true.reshape(s, m).T.copy(),
     }
 

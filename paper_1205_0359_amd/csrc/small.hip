@@ -771,6 +771,147 @@ hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double to
 }
 
 // ---------------------------------------------------------------------------
+// Vector-wise stopping (Sec. 3: the iterates advance one Lanczos vector at a
+// time).  The leading part of a block root-free Cholesky factorisation of
+// T_sigma is the factorisation of its leading part, so within block step i
+// (width b, K_{i-1} vectors before it) the Galerkin iterate on the first
+// K_{i-1} + r vectors is
+//   X^(r) = X_{i-1} + P_{j,i}[:, 1..r] y_r,   y_r = Delta_r^{-1} Z_{j,i}[1..r]
+// (Delta_r the leading r x r part of Delta_{j,i}), and its residual is
+// V_i[:, r+1..b] c_a + V_{i+1} c_b with
+//   c_a = Z_{j,i}[r+1..b] - Delta_{j,i}[r+1..b, 1..r] y_r,   c_b = -beta_{i+1}[:, 1..r] y_r
+// (Z_{j,1} = rho covers the first block).  With Delta_{j,i} = L L^H and
+// w = L^{-1} Z_{j,i} = L^H M_{j,i} these are
+//   y_r = L_r^{-H} w[1..r],   c_a[a] = sum_{k = r+1..a} L[a][k] w[k].
+// r = b is the block iterate, whose estimate small_finish has computed.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void vector_stop_kernel(SmallState *st, StepReport *rep, double tol,
+                                                          const int32_t *__restrict__ list, int nact) {
+    __shared__ uint32_t mask[kS];
+    if (st->redo) return;  // uniform: the QR of this step is redone first
+    const int t = threadIdx.x;
+    const int b = st->bp, nk = st->b, m = st->m;  // small_finish has rotated the widths
+    const int js = t / kS, l = t - js * kS;
+    const bool mine = js < nact && l < m;
+    const int j = mine ? list[js] : 0;
+    if (t < nact) mask[t] = rep->colmask[list[t]];
+    __syncthreads();
+    int rstop = 0;
+    double estop = 0.0;
+    zd y[kS];
+    if (mine) {
+        for (int q = 0; q < kS; ++q) st->dM[j][q * 16 + l] = mk<double>(0, 0);
+        rep->stage[j][l] = 0;
+    }
+    if (mine && ((mask[js] >> l) & 1u)) {
+        const zd *L = st->L[j];
+        const zd *M = st->M[j];
+        const zd *BN = st->betanext;
+        const double bn = st->bnorm[st->colmap[j][l]];
+        zd w[kS];
+        for (int a = 0; a < b; ++a) {
+            zd v = mk<double>(0, 0);
+            for (int k = a; k < b; ++k) v = v + conj(L[k * 16 + a]) * M[k * 16 + l];
+            w[a] = v;
+        }
+        for (int r = 1; r < b && !rstop; ++r) {
+            double na = 0.0;
+            for (int a = r; a < b; ++a) {
+                zd v = mk<double>(0, 0);
+                for (int k = r; k <= a; ++k) v = v + L[a * 16 + k] * w[k];
+                na += norm2(v);
+            }
+            for (int q = r - 1; q >= 0; --q) {
+                zd v = w[q];
+                for (int c = q + 1; c < r; ++c) v = v - conj(L[c * 16 + q]) * y[c];
+                y[q] = zdivr(v, L[q * 16 + q].x);
+            }
+            double nb = 0.0;
+            for (int q = 0; q < nk; ++q) {
+                zd v = mk<double>(0, 0);
+                for (int k = 0; k < r; ++k) v = v + BN[q * 16 + k] * y[k];
+                nb += norm2(v);
+            }
+            const double e = (bn > 0.0) ? sqrt(na + nb) / bn : 0.0;
+            if (e <= tol) {
+                rstop = r;
+                estop = e;
+            }
+        }
+        if (!rstop && rep->est[j][l] <= tol) {
+            rstop = b;
+            estop = rep->est[j][l];
+        }
+        if (rstop) {
+            atomicAnd(&mask[js], ~(1u << l));
+            rep->est[j][l] = estop;
+            rep->stage[j][l] = rstop;
+            if (rstop < b)
+                for (int q = 0; q < b; ++q)
+                    st->dM[j][q * 16 + l] = (q < rstop ? y[q] : mk<double>(0, 0)) - M[q * 16 + l];
+        }
+    }
+    __syncthreads();
+    if (t < nact) rep->colmask[list[t]] = mask[t];
+}
+
+hipError_t small_vector_stop(SmallState *st, StepReport *rep, double tol, const int32_t *shift_list,
+                             int nact, hipStream_t stream) {
+    if (nact <= 0) return hipSuccess;
+    if (nact > kS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(vector_stop_kernel, dim3(1), dim3(256), 0, stream, st, rep, tol, shift_list, nact);
+    return hipGetLastError();
+}
+
+// One block per (active shift, window slot), as window_update_kernel.
+__global__ __launch_bounds__(64) void window_correct_kernel(const SmallState *st, WinCoef wc, WindowStep w,
+                                                            const int32_t *__restrict__ list) {
+    __shared__ zd Mh[256], A[256], tmp[256];
+    if (st->redo) return;
+    const int j = list[blockIdx.x];
+    const int u = blockIdx.y;
+    const int t = threadIdx.x;
+    if (u == w.t + 1 && w.bp0 == 0) return;
+    for (int e = t; e < 256; e += 64) {
+        const int r = e / 16, c = e - r * 16;
+        Mh[e] = (r < w.b && c < w.m) ? st->dM[j][e] : mk<double>(0, 0);
+    }
+    __syncthreads();
+    if (u == w.t + 1) {
+        zd *G = wc.Wg + j * 256, *Fp = wc.Wfp + j * 256;
+        for (int e = t; e < 256; e += 64) {
+            A[e] = G[e];
+            tmp[e] = Fp[e];
+        }
+        __syncthreads();
+        mat_mul_acc(tmp, A, Mh, w.bp0, w.b, w.m, false);
+        for (int e = t; e < 256; e += 64) Fp[e] = tmp[e];
+        return;
+    }
+    zd *H = wc.Wh + ((size_t)j * kWinMax + u) * 256, *F = wc.Wf + ((size_t)j * kWinMax + u) * 256;
+    if (u == w.t) {
+        for (int e = t; e < 256; e += 64) F[e] = F[e] + Mh[e];
+        return;
+    }
+    for (int e = t; e < 256; e += 64) {
+        A[e] = H[e];
+        tmp[e] = F[e];
+    }
+    __syncthreads();
+    mat_mul_acc(tmp, A, Mh, kS, w.b, w.m, false);
+    for (int e = t; e < 256; e += 64) F[e] = tmp[e];
+}
+
+hipError_t small_window_correct(const SmallState *st, WinCoef wc, WindowStep ws, const int32_t *shift_list,
+                                int nact, hipStream_t stream) {
+    if (nact <= 0) return hipSuccess;
+    if (ws.t < 0 || ws.t >= kWinMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(window_correct_kernel, dim3(nact, ws.t + 2), dim3(64), 0, stream, st, wc, ws,
+                       shift_list);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Column-by-column deflated QR of W, used when the first CholQR pass cannot
 // resolve a drop decision (classical Gram-Schmidt twice, column order).
 // ---------------------------------------------------------------------------

@@ -30,6 +30,7 @@ struct SmallState {
     zd Z[kS][256];       // per shift: Z_{j,i} (b x m)
     zd N[kS][256];       // per shift: N_{j,i} (bp x b)
     zd M[kS][256];       // per shift: M_{j,i} (b x m)
+    zd dM[kS][256];      // per shift: change of M_{j,i} made by vector-wise stopping (b x m)
     double sigma[kS];
     double bnorm[kStack];       // norms of the stacked right-hand-side columns
     int32_t colmap[kS][kS];     // stacked column of right-hand side l of shift j
@@ -50,6 +51,8 @@ struct StepReport {
     uint32_t colmask[kS];// per shift: columns still being updated
     double est[kS][kS];  // [j][l] estimated relative residual
     double scalar[4];    // [0]: norm of the last CGS remainder, [1]: kept flag of that column
+    int32_t stage[kS][kS];  // [j][l] vector-wise stopping: the number r of this step's
+                            // Lanczos vectors after which (l, j) stopped (0: did not stop)
     int32_t skip_qr2;    // the second CholQR pass of this step was not run
 };
 
@@ -183,6 +186,24 @@ hipError_t small_wqr_end(SmallState *st, StepReport *rep, int nk, WqrKept kept, 
 // pass is skipped, else I; rotates b, bp.  Does nothing while st->redo is set.
 hipError_t small_finish(SmallState *st, StepReport *rep, const zd *G2, double tol, int freeze,
                         const int32_t *shift_list, int nact, hipStream_t stream);
+
+// Vector-wise stopping granularity (Sec. 3: the iterates advance one Lanczos
+// vector at a time, X^(k) = X^(k-1) + p^(k) u^(k) / d^(k)).  Run after
+// small_finish (called with freeze = 0) of block step i, width b: for every
+// system (l, j) still updated it evaluates the residual estimates of the
+// Galerkin iterates on the first K_{i-1} + r basis vectors, r = 1..b, and
+// stops the system at the first r whose estimate is <= tol (clearing its
+// colmask bit, with est and stage[j][l] = r in the report).  When r < b its
+// update of this step is the leading part P_{j,i}[:, 1..r] y_r of the block
+// update, and dM_j holds the change of its column of M_{j,i}; otherwise dM_j
+// is zero.  Does nothing while st->redo is set.
+hipError_t small_vector_stop(SmallState *st, StepReport *rep, double tol, const int32_t *shift_list,
+                             int nact, hipStream_t stream);
+// Add dM_j into the window coefficients of step i (ws as given to
+// small_window_update for that step): Wfp_j += Wg_j dM_j, Wf_{j,u} += Wh_{j,u} dM_j
+// (u < t) and Wf_{j,t} += dM_j.  Does nothing while st->redo is set.
+hipError_t small_window_correct(const SmallState *st, WinCoef wc, WindowStep ws, const int32_t *shift_list,
+                                int nact, hipStream_t stream);
 
 // Initial deflated QR of B, classical Gram-Schmidt twice per column.
 // small_bnorms: ||b_l|| for the stacked columns c0 .. c0+cnt-1 from the diagonal of

@@ -399,7 +399,10 @@ struct SolveStats {
     int32_t qr2_skipped = 0;  // steps whose second CholQR pass was not needed
     int32_t qr_redone = 0;    // steps whose QR was redone column by column
     int64_t mvms = 0;
+    int64_t mvms_vector = 0;      // Lanczos vectors through the stage at which the last system stopped
     std::vector<int32_t> widths;  // block width of each main-phase step
+    std::vector<int32_t> frozen_at;  // [j * m + l]: Lanczos vectors through the stage at which
+                                     // (l, j) stopped (0: never)
     double est[kS * kS] = {};
 };
 
@@ -886,6 +889,14 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     int iters = 0;
     std::vector<int32_t> act;
     std::vector<void *> colptr_host;
+    // vector-wise stopping: small_finish leaves the masks alone and
+    // small_vector_stop stops each system at its own Lanczos vector
+    const bool vstop = o.freeze && o.vector_stop;
+    const int finish_freeze = vstop ? 0 : o.freeze;
+    int64_t kvec = 0;  // Lanczos vectors before the current block
+    stt.frozen_at.assign((size_t)s * m, 0);
+    std::vector<uint32_t> mask_in(s, 0), mask0(s);
+    for (int j = 0; j < s; ++j) mask_in[j] = h->rep_host->colmask[j];
     bool xfresh = true;  // X has not been written yet in this solve
     // shifts whose X_j the last window already stored in the caller's layout
     std::vector<char> api_done(s, 0);
@@ -1173,6 +1184,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         }
         const bool f64 = !lo;
         Ts ts{h, f64, st, n};
+        for (int j = 0; j < s; ++j) mask0[j] = h->rep_host->colmask[j];
         iters = i;
         stt.mvms += b;
         stt.widths.push_back(b);
@@ -1217,8 +1229,8 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         PROF_LAUNCH(h, kProfSmall, 0.0, st,
                     small_shift_coeffs(S, rep, red_slot(h, 0), i == 1, (const int32_t *)h->list.p,
                                        (int)act.size(), st));
+        WindowStep wsp;
         {
-            WindowStep wsp;
             wsp.t = i - i0 - 1;
             wsp.bp0 = i0 >= 1 ? bw[i0] : 0;
             wsp.b = b;
@@ -1228,6 +1240,17 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             PROF_LAUNCH(h, kProfSmall, 0.0, st,
                         small_window_update(S, rep, WC, wsp, (const int32_t *)h->list.p, (int)act.size(), st));
         }
+        // vector-wise stopping after small_finish: the stage estimates inside
+        // this block, and the window coefficients of the systems that stop
+        // before its last vector
+        auto vector_stop = [&](void) -> int {
+            if (!vstop) return DSBCG_OK;
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        small_vector_stop(S, rep, tol, (const int32_t *)h->list.p, (int)act.size(), st));
+            PROF_LAUNCH(h, kProfSmall, 0.0, st,
+                        small_window_correct(S, WC, wsp, (const int32_t *)h->list.p, (int)act.size(), st));
+            return DSBCG_OK;
+        };
         // first CholQR pass with deflation on the Gram of W''
         PROF_LAUNCH(h, kProfSmall, 0.0, st,
                     small_chol_deflate(S, rep, red_slot(h, 0), red_slot(h, 2), lo ? tau32 : o.tau_W, st,
@@ -1253,8 +1276,9 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         // second CholQR pass, only when the kept columns are ill-conditioned
         // (skipped on the device otherwise): V_{i+1} = V' R2^{-1}, R2 from G2
         PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                    small_finish(S, rep, red_slot(h, 3), tol, o.freeze, (const int32_t *)h->list.p,
+                    small_finish(S, rep, red_slot(h, 3), tol, finish_freeze, (const int32_t *)h->list.p,
                                  (int)act.size(), st));
+        CHK(vector_stop());
         {
             TsArgs a = ts_args(n);
             a.K = 1;
@@ -1302,8 +1326,9 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                 CHK(ts.run_reduce(a, nk, 3));
             }
             PROF_LAUNCH(h, kProfSmall, 0.0, st,
-                        small_finish(S, rep, red_slot(h, 3), tol, o.freeze, (const int32_t *)h->list.p,
+                        small_finish(S, rep, red_slot(h, 3), tol, finish_freeze, (const int32_t *)h->list.p,
                                      (int)act.size(), st));
+            CHK(vector_stop());
             CHK(read_report(h, st));
             stt.qr_redone += 1;
         }
@@ -1321,6 +1346,11 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         }
         const int bnew = R.bnew;
         stt.deflations += b - bnew;
+        for (int j = 0; j < s; ++j)
+            for (int l = 0; l < m; ++l)
+                if (((mask0[j] >> l) & 1u) && !((R.colmask[j] >> l) & 1u))
+                    stt.frozen_at[(size_t)j * m + l] = (int32_t)(kvec + (vstop ? R.stage[j][l] : b));
+        kvec += b;
         active_list();
         if (bnew == 0) done = true;
         if (o.fixed_iters <= 0 && act.empty()) done = true;
@@ -1335,6 +1365,20 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
     if (xfresh && !rmode)  // no window was applied (no step, or nothing to update)
         HIPCHK(hipMemsetAsync(h->X.p, 0, (size_t)n * m * s * sizeof(zd), st));
     stt.block_iters += iters;
+    {
+        // the stage at which the last system stopped (all of them did), else
+        // every Lanczos vector of the run
+        bool all = true;
+        int64_t last = 0;
+        for (int j = 0; j < s; ++j)
+            for (int l = 0; l < m; ++l)
+                if ((mask_in[j] >> l) & 1u) {
+                    const int32_t f = stt.frozen_at[(size_t)j * m + l];
+                    all = all && f > 0;
+                    last = std::max<int64_t>(last, f);
+                }
+        stt.mvms_vector = all ? last : kvec;
+    }
     if (status == DSBCG_OK && !done && o.fixed_iters <= 0)
         status = fail(DSBCG_ERR_NOT_CONVERGED, "max_iters reached");
     // iterates (or their partial-fraction sum) to the caller's layout
@@ -1378,6 +1422,7 @@ void dsbcg_default_opts(dsbcg_opts *o) {
     o->switch_at = -1.0;  // resolved to min(1e-2, 1e5 * tol)
     o->window = 0;        // automatic window length
     o->keep_workspace = 1;
+    o->vector_stop = 0;   // stop systems at block boundaries
 }
 
 const char *dsbcg_last_error(void) { return g_err.c_str(); }
@@ -1546,6 +1591,10 @@ void fill_stats(dsbcg_stats *stats, const SolveStats &stt, const double *tr, int
     stats->qr_redone = stt.qr_redone;
     stats->main_relres_max = main_max;
     stats->mvms = stt.mvms;
+    stats->mvms_vector = stt.mvms_vector;
+    if (stats->frozen_at)
+        for (size_t k = 0; k < (size_t)s * m; ++k)
+            stats->frozen_at[k] = k < stt.frozen_at.size() ? stt.frozen_at[k] : 0;
     if (stats->widths)
         for (int32_t k = 0; k < stats->widths_len; ++k)
             stats->widths[k] = k < (int32_t)stt.widths.size() ? stt.widths[k] : 0;
@@ -1581,7 +1630,12 @@ int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, in
             stt.qr_redone += one.qr_redone;
             stt.deflations += one.deflations;
             stt.rank0 = std::max(stt.rank0, one.rank0);
-            for (int l = 0; l < m; ++l) stt.est[j * m + l] = one.est[l];
+            stt.mvms_vector = std::max(stt.mvms_vector, one.mvms_vector);
+            stt.frozen_at.resize((size_t)s * m, 0);
+            for (int l = 0; l < m; ++l) {
+                stt.est[j * m + l] = one.est[l];
+                stt.frozen_at[(size_t)j * m + l] = one.frozen_at[l];
+            }
         }
     }
     if (status != DSBCG_OK && status != DSBCG_ERR_NOT_CONVERGED) return status;

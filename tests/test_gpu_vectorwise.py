@@ -1,0 +1,127 @@
+"""Vector-wise stopping granularity on the GPU against the oracle.
+
+With opts.vector_stop = 1 every system (l, j) stops at the first Lanczos
+vector k whose Galerkin iterate X^(k) = V^(k) (T_sigma^(k))^{-1} (V^(k))^H B
+(eq. (3.2)) has an estimated relative residual <= tol (Sec. 3: the iterates
+advance one vector at a time).  The GPU forms the stage estimates from the
+block's small matrices and adds the leading part of the block update; the
+oracle (``oracle.dsbcg_vectorwise``) solves every stage's k x k system
+densely.  Checked: the stopping stage of every system (exact integers),
+mvms_vector, the block widths, and X element-wise and by norm at 1e-10 in
+FP64 (windows of 1, 3 and automatic length, a tolerance that stops systems
+in mid-block, in-iteration deflation, and the partial-fraction form); the
+FP32 form reaches the FP64 true residual tol; with one right-hand side the
+vector-wise run equals the block-wise one bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1205_0359_amd import inputs
+import paper_1205_0359_amd as dsb
+
+from gpu_util import announce, dev, host, rel_fro, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(L, U, kappa):
+    V = int(np.prod(L))
+
+    def f(Y):
+        return oracle.apply_A(L, U, kappa, np.ascontiguousarray(Y).reshape(V, 4, 3, -1)).reshape(12 * V, -1)
+    return f
+
+
+@pytest.fixture(scope="module")
+def haar4():
+    w = inputs.WORKLOADS["haar4^4_m4_s3"]
+    U, B = w.make()
+    return w, U, B
+
+
+def _oracle(w, U, B, tol, sig=None):
+    sig = w.shifts if sig is None else sig
+    return oracle.dsbcg_vectorwise(_op(w.L, U, w.kappa), B.reshape(w.n, -1), sig, tol)
+
+
+def _check(w, r, X, st, tol_x=1e-10):
+    m = r.X.shape[2]
+    assert st["widths"] == r.widths
+    assert np.array_equal(st["frozen_at"], r.frozen_stage), (st["frozen_at"], r.frozen_stage)
+    assert st["mvms_vector"] == r.mvms_vector
+    assert st["mvms"] == r.mvms
+    for j in range(X.shape[0]):
+        got = X[j].reshape(w.n, m)
+        assert rel_fro(got, r.X[j]) <= tol_x
+        assert rel_max(got, r.X[j]) <= tol_x
+
+
+@pytest.mark.parametrize("window", [0, 1, 3])
+@pytest.mark.parametrize("tol", [1e-10, 3e-7])
+def test_stopping_stages_and_iterates_match_oracle(haar4, window, tol):
+    w, U, B = haar4
+    announce("vector_stop", w.name, f"window={window}", f"tol={tol}")
+    r = _oracle(w, U, B, tol)
+    h = dsb.Handle(w.L)
+    X, st = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(B), w.shifts, tol, vector_stop=1, window=window,
+                            refine=0)
+    _check(w, r, host(X), st)
+    # some systems stop inside a block, which is what the option is for
+    assert (r.frozen_stage % w.m != 0).any()
+    assert (st["est_relres"] <= tol).all()
+
+
+def test_in_iteration_deflation(haar4):
+    w, U, _ = haar4
+    V = w.V
+    G = inputs.gaussian_rhs(inputs.rng_for(77, 1), V, 3)
+    b1 = G[..., 0:1]
+    Ab1 = oracle.apply_A(w.L, U, w.kappa, np.ascontiguousarray(b1))
+    B = np.ascontiguousarray(np.concatenate([b1, Ab1, G[..., 1:3]], axis=-1))
+    tol = 1e-10
+    announce("vector_stop deflation", w.name)
+    r = _oracle(w, U, B, tol)
+    assert min(r.widths) < 4
+    h = dsb.Handle(w.L)
+    X, st = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(B), w.shifts, tol, vector_stop=1, refine=0)
+    _check(w, r, host(X), st)
+
+
+def test_partial_fraction_form(haar4):
+    w, U, B = haar4
+    tol = 3e-7
+    coef, c0 = (0.6, -1.3, 2.1), 0.25
+    announce("vector_stop rational", w.name)
+    r = _oracle(w, U, B, tol)
+    Yo = oracle.partial_fraction(B.reshape(w.n, w.m), r.X, coef, c0)
+    h = dsb.Handle(w.L)
+    Y, st = dsb.dsbcg_solve_rational(h, dev(U), w.kappa, dev(B), w.shifts, coef, c0, tol, vector_stop=1)
+    got = host(Y).reshape(w.n, w.m)
+    assert np.array_equal(st["frozen_at"], r.frozen_stage)
+    assert rel_fro(got, Yo) <= 1e-10 and rel_max(got, Yo) <= 1e-10
+
+
+def test_fp32_form_reaches_true_residual(haar4):
+    w, U, B = haar4
+    tol = 1e-10
+    announce("vector_stop fp32", w.name)
+    h = dsb.Handle(w.L)
+    X, st = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(B), w.shifts, tol, vector_stop=1,
+                            precision=dsb.DSBCG_FP32_RELIABLE)
+    assert st["true_relres"].max() <= tol
+    ref = oracle.dsbcg(_op(w.L, U, w.kappa), B.reshape(w.n, w.m), w.shifts, 1e-13)
+    for j in range(len(w.shifts)):
+        assert rel_fro(host(X)[j].reshape(w.n, w.m), ref.X[j]) <= 1e-8
+
+
+def test_single_rhs_equals_block_stopping(haar4):
+    w, U, B = haar4
+    b = np.ascontiguousarray(B[..., 1:2])
+    announce("vector_stop m=1", w.name)
+    h = dsb.Handle(w.L)
+    Xv, sv = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(b), w.shifts, 1e-10, vector_stop=1, refine=0)
+    Xb, sb = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(b), w.shifts, 1e-10, vector_stop=0, refine=0)
+    assert np.array_equal(host(Xv), host(Xb))
+    assert np.array_equal(sv["frozen_at"], sb["frozen_at"])
+    assert sv["mvms_vector"] == sb["mvms_vector"] == sb["mvms"]
