@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+GRAD_CLASS = "link_grad"  # profiler class of the link-derivative kernel
 METRIC = ("shifted systems solved/sec to 1e-10 + D\u2020D stencil HBM GB/s, FP32-mixed vs FP64")
 DEFAULT_WORKLOAD = "haar32^3x64_m8r5_s10"
 
@@ -463,6 +464,8 @@ def grad_rate(dsb, prec, reps=3):
     p = dsb.DSBCG_FP32_RELIABLE if prec == "fp32" else dsb.DSBCG_FP64
     fw, bw = [], []
     for k in range(reps + 1):
+        if k == 1:
+            dsb.dsbcg_profile_enable(h, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         X = autograd.solve(dU, dB, sig, h, w.kappa, w.tol, precision=p, recompute=True)
@@ -476,8 +479,19 @@ def grad_rate(dsb, prec, reps=3):
             fw.append(t1 - t0)
             bw.append(t2 - t1)
         dU.grad = dB.grad = sig.grad = None
+    prof = dsb.dsbcg_profile_read(h)
+    dsb.dsbcg_profile_enable(h, False)
+    lg = prof.get(GRAD_CLASS, {"ms": 0.0, "launches": 0, "bytes": 0.0})
+    link = None
+    if lg["launches"]:
+        gbs = lg["bytes"] / (lg["ms"] * 1e-3) / 1e9
+        link = {"launches_per_backward": lg["launches"] / reps,
+                "avg_launch_us": round(1e3 * lg["ms"] / lg["launches"], 2),
+                "algorithmic_bytes_per_launch": lg["bytes"] / lg["launches"],
+                "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     return {"workload": w.name, "form": prec, "ms_forward": round(1e3 * float(np.median(fw)), 3),
             "ms_backward": round(1e3 * float(np.median(bw)), 3),
+            "link_grad": link,
             "note": "backward = adjoint block solve + X_j recompute + dL/dU, dL/dB, dL/dsigma kernels"}
 
 
@@ -567,6 +581,7 @@ def switch_sweep(dsb, h, dB, w, values):
     without re-solves (largest FP64 true relative residual after the main
     phase, the steps run in FP32, time) and with them (re-solve block steps,
     time, final residual)."""
+    import numpy as np
     import torch
     for v in values:
         out = {"switch_at": v}
@@ -580,6 +595,13 @@ def switch_sweep(dsb, h, dB, w, values):
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t0)
             tag = "refine" if refine else "main"
+            if not refine:
+                # per shift: the largest FP64 true relative residual over the
+                # estimate it stopped on, and whether the shift misses tol
+                tr, es = st["true_relres"], st["est_relres"]
+                ratio = tr / np.where(es > 0, es, 1.0)
+                out["drift_per_shift"] = [round(float(ratio[:, j].max()), 3) for j in range(tr.shape[1])]
+                out["shifts_above_tol"] = [j for j in range(tr.shape[1]) if tr[:, j].max() > w.tol]
             out[tag] = {"ms": round(ms, 1), "block_iters": st["block_iters"], "switch_iter": st["switch_iter"],
                         "fp32_steps": (st["block_iters"] - st["switch_iter"] + 1) if st["switch_iter"] else 0,
                         "main_relres_max": st["main_relres_max"], "refine_iters": st["refine_iters"],

@@ -11,55 +11,40 @@
 //   G_mu(x) = -kappa sum_{spin, k} [ ((1 - g_mu) Phi(x)) Psi(x+mu)^H
 //                                   + Psi(x) ((1 + g_mu) Phi(x+mu))^H ],
 //
-// a fused outer-product stencil: one thread per (site, mu) accumulates the
-// 3 x 3 colour matrix over spins and columns in registers.
+// a fused outer-product stencil.  (1 - s g_mu) is hermitian and its image
+// is fixed by the half spinor h(p) = (h_0, h_1) of spins 0 and 1, with the
+// lower spins unit multiples of them, so the spin sums reduce to half spinors:
+//   sum_spin ((1 - s g_mu) p) y^H = sum_{k=0,1} h_k(p) h_k(y)^H
+// (same mu and s on both sides).  One thread per (site, mu), mu the fastest
+// index: the four threads of a site are neighbouring lanes, read Phi(x) and
+// Psi(x) together and write the site's four 3 x 3 blocks as one contiguous
+// run.
 
 #include "grad.hpp"
 #include "lattice.hpp"
 
 namespace dsbcg {
 
-template <int MU>
-__device__ inline void grad_dir(const Geom &g, int x, const int c[4], double kappa,
-                                const zd *__restrict__ Phi, const zd *__restrict__ Psi, int cols,
-                                zd G[3][3]) {
-    const int64_t V = g.V, n = 12 * V;
-    const int xf = hop(g, x, c, MU, true);
-    for (int k = 0; k < cols; ++k) {
-        const zd *ph = Phi + (int64_t)k * n;
-        const zd *ps = Psi + (int64_t)k * n;
-        zd p[4][3], a[4][3];
-        // ((1 - g_mu) Phi(x)) Psi(x+mu)^H
+// Half spinor of the projector (1 - s g_mu) with mu a runtime value (no
+// divergence between the lanes of different mu): h_k = p_k + f_k p_partner,
+// partner 3 - k for x, y and 2 + k for z, t, f_k = s * (x: -i, -i;
+// y: +1, -1; z: -i, +i; t: -1, -1).  Loads the 12 components of the spinor
+// at site x of the column-major field f.
+__device__ inline void half_rt(int mu, double sgn, const zd *__restrict__ f, int64_t V, int x,
+                               zd h[2][3]) {
+    const bool xy = mu < 2;
+    const double fr[2] = {sgn * (mu == 1 ? 1.0 : (mu == 3 ? -1.0 : 0.0)),
+                          sgn * (mu == 1 ? -1.0 : (mu == 3 ? -1.0 : 0.0))};
+    const double fi[2] = {sgn * ((mu == 0 || mu == 2) ? -1.0 : 0.0),
+                          sgn * (mu == 0 ? -1.0 : (mu == 2 ? 1.0 : 0.0))};
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+    for (int k = 0; k < 2; ++k) {
+        const int partner = xy ? 3 - k : 2 + k;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) p[s][q] = ph[(int64_t)(s * 3 + q) * V + x];
-        project_full<double, MU, 1>(p, a);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            zd y[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) y[q] = ps[(int64_t)(s * 3 + q) * V + xf];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) cmac_conj(G[i][j], y[j], a[s][i]);
-        }
-        // Psi(x) ((1 + g_mu) Phi(x+mu))^H
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) p[s][q] = ph[(int64_t)(s * 3 + q) * V + xf];
-        project_full<double, MU, -1>(p, a);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            zd y[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) y[q] = ps[(int64_t)(s * 3 + q) * V + x];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) cmac_conj(G[i][j], a[s][j], y[i]);
+        for (int q = 0; q < 3; ++q) {
+            const zd a = f[(int64_t)(k * 3 + q) * V + x];
+            const zd b = f[(int64_t)(partner * 3 + q) * V + x];
+            h[k][q] = mk<double>(a.x + fr[k] * b.x - fi[k] * b.y, a.y + fr[k] * b.y + fi[k] * b.x);
         }
     }
 }
@@ -68,29 +53,62 @@ __global__ __launch_bounds__(256) void link_grad_kernel(Geom g, double kappa, co
                                                         const zd *__restrict__ Psi, int cols,
                                                         zd *__restrict__ dU, int accumulate,
                                                         double scale) {
+    // the workgroup's 64 sites x 4 directions x 9 entries, written out as one
+    // contiguous run after the barrier
+    __shared__ zd out[256 * 9];
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= 4 * (int64_t)g.V) return;
-    const int mu = (int)(t / g.V);
-    const int x = (int)(t - (int64_t)mu * g.V);
-    int c[4];
-    site_coords(g, x, c);
+    const int64_t total = 4 * (int64_t)g.V;
     zd G[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) G[i][j] = mk<double>(0, 0);
-    if (mu == 0) grad_dir<0>(g, x, c, kappa, Phi, Psi, cols, G);
-    else if (mu == 1) grad_dir<1>(g, x, c, kappa, Phi, Psi, cols, G);
-    else if (mu == 2) grad_dir<2>(g, x, c, kappa, Phi, Psi, cols, G);
-    else grad_dir<3>(g, x, c, kappa, Phi, Psi, cols, G);
-    zd *o = dU + ((int64_t)x * 4 + mu) * 9;
+    if (t < total) {
+        const int mu = (int)(t & 3);
+        const int x = (int)(t >> 2);
+        const int64_t V = g.V, n = 12 * V;
+        int c[4];
+        site_coords(g, x, c);
+        const int s1 = g.L[0], s2 = s1 * g.L[1], s3 = s2 * g.L[2];
+        const int stride = mu == 0 ? 1 : (mu == 1 ? s1 : (mu == 2 ? s2 : s3));
+        const int cm = mu == 0 ? c[0] : (mu == 1 ? c[1] : (mu == 2 ? c[2] : c[3]));
+        const int lm = g.L[mu];
+        const int xf = x + stride - (cm == lm - 1 ? lm * stride : 0);
+        for (int k = 0; k < cols; ++k) {
+            const zd *ph = Phi + (int64_t)k * n;
+            const zd *ps = Psi + (int64_t)k * n;
+            zd a[2][3], b[2][3];
+            // ((1 - g_mu) Phi(x)) Psi(x+mu)^H
+            half_rt(mu, 1.0, ph, V, x, a);
+            half_rt(mu, 1.0, ps, V, xf, b);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) cmac_conj(G[i][j], b[h][j], a[h][i]);
+            // Psi(x) ((1 + g_mu) Phi(x+mu))^H
+            half_rt(mu, -1.0, ps, V, x, a);
+            half_rt(mu, -1.0, ph, V, xf, b);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) cmac_conj(G[i][j], b[h][j], a[h][i]);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const zd v = mk<double>(-scale * kappa * G[i][j].x, -scale * kappa * G[i][j].y);
-            o[i * 3 + j] = accumulate ? o[i * 3 + j] + v : v;
-        }
+        for (int j = 0; j < 3; ++j)
+            out[threadIdx.x * 9 + i * 3 + j] = mk<double>(-scale * kappa * G[i][j].x, -scale * kappa * G[i][j].y);
+    __syncthreads();
+    // dU[x][mu][3][3] with t = 4 x + mu: the block's entries are contiguous
+    zd *o = dU + (int64_t)blockIdx.x * blockDim.x * 9;
+    const int64_t left = 9 * (total - (int64_t)blockIdx.x * blockDim.x);
+    const int cnt = (int)(left < 9 * (int64_t)blockDim.x ? left : 9 * (int64_t)blockDim.x);
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) o[e] = accumulate ? o[e] + out[e] : out[e];
 }
 
 hipError_t link_grad_apply(const Geom &g, double kappa, const void *Phi, const void *Psi, int cols,

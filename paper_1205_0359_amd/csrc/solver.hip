@@ -1817,9 +1817,11 @@ int dsbcg_grad(dsbcg_handle h, const void *U, double kappa, const double *sigma,
             // dL/dU = -sum_j [ d Re <D X_j, D Lambda_j> + d Re <D Lambda_j, D X_j> ]
             CHK(stencil(h, true, h->Ul64.p, kappa, h->R0.p, h->R2.p, m, false, st));   // D X_j
             CHK(stencil(h, true, h->Ul64.p, kappa, h->R1.p, h->R3.p, m, false, st));   // D Lambda_j
-            PROF_LAUNCH(h, kProfGrad, (double)h->g.V * (4.0 * 12 * m + 36.0 * (j ? 2 : 1)) * 16, st,
+            // algorithmic bytes: each field read once, dU written (and read
+            // when accumulating)
+            PROF_LAUNCH(h, kProfGrad, (double)h->g.V * (2.0 * 12 * m + 36.0 * (j ? 2 : 1)) * 16, st,
                         link_grad_apply(h->g, kappa, h->R2.p, h->R1.p, m, dU, j > 0, -1.0, st));
-            PROF_LAUNCH(h, kProfGrad, (double)h->g.V * (4.0 * 12 * m + 72.0) * 16, st,
+            PROF_LAUNCH(h, kProfGrad, (double)h->g.V * (2.0 * 12 * m + 72.0) * 16, st,
                         link_grad_apply(h->g, kappa, h->R3.p, h->R0.p, m, dU, true, -1.0, st));
         }
     }
