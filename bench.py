@@ -70,6 +70,10 @@ def parse():
     p.add_argument("--switch-sweep", metavar="VALUES",
                    help="comma-separated switch_at values: time the FP32 form at each, without and "
                         "with the FP64 re-solve, print one JSON line per value and exit")
+    p.add_argument("--paper-experiments", action="store_true",
+                   help="the paper's comparison on MI355X: Table 1 (CG, block CG, shifted CG, "
+                        "DSBlockCG), the sweep over the number of shifts (Fig. 2) and over the "
+                        "number of right-hand sides (Fig. 3); one JSON line each")
     p.add_argument("--summarize-counters", metavar="PMC_DIR",
                    help="print per-kernel averages of every counter of a rocprofv3 --pmc CSV run "
                         "(with the dispatch durations of that run), then exit")
@@ -278,6 +282,140 @@ def stored_traffic(kernel: str, digest: str):
     if not ent or ent.get("source_digest") != digest:
         return None
     return ent.get("bytes_per_launch")
+
+
+PAPER_TABLE1 = {"mvms": {"CG": 22337, "BlockCG": 13488, "shiftedCG": 4883, "DSBlockCG": 2766},
+                "relative_time": {"CG": 5.03, "BlockCG": 3.96, "shiftedCG": 1.31, "DSBlockCG": 1.0}}
+
+
+def lanczos_lmin(dsb, h, kappa, V, steps, seed):
+    """Smallest eigenvalue of A by plain Lanczos from a seeded Gaussian start
+    (FP64, A applied through dsbcg_apply_A): the smallest Ritz value and its
+    residual bound beta_k |s_k|."""
+    import numpy as np
+    import torch
+    from paper_1205_0359_amd import inputs
+    q = torch.from_numpy(inputs.gaussian_rhs(np.random.default_rng(seed), V, 1)).to("cuda")
+    q = q / torch.linalg.vector_norm(q)
+    q_prev = torch.zeros_like(q)
+    alpha, beta = [], []
+    b_prev = 0.0
+    for _ in range(steps):
+        w = dsb.dsbcg_apply_A(h, None, kappa, q)
+        a = float(torch.vdot(q.flatten(), w.flatten()).real)
+        w = w - a * q - b_prev * q_prev
+        b = float(torch.linalg.vector_norm(w))
+        alpha.append(a)
+        beta.append(b)
+        q_prev, q, b_prev = q, w / b, b
+    k = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:-1], 1) + np.diag(beta[:-1], -1)
+    th, S = np.linalg.eigh(T)
+    return float(th[0]), float(abs(beta[-1] * S[-1, 0])), float(th[-1])
+
+
+def paper_experiments(dsb, args):
+    """The paper's comparison (Sec. 4) on synthetic smooth links, FP64 form,
+    tol 1e-8: CG (m = s = 1 per system), block CG (s = 1 per shift), shifted
+    CG (m = 1 per right-hand side) and DSBlockCG as special cases of
+    dsbcg_solve.  Shifts put the smallest eigenvalue of the shifted systems at
+    logspace(-6, -1, s), from a Lanczos estimate of lambda_min(A).  Each run
+    is timed three times (median), after an untimed solve of each shape."""
+    import numpy as np
+    import torch
+    from paper_1205_0359_amd import inputs
+    tol, kappa = 1e-8, 0.125
+    shape_seen = set()
+
+    def setup(L, wid, mmax):
+        V = int(np.prod(L))
+        U = inputs.make_links(L, "smooth", inputs.rng_for(wid, 0))
+        B = torch.from_numpy(inputs.gaussian_rhs(inputs.rng_for(wid, 1), V, mmax)).to("cuda")
+        h = dsb.Handle(L)
+        dsb.dsbcg_stage_links(h, torch.from_numpy(U).to("cuda"))
+        lmin, bound, lmax = lanczos_lmin(dsb, h, kappa, V, 1500, 1000 * wid + 3)
+        if bound > 1e-9:
+            raise RuntimeError(f"lambda_min estimate not converged (bound {bound:.2e})")
+        info = {"lattice": list(L), "kappa": kappa, "links": "smooth", "lambda_min": lmin,
+                "lambda_min_bound": bound, "lambda_max": lmax}
+        log(f"[bench] paper experiments {L}: lambda_min {lmin:.6e} (bound {bound:.1e}), lambda_max {lmax:.4f}")
+        return h, B, lmin, info
+
+    def run(h, B, cols, sig):
+        Bc = B[..., cols].contiguous()
+        key = (id(h), len(cols), len(sig))
+        X = None
+        if key not in shape_seen:
+            # the first solve of a shape allocates the workspace: not timed
+            X, _ = dsb.dsbcg_solve(h, None, kappa, Bc, sig, tol, keep_workspace=1)
+            shape_seen.add(key)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, st = dsb.dsbcg_solve(h, None, kappa, Bc, sig, tol, X=X, keep_workspace=1)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        if st["true_relres"].max() > tol:
+            raise RuntimeError(f"paper experiment: residual {st['true_relres'].max():.2e} above {tol}")
+        del X
+        return dt, st["mvms"]
+
+    def methods(h, B, m, sig, which):
+        cases = {
+            "DSBlockCG": [(list(range(m)), sig)],
+            "shiftedCG": [([l], sig) for l in range(m)],
+            "BlockCG": [(list(range(m)), [s]) for s in sig],
+            "CG": [([l], [s]) for l in range(m) for s in sig],
+        }
+        out = {}
+        for name in which:
+            t = mv = 0
+            for cols, sh in cases[name]:
+                dt, k = run(h, B, cols, sh)
+                t += dt
+                mv += k
+            out[name] = {"s": t, "mvms": mv}
+        return out
+
+    # Table 1: 16^4, 4 right-hand sides, 7 shifts
+    h16, B16, lmin16, info16 = setup((16, 16, 16, 16), 1205, 4)
+    sig7 = list(np.logspace(-6, -1, 7) - lmin16)
+    res = methods(h16, B16, 4, sig7, ("DSBlockCG", "shiftedCG", "BlockCG", "CG"))
+    base = res["DSBlockCG"]["s"]
+    for v in res.values():
+        v["relative_time"] = round(v["s"] / base, 3)
+    print(json.dumps({"experiment": "table1", **info16, "m": 4, "s": 7, "tol": tol,
+                      "shifted_lambda_min": list(np.logspace(-6, -1, 7)), "methods": res,
+                      "paper": PAPER_TABLE1}), flush=True)
+
+    # Fig. 2: 16^4, 4 right-hand sides, 1..12 shifts
+    rows = []
+    for s in range(1, 13):
+        t = np.logspace(-6, -1, s) if s > 1 else np.array([1e-6])
+        r = methods(h16, B16, 4, list(t - lmin16), ("DSBlockCG", "shiftedCG"))
+        rows.append({"s": s, "relative_time": round(r["DSBlockCG"]["s"] / r["shiftedCG"]["s"], 3),
+                     "relative_mvms": round(r["DSBlockCG"]["mvms"] / r["shiftedCG"]["mvms"], 3),
+                     "ms_dsblockcg": round(1e3 * r["DSBlockCG"]["s"], 1),
+                     "ms_shiftedcg": round(1e3 * r["shiftedCG"]["s"], 1)})
+        log(f"[bench] fig 2 s={s}: {rows[-1]}")
+    print(json.dumps({"experiment": "fig2_shifts", **info16, "m": 4, "tol": tol, "rows": rows}), flush=True)
+    del h16, B16
+    torch.cuda.empty_cache()
+
+    # Fig. 3: 12^4, 10 shifts, 1..12 right-hand sides
+    h12, B12, lmin12, info12 = setup((12, 12, 12, 12), 1206, 12)
+    sig10 = list(np.logspace(-6, -1, 10) - lmin12)
+    rows = []
+    for m in range(1, 13):
+        r = methods(h12, B12, m, sig10, ("DSBlockCG", "shiftedCG"))
+        rows.append({"m": m, "relative_time": round(r["DSBlockCG"]["s"] / r["shiftedCG"]["s"], 3),
+                     "relative_mvms": round(r["DSBlockCG"]["mvms"] / r["shiftedCG"]["mvms"], 3),
+                     "ms_dsblockcg": round(1e3 * r["DSBlockCG"]["s"], 1),
+                     "ms_shiftedcg": round(1e3 * r["shiftedCG"]["s"], 1)})
+        log(f"[bench] fig 3 m={m}: {rows[-1]}")
+    print(json.dumps({"experiment": "fig3_rhs", **info12, "s": 10, "tol": tol, "rows": rows}), flush=True)
 
 
 def vector_stop_rate(dsb, h, dB, w, prec, steps):
@@ -626,6 +764,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
               "multi-GPU form in this build", file=sys.stderr)
         sys.exit(2)
+    if args.paper_experiments:
+        import paper_1205_0359_amd as dsb
+        paper_experiments(dsb, args)
+        return
     if args.cpu_sample_only:
         from paper_1205_0359_amd import inputs
         print(json.dumps(cpu_sample(inputs.WORKLOADS[args.workload], args.cpu_steps,
