@@ -59,8 +59,10 @@ typedef enum {
 
 typedef enum {
     DSBCG_FP64 = 0,          /* every vector operation in FP64 */
-    DSBCG_FP32_RELIABLE = 1  /* FP32 stencil and block updates, FP64 small algebra,
-                                FP64 solution accumulation and true-residual updates */
+    DSBCG_FP32_RELIABLE = 1  /* FP64 vectors until the estimates reach opts.switch_at, then
+                                FP32 stencil and block updates; FP64 small algebra, FP64
+                                solution accumulation, FP64 true residuals of every system at
+                                the end and re-solves of the shifts that miss tol */
 } dsbcg_precision;
 
 /* Largest supported number of right-hand sides and of shifts. */
