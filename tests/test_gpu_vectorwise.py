@@ -125,3 +125,18 @@ def test_single_rhs_equals_block_stopping(haar4):
     assert np.array_equal(host(Xv), host(Xb))
     assert np.array_equal(sv["frozen_at"], sb["frozen_at"])
     assert sv["mvms_vector"] == sb["mvms_vector"] == sb["mvms"]
+
+
+@pytest.mark.parametrize("m,s,tol", [(12, 3, 1e-10), (16, 16, 1e-6)])
+def test_wide_blocks_and_maximum_sizes(haar4, m, s, tol):
+    """Blocks of 12 and 16 vectors (stages r = 1..16 inside a step) and 16 x 16
+    systems, one per thread of the stopping kernel."""
+    w, U, _ = haar4
+    B = inputs.gaussian_rhs(inputs.rng_for(78, m), w.V, m)
+    sig = tuple(np.logspace(-3, 0, s))
+    announce("vector_stop wide", w.name, f"m={m}", f"s={s}", f"tol={tol}")
+    r = _oracle(w, U, B, tol, sig=sig)
+    h = dsb.Handle(w.L)
+    X, st = dsb.dsbcg_solve(h, dev(U), w.kappa, dev(B), sig, tol, vector_stop=1, refine=0)
+    _check(w, r, host(X), st)
+    assert (r.frozen_stage % m != 0).any()
