@@ -706,24 +706,27 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
             }
         }
         if (fail) atomicOr(&rep->flags, kFlagQR2);
-        // R2inv = R2^{-1}: rows of I solved against upper-triangular R2
-        for (int r = 0; r < 16; ++r) {
-            zd x[16];
-            for (int c = 0; c < nk; ++c) {
-                zd v = (r == c) ? mk<double>(1, 0) : mk<double>(0, 0);
-                for (int q = 0; q < c; ++q) v = v - x[q] * R2[q * 16 + c];
-                x[c] = zdivr(v, R2[c * 16 + c].x);
-            }
-            for (int c = 0; c < 16; ++c) st->R2inv[r * 16 + c] = (r < nk && c < nk) ? x[c] : mk<double>(0, 0);
+    }
+    __syncthreads();
+    // R2inv = R2^{-1}: row r of I solved against upper-triangular R2, one
+    // row per thread
+    if (t < 16) {
+        const int r = t;
+        zd x[16];
+        for (int c = 0; c < nk; ++c) {
+            zd v = (r == c) ? mk<double>(1, 0) : mk<double>(0, 0);
+            for (int q = 0; q < c; ++q) v = v - x[q] * R2[q * 16 + c];
+            x[c] = zdivr(v, R2[c * 16 + c].x);
         }
-        // beta_{i+1} = R2 R1 (nk x b)
-        for (int r = 0; r < 16; ++r)
-            for (int c = 0; c < 16; ++c) {
-                zd v = mk<double>(0, 0);
-                if (r < nk && c < b)
-                    for (int q = r; q < nk; ++q) v = v + R2[r * 16 + q] * R1s[q * 16 + c];
-                BN[r * 16 + c] = v;
-            }
+        for (int c = 0; c < 16; ++c) st->R2inv[r * 16 + c] = (r < nk && c < nk) ? x[c] : mk<double>(0, 0);
+    }
+    // beta_{i+1} = R2 R1 (nk x b), one entry per thread
+    {
+        const int r = t >> 4, c = t & 15;
+        zd v = mk<double>(0, 0);
+        if (r < nk && c < b)
+            for (int q = r; q < nk; ++q) v = v + R2[r * 16 + q] * R1s[q * 16 + c];
+        BN[r * 16 + c] = v;
     }
     __syncthreads();
     // per shift: C_j = -beta_{i+1} M_j = Z_{j,i+1}; estimates; freezing
