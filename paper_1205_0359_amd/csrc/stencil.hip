@@ -153,15 +153,20 @@ int stencil_chunk(bool fp64, int nb) { return (fp64 && nb > 7) ? 5 : nb; }
 // Block order.  Workgroups are dealt to the 8 XCDs of the chip round robin
 // (workgroup q runs on XCD q mod 8), and each XCD has its own L2.  In the
 // plain order workgroup q owns sites 64 q .. 64 q + 63, so the y neighbours
-// one workgroup over sit in another XCD's cache.  The lockstep order
-// (LOCK) gives XCD k the tiles k tpx .. (k+1) tpx - 1 of 64 sites of every
-// t-slice and walks t: the workgroups an XCD runs at one time cover a block
-// of neighbouring tiles of one slice, and their x, y, z neighbours mostly
-// sit in the same L2.  The output goes out with non-temporal stores, which
-// keep it from displacing the inputs in L2.  Measured on 32^3 x 64, FP64,
-// 5 columns: 2.02 ms against 2.16 ms per pass, L2-to-fabric reads 11.7 GB
-// against 12.6 GB (the algorithmic reads are 3.2 GB); the same order for the
-// FP32 LDS-staged form was slower and is not used there.
+// one workgroup over sit in another XCD's cache.  The lockstep order used by
+// every launch gives XCD k the tiles k tpx .. (k+1) tpx - 1 of 64 sites of
+// every t-slice and walks t: the workgroups an XCD runs at one time cover a
+// block of neighbouring tiles of one slice, and their x, y, z neighbours
+// mostly sit in the same L2.  The output goes out with non-temporal stores,
+// which keep it from displacing the inputs in L2.  Measured on 32^3 x 64
+// against the plain order, bitwise equal results: FP64 with global links,
+// 5 columns, 2.02 against 2.16 ms per pass (L2-to-fabric reads 11.7 GB
+// against 12.6 GB; the algorithmic reads are 3.2 GB); LDS-staged forms 2 to
+// 13 % faster (FP64 3 and 4 columns 1.30 / 1.62 against 1.49 / 1.84 ms, FP32
+// 5 and 12 columns 1.13 / 2.74 against 1.16 / 2.96 ms).  Walking an XCD's
+// share of a slice in smaller chunks over all t (so that the t neighbours
+// were read fewer workgroups earlier) was slower: 2.18, 2.36 and 2.46 ms for
+// chunks of 32, 16 and 8 tiles against 2.02 ms for the whole share of 64.
 struct BlockOrder {
     int32_t vs;     // sites per t-slice, Lx Ly Lz
     int32_t ntile;  // tiles of 64 sites per slice
@@ -177,7 +182,7 @@ inline BlockOrder lockstep_order(const Geom &g) {
 }
 inline int lockstep_blocks(const Geom &g) { return kXcds * lockstep_order(g).tpx * g.L[3]; }
 
-template <typename R, bool DAG, bool RESID, int MAXT, bool GL, bool LOCK>
+template <typename R, bool DAG, bool RESID, int MAXT, bool GL>
 __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
                                                          R kappa, const cx<R> *__restrict__ in,
                                                          cx<R> *__restrict__ out, int nb, ResidOut ro,
@@ -187,18 +192,12 @@ __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;  // = column
     const int nwaves = blockDim.x >> 6;
-    int x;
-    bool inside;
-    if (LOCK) {
-        const int xcd = blockIdx.x % kXcds, q = blockIdx.x / kXcds;
-        const int t = q / bo.tpx, tile = xcd * bo.tpx + (q - t * bo.tpx);
-        const int xs = tile * kSitesPerWG + lane;
-        inside = tile < bo.ntile && t < g.L[3] && xs < bo.vs;
-        x = t * bo.vs + xs;
-    } else {
-        x = blockIdx.x * kSitesPerWG + lane;
-        inside = x < g.V;
-    }
+    // lockstep block order
+    const int xcd = blockIdx.x % kXcds, q = blockIdx.x / kXcds;
+    const int t = q / bo.tpx, tile = xcd * bo.tpx + (q - t * bo.tpx);
+    const int xs = tile * kSitesPerWG + lane;
+    const bool inside = tile < bo.ntile && t < g.L[3] && xs < bo.vs;
+    const int x = t * bo.vs + xs;
     const bool valid = inside && wave < nb;
     int c[4] = {0, 0, 0, 0};
     if (valid) site_coords(g, x, c);
@@ -256,12 +255,8 @@ __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__
             const int64_t idx = (int64_t)(s * 3 + a) * g.V + x;
             const cx<R> v = col[idx];
             const cx<R> r = mk<R>(v.x - kappa * acc[s][a].x, v.y - kappa * acc[s][a].y);
-            if (LOCK) {
-                __builtin_nontemporal_store(r.x, &oc[idx].x);
-                __builtin_nontemporal_store(r.y, &oc[idx].y);
-            } else {
-                oc[idx] = r;
-            }
+            __builtin_nontemporal_store(r.x, &oc[idx].x);
+            __builtin_nontemporal_store(r.y, &oc[idx].y);
         }
 }
 
@@ -279,31 +274,22 @@ __global__ void neighbor_kernel(Geom g, int32_t *out) {
 hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, const void *in,
                         void *out, int nb, bool dagger, hipStream_t st) {
     if (nb < 1 || nb > 16) return hipErrorInvalidValue;
-    const dim3 grid((g.V + kSitesPerWG - 1) / kSitesPerWG);
+    const dim3 grid((unsigned)lockstep_blocks(g));
     const dim3 block(64 * nb);
     const ResidOut none{nullptr, nullptr, 0.0, nullptr};
-    const BlockOrder plain{0, 0, 0};
-#define DSBCG_W(R, D)                                                                              \
-    do {                                                                                           \
-        if (small_bound(nb))                                                                       \
-            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 512, false, false>), grid, block, 0, st, g, \
-                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none,   \
-                               plain);                                                             \
-        else                                                                                       \
-            hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, 1024, false, false>), grid, block, 0, st, g, \
-                               (const cx<R> *)Ul, (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none,   \
-                               plain);                                                             \
+    const BlockOrder lo = lockstep_order(g);
+#define DSBCG_L(R, D, MT, GLB)                                                                      \
+    hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, MT, GLB>), grid, block, 0, st, g, (const cx<R> *)Ul, \
+                       (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none, lo)
+#define DSBCG_W(R, D)                                                                               \
+    do {                                                                                            \
+        if (small_bound(nb)) DSBCG_L(R, D, 512, false);                                             \
+        else DSBCG_L(R, D, 1024, false);                                                            \
     } while (0)
     if (fp64 && global_links(fp64, nb)) {
-        // 5 to 7 columns (at most 448 threads), lockstep block order
-        const dim3 lgrid((unsigned)lockstep_blocks(g));
-        const BlockOrder lo = lockstep_order(g);
-        if (dagger)
-            hipLaunchKernelGGL((wilson_cm_kernel<double, true, false, 512, true, true>), lgrid, block, 0, st, g,
-                               (const zd *)Ul, kappa, (const zd *)in, (zd *)out, nb, none, lo);
-        else
-            hipLaunchKernelGGL((wilson_cm_kernel<double, false, false, 512, true, true>), lgrid, block, 0, st, g,
-                               (const zd *)Ul, kappa, (const zd *)in, (zd *)out, nb, none, lo);
+        // 5 to 7 columns (at most 448 threads)
+        if (dagger) DSBCG_L(double, true, 512, true);
+        else DSBCG_L(double, false, 512, true);
     } else if (fp64) {
         if (dagger) DSBCG_W(double, true);
         else DSBCG_W(double, false);
@@ -312,6 +298,7 @@ hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, 
         else DSBCG_W(float, false);
     }
 #undef DSBCG_W
+#undef DSBCG_L
     return hipGetLastError();
 }
 
@@ -320,20 +307,19 @@ int wilson_resid_workgroups(const Geom &g) { return lockstep_blocks(g); }
 hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const void *in, const void *b,
                               const void *x, double sigma, int nb, double *partials, hipStream_t st) {
     if (nb < 1 || nb > 16 || !partials) return hipErrorInvalidValue;
-    // lockstep block order for every width: the partial of a workgroup with
-    // no sites is zero
+    // the partial of a workgroup with no sites is zero
     const dim3 grid((unsigned)wilson_resid_workgroups(g));
     const dim3 block(64 * nb);
     const ResidOut ro{(const zd *)b, (const zd *)x, sigma, partials};
     const BlockOrder lo = lockstep_order(g);
     if (global_links(true, nb))
-        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, true, true>), grid, block, 0, st, g,
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, true>), grid, block, 0, st, g,
                            (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
     else if (small_bound(nb))
-        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, false, true>), grid, block, 0, st, g,
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, false>), grid, block, 0, st, g,
                            (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
     else
-        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 1024, false, true>), grid, block, 0, st, g,
+        hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 1024, false>), grid, block, 0, st, g,
                            (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
     return hipGetLastError();
 }
