@@ -201,10 +201,11 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation).  Same arguments, results (bit for bit) and errors as
  * dsbcg_apply_A; U may be NULL after dsbcg_stage_links.  The column-major
- * staging of X and Y, the intermediate D X and, when U is given, the
- * converted links live in one fixed workspace per device of 128 MiB (held
- * by every GPU the library runs on until the process ends), so a call needs
- *     V * 36 * e  (only when U != NULL)  +  3 * 12 * V * m * e  bytes,
+ * staging of X, the intermediate D X and, when U is given, the converted
+ * links live in one fixed workspace per device of 128 MiB (held by every GPU
+ * the library runs on until the process ends; the second pass writes Y in
+ * the caller's layout directly), so a call needs
+ *     V * 36 * e  (only when U != NULL)  +  2 * 12 * V * m * e  bytes,
  * e = 16 (FP64) or 8 (FP32), each part rounded up to 256 bytes; a larger call
  * returns DSBCG_ERR_ARG and leaves Y untouched.  The handle must belong to
  * the current device.  Every call on one GPU uses the same workspace: calls

@@ -1,8 +1,9 @@
 // dsbcg_apply_A_noalloc: Y = A X = D^H (D X) with no device allocation, for
 // callers that cannot allocate (code under HIP graph capture, serving loops,
-// harnesses that forbid it).  The column-major staging blocks, the
+// harnesses that forbid it).  The column-major staging of X, the
 // intermediate D X and (when the caller passes U) the structure-of-arrays
-// links live in one workspace per device, a file-scope device array that
+// links live in one workspace per device (the second pass writes Y in the
+// caller's layout directly), a file-scope device array that
 // each GPU the library runs on holds until the process ends.  The kernels
 // are those of dsbcg_apply_A, launched in the same order, so the result is
 // the same bit for bit.
@@ -79,7 +80,7 @@ extern "C" int dsbcg_apply_A_noalloc(dsbcg_handle h, const void *U, double kappa
     const size_t esz = f64 ? 16 : 8;
     const size_t links_b = U ? round256((size_t)V * 36 * esz) : 0;
     const size_t block_b = round256((size_t)n * m * esz);
-    const size_t need = links_b + 3 * block_b;
+    const size_t need = links_b + 2 * block_b;
     if (need > kNoallocScratchBytes) {
         char msg[200];
         snprintf(msg, sizeof msg,
@@ -89,7 +90,7 @@ extern "C" int dsbcg_apply_A_noalloc(dsbcg_handle h, const void *U, double kappa
     }
     char *p = (char *)base;
     void *links = U ? (void *)p : const_cast<void *>(staged);
-    void *xin = p + links_b, *tmp = p + links_b + block_b, *yout = p + links_b + 2 * block_b;
+    void *xin = p + links_b, *tmp = p + links_b + block_b;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (U) e = links_to_soa(V, U, links, f64, st);
@@ -97,17 +98,17 @@ extern "C" int dsbcg_apply_A_noalloc(dsbcg_handle h, const void *U, double kappa
         e = copy_field(V, m, FieldDesc{const_cast<void *>(X), kApi, m, 0, true}, FieldDesc{xin, kCM, n, 0, f64},
                        false, 1.0, st);
     const size_t colb = (size_t)n * esz;
+    // D into tmp, then D^H of it straight into the caller's layout
     for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
         const char *in = (const char *)(pass ? tmp : xin);
-        char *out = (char *)(pass ? yout : tmp);
         for (int c0 = 0; c0 < m && e == hipSuccess;) {
             const int k = stencil_chunk(f64, m - c0);
-            e = wilson_apply(g, f64, links, kappa, in + c0 * colb, out + c0 * colb, k, pass == 1, st);
+            const ApiOut ao{Y, m, c0};
+            e = pass ? wilson_apply(g, f64, links, kappa, in + c0 * colb, nullptr, k, true, st, &ao)
+                     : wilson_apply(g, f64, links, kappa, in + c0 * colb, (char *)tmp + c0 * colb, k, false, st);
             c0 += k;
         }
     }
-    if (e == hipSuccess)
-        e = copy_field(V, m, FieldDesc{yout, kCM, n, 0, f64}, FieldDesc{Y, kApi, m, 0, true}, false, 1.0, st);
     if (e != hipSuccess) {
         char msg[160];
         snprintf(msg, sizeof msg, "dsbcg_apply_A_noalloc: %s", hipGetErrorString(e));

@@ -361,15 +361,18 @@ int validate_geom(const int32_t *L) {
     return DSBCG_OK;
 }
 
+// Y = D X or D^H X on b column-major columns; with Yapi the result goes to
+// the caller's layout [V][4][3][b] (complex128) instead of Y.
 int stencil(dsbcg_ctx *h, bool fp64, const void *Ul, double kappa, const void *X, void *Y, int b,
-            bool dagger, hipStream_t st) {
+            bool dagger, hipStream_t st, void *Yapi = nullptr) {
     const size_t esz = fp64 ? sizeof(zd) : sizeof(zf);
     const size_t col = (size_t)12 * h->g.V * esz;  // bytes per column
     for (int c0 = 0; c0 < b;) {
         const int k = stencil_chunk(fp64, b - c0);
+        const ApiOut ao{Yapi, b, c0};
         PROF_LAUNCH(h, prof_cls(kProfStencil, fp64), stencil_bytes(h->g, k, esz), st,
-                    wilson_apply(h->g, fp64, Ul, kappa, (const char *)X + c0 * col, (char *)Y + c0 * col, k,
-                                 dagger, st));
+                    wilson_apply(h->g, fp64, Ul, kappa, (const char *)X + c0 * col,
+                                 Yapi ? nullptr : (char *)Y + c0 * col, k, dagger, st, Yapi ? &ao : nullptr));
         c0 += k;
     }
     return DSBCG_OK;
@@ -1511,11 +1514,10 @@ int dsbcg_apply_D(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = 12 * (int64_t)h->g.V;
     CHK(ensure_ws(h, h->Xin, (size_t)n * m * sizeof(zd)));
-    CHK(ensure_ws(h, h->Yout, (size_t)n * m * sizeof(zd)));
     CHK(use_links(h, U, false, false, st));
     CHK(copy(h, m, api(X, m), cm(h->Xin.p, n, true), false, st));
-    CHK(stencil(h, true, h->Ul64.p, kappa, h->Xin.p, h->Yout.p, m, dagger != 0, st));
-    CHK(copy(h, m, cm(h->Yout.p, n, true), api(Y, m), false, st));
+    // the pass writes the caller's layout directly
+    CHK(stencil(h, true, h->Ul64.p, kappa, h->Xin.p, nullptr, m, dagger != 0, st, Y));
     return DSBCG_OK;
 }
 
@@ -1529,7 +1531,6 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
     const int64_t n = 12 * (int64_t)h->g.V;
     const size_t esz = f64 ? sizeof(zd) : sizeof(zf);
     CHK(ensure_ws(h, h->Xin, (size_t)n * m * esz));
-    CHK(ensure_ws(h, h->Yout, (size_t)n * m * esz));
     CHK(ensure_ws(h, h->T, (size_t)n * m * esz));
     if (U) {
         // only the precision this call needs
@@ -1539,8 +1540,10 @@ int dsbcg_apply_A(dsbcg_handle h, const void *U, double kappa, const void *X, vo
         CHK(use_links(h, U, false, false, st));
     }
     CHK(copy(h, m, api(X, m), cm(h->Xin.p, n, f64), false, st));
-    CHK(apply_A_cm(h, f64, f64 ? h->Ul64.p : h->Ul32.p, kappa, h->Xin.p, h->T.p, h->Yout.p, m, st));
-    CHK(copy(h, m, cm(h->Yout.p, n, f64), api(Y, m), false, st));
+    // D X column-major, then D^H of it straight into the caller's layout
+    const void *Ul = f64 ? h->Ul64.p : h->Ul32.p;
+    CHK(stencil(h, f64, Ul, kappa, h->Xin.p, h->T.p, m, false, st));
+    CHK(stencil(h, f64, Ul, kappa, h->T.p, nullptr, m, true, st, Y));
     return DSBCG_OK;
 }
 

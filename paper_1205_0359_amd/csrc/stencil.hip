@@ -186,7 +186,7 @@ template <typename R, bool DAG, bool RESID, int MAXT, bool GL>
 __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__restrict__ Ul,
                                                          R kappa, const cx<R> *__restrict__ in,
                                                          cx<R> *__restrict__ out, int nb, ResidOut ro,
-                                                         BlockOrder bo) {
+                                                         BlockOrder bo, ApiOut ao) {
     __shared__ cx<R> lf[9 * kSitesPerWG];
     __shared__ cx<R> lb[9 * kSitesPerWG];
     const int lane = threadIdx.x & 63;
@@ -247,6 +247,21 @@ __global__ __launch_bounds__(MAXT) void wilson_cm_kernel(Geom g, const cx<R> *__
     }
     if (!valid) return;
 
+    if (ao.y) {
+        // the caller's layout: the 12 components of a site and its m
+        // columns are one contiguous run, which the nb waves of the
+        // workgroup fill together in L2 (plain stores)
+        zd *oy = (zd *)ao.y + (int64_t)x * 12 * ao.m + ao.c0 + wave;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const cx<R> v = col[(int64_t)(s * 3 + a) * g.V + x];
+                const cx<R> r = mk<R>(v.x - kappa * acc[s][a].x, v.y - kappa * acc[s][a].y);
+                oy[(s * 3 + a) * ao.m] = mk<double>((double)r.x, (double)r.y);
+            }
+        return;
+    }
     cx<R> *oc = out + (int64_t)wave * n;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -272,15 +287,17 @@ __global__ void neighbor_kernel(Geom g, int32_t *out) {
 }
 
 hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, const void *in,
-                        void *out, int nb, bool dagger, hipStream_t st) {
+                        void *out, int nb, bool dagger, hipStream_t st, const ApiOut *api) {
     if (nb < 1 || nb > 16) return hipErrorInvalidValue;
+    if (api && (!api->y || api->c0 < 0 || api->m < api->c0 + nb)) return hipErrorInvalidValue;
+    const ApiOut ao = api ? *api : ApiOut{nullptr, 0, 0};
     const dim3 grid((unsigned)lockstep_blocks(g));
     const dim3 block(64 * nb);
     const ResidOut none{nullptr, nullptr, 0.0, nullptr};
     const BlockOrder lo = lockstep_order(g);
 #define DSBCG_L(R, D, MT, GLB)                                                                      \
     hipLaunchKernelGGL((wilson_cm_kernel<R, D, false, MT, GLB>), grid, block, 0, st, g, (const cx<R> *)Ul, \
-                       (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none, lo)
+                       (R)kappa, (const cx<R> *)in, (cx<R> *)out, nb, none, lo, ao)
 #define DSBCG_W(R, D)                                                                               \
     do {                                                                                            \
         if (small_bound(nb)) DSBCG_L(R, D, 512, false);                                             \
@@ -312,15 +329,16 @@ hipError_t wilson_resid_norms(const Geom &g, const void *Ul, double kappa, const
     const dim3 block(64 * nb);
     const ResidOut ro{(const zd *)b, (const zd *)x, sigma, partials};
     const BlockOrder lo = lockstep_order(g);
+    const ApiOut ao{nullptr, 0, 0};
     if (global_links(true, nb))
         hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, true>), grid, block, 0, st, g,
-                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo, ao);
     else if (small_bound(nb))
         hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 512, false>), grid, block, 0, st, g,
-                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo, ao);
     else
         hipLaunchKernelGGL((wilson_cm_kernel<double, true, true, 1024, false>), grid, block, 0, st, g,
-                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo);
+                           (const zd *)Ul, kappa, (const zd *)in, (zd *)nullptr, nb, ro, lo, ao);
     return hipGetLastError();
 }
 

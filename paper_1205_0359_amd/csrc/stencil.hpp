@@ -10,13 +10,22 @@ struct Geom {
     int32_t V;
 };
 
+// Output in the caller's layout: column r of a launch goes to column c0 + r
+// of the complex128 field y [V][4][3][m] (site-major, column minor),
+// widened from FP32 where the launch computes in FP32.
+struct ApiOut {
+    void *y;
+    int32_t m, c0;
+};
+
 // out = D in (dagger = false) or D^H in (dagger = true) on nb <= 16 columns.
 // in, out: column-major fields, element (column r, spin-colour c, site x) at
 // (r*12 + c)*V + x.  Ul: links as structure of arrays, element e of U_mu(x)
 // at (mu*9 + e)*V + x.  fp64 selects double or float data.  out must not
-// alias in.
+// alias in.  With api != nullptr the result goes to api->y instead of out
+// (out unused).
 hipError_t wilson_apply(const Geom &g, bool fp64, const void *Ul, double kappa, const void *in,
-                        void *out, int nb, bool dagger, hipStream_t st);
+                        void *out, int nb, bool dagger, hipStream_t st, const ApiOut *api = nullptr);
 
 // Columns of the first launch when a pass over nb columns is split into
 // launches (the remainder is split by the same rule): FP64 passes over more

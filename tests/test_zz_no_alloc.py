@@ -58,7 +58,7 @@ def test_noalloc_equals_apply_A_twice_second_smaller(precision, staged):
 
 
 def test_noalloc_rejects_inputs_beyond_the_workspace():
-    L, m = (16, 16, 16, 16), 4  # 65536 sites: 4 blocks of 12 V m complex128 exceed 128 MiB
+    L, m = (16, 16, 16, 16), 4  # 65536 sites: the links and 2 blocks of 12 V m complex128 exceed 128 MiB
     announce("noalloc limit", L, m)
     import torch
     h = dsb.Handle(L)
