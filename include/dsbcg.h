@@ -157,6 +157,9 @@ typedef struct {
     int32_t *frozen_at;       /* host [s*m] (index j*m + l) or NULL: main phase, the number of
                                  Lanczos vectors through the stage at which (l, j) stopped (0:
                                  it never stopped, or its column of B is zero) */
+    double *est_history;      /* host [widths_len] or NULL: residual history of the main phase,
+                                 the largest estimated relative residual over the systems still
+                                 updated after step i at est_history[i-1] (0 past the last step) */
 } dsbcg_stats;
 
 /* Fill opts with the defaults listed above. */

@@ -61,7 +61,8 @@ class dsbcg_stats(ctypes.Structure):
                 ("true_relres", ctypes.POINTER(ctypes.c_double)),
                 ("widths", ctypes.POINTER(ctypes.c_int32)), ("widths_len", ctypes.c_int32),
                 ("qr_redone", ctypes.c_int32), ("mvms_vector", ctypes.c_int64),
-                ("frozen_at", ctypes.POINTER(ctypes.c_int32))]
+                ("frozen_at", ctypes.POINTER(ctypes.c_int32)),
+                ("est_history", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -293,6 +294,9 @@ def _new_stats(s, m):
     st.frozen_at = frozen.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     st._widths_buf = widths  # kept alive with the struct
     st._frozen_buf = frozen
+    hist = np.zeros(_MAX_WIDTHS)
+    st.est_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st._hist_buf = hist
     return st, est, true
 
 
@@ -306,6 +310,7 @@ def _stats_dict(code, st, est, true, s, m):
         "final_width": st.final_width, "switch_iter": st.switch_iter, "qr2_skipped": st.qr2_skipped,
         "main_relres_max": st.main_relres_max, "mvms": int(st.mvms),
         "mvms_vector": int(st.mvms_vector), "frozen_at": st._frozen_buf.reshape(s, m).T.copy(),
+        "est_history": st._hist_buf[:min(st.block_iters, _MAX_WIDTHS)].tolist(),
         "est_relres": est.reshape(s, m).T.copy(), "true_relres": true.reshape(s, m).T.copy(),
     }
 

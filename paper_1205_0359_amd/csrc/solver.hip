@@ -404,6 +404,7 @@ struct SolveStats {
     int64_t mvms = 0;
     int64_t mvms_vector = 0;      // Lanczos vectors through the stage at which the last system stopped
     std::vector<int32_t> widths;  // block width of each main-phase step
+    std::vector<double> est_hist; // largest active estimate after each main-phase step
     std::vector<int32_t> frozen_at;  // [j * m + l]: Lanczos vectors through the stage at which
                                      // (l, j) stopped (0: never)
     double est[kS * kS] = {};
@@ -1354,6 +1355,15 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                 if (((mask0[j] >> l) & 1u) && !((R.colmask[j] >> l) & 1u))
                     stt.frozen_at[(size_t)j * m + l] = (int32_t)(kvec + (vstop ? R.stage[j][l] : b));
         kvec += b;
+        {
+            // residual history: the worst estimate among the systems that
+            // were updated in this step
+            double e = 0.0;
+            for (int j = 0; j < s; ++j)
+                for (int l = 0; l < m; ++l)
+                    if ((mask0[j] >> l) & 1u) e = std::max(e, R.est[j][l]);
+            stt.est_hist.push_back(e);
+        }
         active_list();
         if (bnew == 0) done = true;
         if (o.fixed_iters <= 0 && act.empty()) done = true;
@@ -1601,6 +1611,9 @@ void fill_stats(dsbcg_stats *stats, const SolveStats &stt, const double *tr, int
     if (stats->widths)
         for (int32_t k = 0; k < stats->widths_len; ++k)
             stats->widths[k] = k < (int32_t)stt.widths.size() ? stt.widths[k] : 0;
+    if (stats->est_history)
+        for (int32_t k = 0; k < stats->widths_len; ++k)
+            stats->est_history[k] = k < (int32_t)stt.est_hist.size() ? stt.est_hist[k] : 0.0;
 }
 
 int solve_checked(dsbcg_handle h, const void *U, double kappa, const void *B, int64_t bstride,

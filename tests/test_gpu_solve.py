@@ -345,3 +345,25 @@ def test_workspace_kept_by_default_and_released_on_request():
     assert free0 - free1 < 64 << 20, (free0, free1)
     assert free1 - free2 > held, (free1, free2)
     assert free0 - free3 < 64 << 20, (free0, free3)
+
+
+def test_residual_history_matches_oracle():
+    """stats.est_history: after each main-phase step, the largest estimated
+    relative residual over the systems updated in that step, against the
+    oracle's per-step estimates (systems active in step i: not frozen before
+    it).  tol 1e-6 over 30 fixed steps: the shifts freeze at steps 22, 26
+    and 27, the last steps update nothing (history 0)."""
+    w = inputs.WORKLOADS["haar4^4_m4_s3"]
+    announce("residual history", w.name)
+    U, B = w.make()
+    n, m = w.n, w.m
+    X, st = _gpu_solve(w.L, U, w.kappa, B, w.shifts, 1e-6, fixed_iters=30)
+    ref = oracle.dsbcg(_op(w.L, U, w.kappa), B.reshape(n, m), w.shifts, 1e-6, fixed_iters=30)
+    hist = st["est_history"]
+    assert len(hist) == ref.iters == 30
+    assert np.array_equal(np.unique(ref.frozen_at), [22, 26, 27])
+    for i in range(1, ref.iters + 1):
+        act = (ref.frozen_at == -1) | (ref.frozen_at >= i)
+        want = ref.history[i - 1][act].max() if act.any() else 0.0
+        assert abs(hist[i - 1] - want) <= 1e-6 * want, (i, hist[i - 1], want)
+    assert hist[26] <= 1e-6 < hist[0] and hist[27:] == [0.0, 0.0, 0.0]
