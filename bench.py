@@ -762,7 +762,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
-              "multi-GPU form in this build", file=sys.stderr)
+              "multi-GPU form", file=sys.stderr)
         sys.exit(2)
     if args.paper_experiments:
         import paper_1205_0359_amd as dsb

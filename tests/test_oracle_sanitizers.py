@@ -1,9 +1,9 @@
 """The oracle's C code under AddressSanitizer and UndefinedBehaviorSanitizer.
 
-tests/oracle_sanitize.c drives every entry point of oracle/wilson_oracle.c on
+tests/oracle_sanitize.c calls every entry point of oracle/wilson_oracle.c on
 small lattices (ragged extents, 1-4 columns) with two OpenMP threads; the
-build stops at the first sanitizer report (-fno-sanitize-recover=all) and
-the driver checks <phi, D psi> = <D^H phi, psi>, A = D^H D and the
+program stops at the first sanitizer report (-fno-sanitize-recover=all) and
+checks <phi, D psi> = <D^H phi, psi>, A = D^H D and the
 site-sampled forms, so a report or a failed check fails the test.  Built
 with ROCm's clang: its AddressSanitizer sees the complex-double stores of
 the stencil (an output buffer one element short is reported), which gcc 11's
