@@ -103,7 +103,7 @@ def kernel_class(name: str):
         return "wilson_stencil." + prec
     if "ts_reg_kernel" in name or "ts_lds_kernel" in name:
         return "block_gram_update." + prec
-    if "window_kernel<" in name:
+    if "window_kernel<" in name or "window3_kernel<" in name:
         return "shift_update." + prec
     if "copy_kernel" in name or "links_soa_kernel" in name or "transpose_kernel" in name:
         return "convert"

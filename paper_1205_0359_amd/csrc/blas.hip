@@ -879,6 +879,221 @@ hipError_t window_launch(const WinArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Three-product form of the window contraction.  For c = a + ib, the
+// coefficient of input d = dr + i di in one output, the real 2 x 2 form
+// above spends four real products; here three real contractions over the
+// window's complex inputs give
+//   T1 = sum a dr,  T2 = sum b di,  T3 = sum (a + b)(dr + di),
+//   Re out = T1 - T2,  Im out = T3 - T1 - T2,
+// a quarter fewer matrix-core products and table entries.  The A operand
+// (16 rows x 4 inputs) holds the 8 outputs of each of two shifts, which
+// share the B operand (4 complex inputs x 16 rows, one real combination per
+// contraction); the lane order of small_window_table3 puts output
+// 2 g + (r & 1) of shift 2 js2 + (r >> 1) in register r of lane group g in
+// both precisions.  Stages of 8 window columns (two blocks of 4) and the
+// tables of all shift pairs of the launch are double buffered in LDS as in
+// window_kernel.  Used for windows with no P_{j,i0} inputs and at most 8
+// outputs per shift; the others take window_kernel.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Win3Stage {
+    static constexpr int blocks = 2;                                  // blocks of 4 columns
+    static constexpr int rows = 64;                                   // rows per workgroup
+    static constexpr int rpl = 16 / (int)sizeof(cx<R>);               // rows per lane and copy
+    static constexpr int data_bytes = 4 * blocks * rows * (int)sizeof(cx<R>);
+    static constexpr int data_copies = data_bytes / 1024;
+    static constexpr int coef_elems = blocks * 3 * 64;                // per shift pair
+    static constexpr int coef_bytes = coef_elems * (int)sizeof(R);
+    static constexpr int coef_copies = (coef_bytes + 1023) / 1024;
+    static_assert(data_bytes % 1024 == 0 && coef_bytes % 16 == 0, "16-byte lanes, 1 KiB copies");
+};
+
+// Asynchronous copies of stage k into buf: the data block [column][64 rows],
+// then per shift pair the table entries [block][t][lane] of the stage's
+// blocks.  Columns past the window, rows past n and blocks past the table
+// read column 0 / row 0 / block 0 (finite values whose products are
+// discarded or multiplied by zero coefficients).
+template <typename R>
+__device__ inline void stage_window3(const WinArgs &a, int k, int64_t r0, char *buf, int lane, int wave,
+                                     int nw) {
+    typedef Win3Stage<R> S;
+    const int nblk = (a.ncolv + 3) >> 2, np2 = (a.nshift + 1) >> 1;
+    const int total = S::data_copies + np2 * S::coef_copies;
+    for (int q = wave; q < total; q += nw) {
+        const void *src;
+        char *dst;
+        if (q < S::data_copies) {
+            const int e = q * 64 * S::rpl + lane * S::rpl;
+            const int cc = e / S::rows, r = e - cc * S::rows;
+            const int c = k * 4 * S::blocks + cc;
+            int64_t row = r0 + r;
+            if (row >= a.nrows) row = 0;
+            src = (const cx<R> *)a.colptr[c < a.ncolv ? c : 0] + row;
+            dst = buf + q * 1024;
+        } else {
+            const int jp = (q - S::data_copies) / S::coef_copies;
+            const int cq = (q - S::data_copies) - jp * S::coef_copies;
+            const int byte = cq * 1024 + lane * 16;
+            if (byte >= S::coef_bytes) continue;  // partial last copy
+            const int e = byte / (int)sizeof(R);
+            int blk = k * S::blocks + e / (3 * 64);
+            const int rest = e % (3 * 64);
+            if (blk >= nblk) blk = 0;
+            src = (const R *)a.table + ((size_t)jp * nblk + blk) * 3 * 64 + rest;
+            dst = buf + S::data_bytes + jp * S::coef_bytes + cq * 1024;
+        }
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    }
+}
+
+template <typename R, int SPW2>
+__device__ inline void window3_stages(const WinArgs &a, char *smem, int64_t r0, int lane, int wave, int nw,
+                                      int tile, int jp0, int npw, bool issued,
+                                      typename Mfma<R>::v4 (&acc)[SPW2][3]) {
+    typedef Win3Stage<R> S;
+    const int rl = lane & 15, kk = lane >> 4;
+    const int nblk = (a.ncolv + 3) >> 2, np2 = (a.nshift + 1) >> 1;
+    const int nst = (nblk + S::blocks - 1) / S::blocks;
+    const int buf_bytes = S::data_bytes + np2 * S::coef_bytes;
+    if (!issued) {
+        __syncthreads();
+        if (nst > 0) stage_window3<R>(a, 0, r0, smem, lane, wave, nw);
+    }
+    for (int k = 0; k < nst; ++k) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (k + 1 < nst) stage_window3<R>(a, k + 1, r0, smem + ((k + 1) & 1) * buf_bytes, lane, wave, nw);
+        const char *buf = smem + (k & 1) * buf_bytes;
+        const cx<R> *dat = (const cx<R> *)buf;
+        const R *cof = (const R *)(buf + S::data_bytes) + (size_t)jp0 * S::coef_elems + lane;
+        const int nb = min(S::blocks, nblk - k * S::blocks);
+#pragma unroll
+        for (int bb = 0; bb < S::blocks; ++bb) {
+            if (bb < nb) {
+                const cx<R> d = dat[(4 * bb + kk) * S::rows + tile * 16 + rl];
+                const R dr = d.x, di = d.y, ds = d.x + d.y;
+#pragma unroll
+                for (int u = 0; u < SPW2; ++u) {
+                    if (u < npw) {
+                        const R *cu = cof + u * S::coef_elems + bb * 3 * 64;
+                        acc[u][0] = Mfma<R>::mac(cu[0], dr, acc[u][0]);
+                        acc[u][1] = Mfma<R>::mac(cu[64], di, acc[u][1]);
+                        acc[u][2] = Mfma<R>::mac(cu[128], ds, acc[u][2]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Workgroup: 64 rows, 4 waves per group of up to SPW2 shift pairs; wave w
+// takes the 16-row tile w % 4 for the pairs of group w / 4.  TWO: the FP32
+// part of a window across the switch (see WinArgs), added in FP64.
+template <typename R, int SPW2, bool TWO>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void window3_kernel(WinArgs a) {
+    typedef typename Mfma<R>::v4 v4;
+    typedef typename Mfma<float>::v4 v4f;
+    extern __shared__ __align__(16) char win3_smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int grp = wave >> 2, tile = wave & 3;
+    const int64_t n = a.nrows;
+    const int64_t r0 = (int64_t)blockIdx.x * Win3Stage<R>::rows;
+    const int64_t row = r0 + tile * 16 + (lane & 15);
+    const int np2 = (a.nshift + 1) >> 1;
+    const int jp0 = grp * SPW2;
+    const int npw = min(SPW2, np2 - jp0);  // >= 1 by the launch shape
+
+    if (a.ncolv > 0) stage_window3<R>(a, 0, r0, win3_smem, lane, wave, nw);
+    v4 acc[SPW2][3];
+    v4f acc2[SPW2][3];
+#pragma unroll
+    for (int u = 0; u < SPW2; ++u)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            acc[u][t] = v4{0, 0, 0, 0};
+            acc2[u][t] = v4f{0, 0, 0, 0};
+        }
+    window3_stages<R, SPW2>(a, win3_smem, r0, lane, wave, nw, tile, jp0, npw, true, acc);
+    // the first part's outputs as (re, im) while the FP32 part runs: two
+    // registers per output instead of three
+    double ore[SPW2][4], oim[SPW2][4];
+#pragma unroll
+    for (int u = 0; u < SPW2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double t1 = (double)acc[u][0][r], t2 = (double)acc[u][1][r], t3 = (double)acc[u][2][r];
+            ore[u][r] = t1 - t2;
+            oim[u][r] = t3 - t1 - t2;
+            if (TWO) {
+                // formed here, not after the FP32 part (which would keep
+                // the three sums alive through it)
+                __asm__ volatile("" : "+v"(ore[u][r]), "+v"(oim[u][r]));
+            }
+        }
+    if (TWO) {
+        WinArgs b = a;
+        b.ncolv = a.ncolv2;
+        b.colptr = a.colptr2;
+        b.table = a.table2;
+        window3_stages<float, SPW2>(b, win3_smem, r0, lane, wave, nw, tile, jp0, npw, false, acc2);
+    }
+    if (row >= n) return;
+    const int g = lane >> 4;
+    const int64_t Vs = n / 12, cs = row / Vs;
+    const int64_t api_row = ((row - cs * Vs) * 12 + cs) * a.m;
+#pragma unroll
+    for (int u = 0; u < SPW2; ++u) {
+        if (u >= npw) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int js = 2 * (jp0 + u) + (r >> 1), q = 2 * g + (r & 1);
+            if (js >= a.nshift) continue;
+            double re = ore[u][r], im = oim[u][r];
+            if (TWO) {
+                const double s1 = (double)acc2[u][0][r], s2 = (double)acc2[u][1][r], s3 = (double)acc2[u][2][r];
+                re += s1 - s2;
+                im += s3 - s1 - s2;
+            }
+            const int j = a.shifts[js];
+            if (q < a.m) {
+                zd *x = a.X + (size_t)j * a.xstride + (int64_t)q * n + row;
+                if (a.xinit || ((a.xmask[j] >> q) & 1u)) {
+                    const zd v = a.xinit ? mk<double>(re, im) : mk<double>(x->x + re, x->y + im);
+                    *x = v;
+                    if (a.Xapi) a.Xapi[(int64_t)j * n * a.m + api_row + q] = v;
+                } else if (a.Xapi) {
+                    a.Xapi[(int64_t)j * n * a.m + api_row + q] = *x;
+                }
+            } else if (a.pmask[j] != 0 && q - a.m < a.bend) {
+                const int64_t at = (int64_t)j * a.pstride + (int64_t)(q - a.m) * n + row;
+                if (TWO)
+                    ((zf *)a.Pnew2)[at] = mk<float>((float)re, (float)im);
+                else
+                    ((cx<R> *)a.Pnew)[at] = mk<R>((R)re, (R)im);
+            }
+        }
+    }
+}
+
+template <typename R, int SPW2>
+hipError_t window3_launch(const WinArgs &a, hipStream_t st) {
+    typedef Win3Stage<R> S;
+    const int np2 = (a.nshift + 1) / 2;
+    const int groups = (np2 + SPW2 - 1) / SPW2;
+    const dim3 block(64 * 4 * groups);
+    const dim3 grid((unsigned)((a.nrows + S::rows - 1) / S::rows));
+    const size_t lds = 2 * ((size_t)S::data_bytes + (size_t)np2 * S::coef_bytes);
+    if constexpr (sizeof(R) == 8) {
+        if (a.ncolv2 > 0) {
+            hipLaunchKernelGGL((window3_kernel<R, SPW2, true>), grid, block, lds, st, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((window3_kernel<R, SPW2, false>), grid, block, lds, st, a);
+    return hipGetLastError();
+}
+
 template <typename R, int NMT>
 hipError_t window_launch_spw(const WinArgs &a, int spw, hipStream_t st) {
     if (spw == 1) return window_launch<R, NMT, 1>(a, st);
@@ -905,6 +1120,15 @@ hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st) {
         (a.Xapi && (a.nrows % 12 != 0 || a.m < 1)))
         return hipErrorInvalidValue;
     if (a.nrows <= 0) return hipSuccess;
+    if (a.gauss) {
+        // all shift pairs in one launch: at most 4 groups of 2 pairs, and
+        // 2 (8 KiB + 8 x 3 KiB) of LDS in FP64
+        if (a.bp0 != 0 || a.nmt != 1 || a.m + a.bend > 8 || (a.ncolv2 > 0 && a.table2 == nullptr))
+            return hipErrorInvalidValue;
+        const int np2 = (a.nshift + 1) / 2;
+        if (fp64) return np2 <= 4 ? window3_launch<double, 1>(a, st) : window3_launch<double, 2>(a, st);
+        return np2 <= 4 ? window3_launch<float, 1>(a, st) : window3_launch<float, 2>(a, st);
+    }
     // shifts per launch: at most 16 waves (4 groups) of SPW <= 4 shifts, FP64
     // accumulators of wide outputs in at most 2 shifts per wave, and at most
     // 64 KiB of double-buffered LDS

@@ -379,6 +379,61 @@ hipError_t small_window_table(const WinCoef wc, const WindowTable &wt, const int
     return hipGetLastError();
 }
 
+// Three-product table (window3_kernel): one 64-lane block per (shift pair
+// js2, block of 4 input columns).  Lane i + 16 k holds, for output row i of
+// the matrix-core tile (two shifts of 8 outputs each) and input column
+// 4 blk + k, the three real coefficients a, b and a + b of c = a + ib in
+// table[((js2 * nblk + blk) * 3 + t) * 64 + lane], t = 0, 1, 2.  Row i
+// belongs to register r of lane group g of the product (FP64 instruction:
+// i = g + 4 r, FP32: i = 4 g + r), which stands for shift 2 js2 + (r >> 1)
+// and output 2 g + (r & 1): both precisions leave the same output in the
+// same register.
+template <typename R>
+__global__ __launch_bounds__(64) void window_table3_kernel(WinCoef wc, WindowTable wt,
+                                                           const int32_t *__restrict__ shifts,
+                                                           const int32_t *__restrict__ pmask, R *table) {
+    const int js2 = blockIdx.x, blk = blockIdx.y;
+    const int lane = threadIdx.x;
+    const int i = lane & 15, k = lane >> 4;
+    const int g = sizeof(R) == 8 ? (i & 3) : (i >> 2), r = sizeof(R) == 8 ? (i >> 2) : (i & 3);
+    const int js = 2 * js2 + (r >> 1), q = 2 * g + (r & 1);
+    const int col = 4 * blk + k;
+    zd c = mk<double>(0, 0);
+    if (js < wt.nshift && col < wt.ncolv) {
+        const int j = shifts[js];
+        const bool xout = q < wt.m;
+        const bool pout = !xout && q - wt.m < wt.bend && pmask[j] != 0;
+        if (xout || pout) {
+            const int qq = xout ? q : q - wt.m;
+            int u = 0, c0 = 0;
+            while (u < wt.K - 1 && col >= c0 + wt.wb[u]) c0 += wt.wb[u++];
+            const int slot = wt.slot0 + u;
+            if (slot < wc.Wcount[j])
+                c = (xout ? wc.Wf : wc.Wh)[((size_t)j * kWinMax + slot) * 256 + (col - c0) * 16 + qq];
+        }
+    }
+    R *o = table + ((size_t)js2 * gridDim.y + blk) * 3 * 64 + lane;
+    o[0] = (R)c.x;
+    o[64] = (R)c.y;
+    o[128] = (R)(c.x + c.y);
+}
+
+hipError_t small_window_table3(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
+                               const int32_t *pmask, bool fp64, void *table, hipStream_t stream) {
+    if (wt.nshift <= 0 || wt.ncolv <= 0) return hipSuccess;
+    if (wt.K < 1 || wt.slot0 < 0 || wt.slot0 + wt.K > kWinMax || wt.bp0 != 0 || wt.m + wt.bend > 8 ||
+        wt.nshift > 16)
+        return hipErrorInvalidValue;
+    const dim3 grid((wt.nshift + 1) / 2, (wt.ncolv + 3) / 4);
+    if (fp64)
+        hipLaunchKernelGGL(window_table3_kernel<double>, grid, dim3(64), 0, stream, wc, wt, shifts, pmask,
+                           (double *)table);
+    else
+        hipLaunchKernelGGL(window_table3_kernel<float>, grid, dim3(64), 0, stream, wc, wt, shifts, pmask,
+                           (float *)table);
+    return hipGetLastError();
+}
+
 // One block of 64 lanes per (input pair, output tile) of the combined table.
 template <typename R>
 __global__ __launch_bounds__(64) void rational_table_kernel(WinCoef wc, WindowTable wt,

@@ -114,6 +114,14 @@ struct WindowTable {
 hipError_t small_window_table(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
                               const int32_t *pmask, bool fp64, void *table, hipStream_t stream);
 
+// Table of the three-product window contraction (WinArgs.gauss) for a
+// window part with no P_{j,i0} inputs (bp0 = 0) and m + bend <= 8:
+// table[js2][blk][t][64] for shift pairs js2 < ceil(nshift / 2) and blocks
+// of 4 input columns blk < ceil(ncolv / 4), t = 0, 1, 2 (real part,
+// imaginary part, their sum); lane order in window_table3_kernel.
+hipError_t small_window_table3(const WinCoef wc, const WindowTable &wt, const int32_t *shifts,
+                               const int32_t *pmask, bool fp64, void *table, hipStream_t stream);
+
 // Combined table of the partial-fraction window update (rational_window_apply):
 // table[pair][mt][lane] in the same lane order, for the outputs 0..m-1 of Y,
 // with input pairs [P_{j,i0} of each window shift (ceil(bp0 / 2) pairs each,

@@ -983,6 +983,10 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
         size_t tab_off = 0;  // elements (doubles) into the table buffer
         WinArgs wfirst;      // FP64 part of a window across the switch
         memset(&wfirst, 0, sizeof(wfirst));
+        // three real products per complex product where the window has no
+        // P_{j,i0} inputs and at most 8 outputs per shift (both parts of a
+        // window across the switch take the same form)
+        const bool gauss = !rmode && (i0 < 1 || bw[i0] == 0) && m + bend <= 8;
         double bytes_first = 0.0;
         const int pnew = pcur ^ 1;
         for (size_t sg = 0; sg < seg.size(); ++sg) {
@@ -1072,8 +1076,13 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                 continue;
             }
             double *tab = (double *)h->wtable.p + tab_off;
-            tab_off += (size_t)wt.nshift * wt.npairs * wt.nmt * 64;
-            PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_table(WC, wt, dshift, dpm, f64s, tab, st));
+            if (gauss) {
+                tab_off += (size_t)((wt.nshift + 1) / 2) * ((wt.ncolv + 3) / 4) * 3 * 64;
+                PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_table3(WC, wt, dshift, dpm, f64s, tab, st));
+            } else {
+                tab_off += (size_t)wt.nshift * wt.npairs * wt.nmt * 64;
+                PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_table(WC, wt, dshift, dpm, f64s, tab, st));
+            }
             WinArgs wa;
             memset(&wa, 0, sizeof(wa));
             wa.nrows = n;
@@ -1098,6 +1107,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             wa.pmask = dpm;
             wa.xinit = (xfresh && sg == 0) ? 1 : 0;
             wa.Xapi = xapi;
+            wa.gauss = gauss ? 1 : 0;
             const double api_bytes = xapi ? (double)n * sizeof(zd) * m * wt.nshift : 0.0;
             if (seg.size() == 2 && sg == 0) {
                 // a window across the switch: the FP64 part waits for the FP32
