@@ -192,3 +192,27 @@ def test_fp32_form_ragged_lattices(L):
     for j in range(len(sig)):
         # both are within cond * 1e-10 of the exact solution; cond(A) is ~20 here
         assert rel_fro(Xh[j], ref.X[j]) <= 1e-8, j
+
+
+@pytest.mark.parametrize("L,m,s", [((3, 5, 7, 9), 4, 3), ((4, 4, 4, 6), 6, 5)])
+def test_fp32_from_the_first_step(L, m, s):
+    """switch_at = 1 puts the switch before the first step (every starting
+    estimate is 1): the first window holds only FP32 blocks, contracted by
+    the FP32 three-product window kernel (odd shift counts leave half of the
+    last shift pair empty).  Every (l, j) reaches the FP64 true residual
+    1e-10 (re-solves allowed) and the solution agrees with the FP64 oracle's
+    within cond * 1e-10."""
+    announce("fp32 from step 1", L, f"m={m}", f"s={s}")
+    V = int(np.prod(L))
+    U = inputs.make_links(L, "haar", inputs.rng_for(884, m))
+    B = inputs.gaussian_rhs(inputs.rng_for(884, 10 + m), V, m)
+    sig = tuple(np.logspace(-4, -0.3, s))
+    h = dsb.Handle(L)
+    X, st = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=FP32, switch_at=1.0)
+    assert st["status"] == "OK" and st["switch_iter"] == 1
+    assert st["true_relres"].max() <= 1e-10
+    n = 12 * V
+    ref = oracle.dsbcg(_op(L, U, 0.124), B.reshape(n, m), sig, 1e-13)
+    Xh = host(X).reshape(s, n, m)
+    for j in range(s):
+        assert rel_fro(Xh[j], ref.X[j]) <= 1e-8, j
