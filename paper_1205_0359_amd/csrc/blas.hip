@@ -893,8 +893,10 @@ hipError_t window_launch(const WinArgs &a, hipStream_t st) {
 // 2 g + (r & 1) of shift 2 js2 + (r >> 1) in register r of lane group g in
 // both precisions.  Stages of 8 window columns (two blocks of 4) and the
 // tables of all shift pairs of the launch are double buffered in LDS as in
-// window_kernel.  Used for windows with no P_{j,i0} inputs and at most 8
-// outputs per shift; the others take window_kernel.
+// window_kernel.  The FP32 part of a window across the switch runs in
+// window_kernel's real 2 x 2 form, whose two accumulators per output leave
+// room for the FP64 part's results.  Used for windows with no P_{j,i0}
+// inputs and at most 8 outputs per shift; the others take window_kernel.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Win3Stage {
@@ -1006,14 +1008,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
 
     if (a.ncolv > 0) stage_window3<R>(a, 0, r0, win3_smem, lane, wave, nw);
     v4 acc[SPW2][3];
-    v4f acc2[SPW2][3];
 #pragma unroll
     for (int u = 0; u < SPW2; ++u)
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            acc[u][t] = v4{0, 0, 0, 0};
-            acc2[u][t] = v4f{0, 0, 0, 0};
-        }
+        for (int t = 0; t < 3; ++t) acc[u][t] = v4{0, 0, 0, 0};
     window3_stages<R, SPW2>(a, win3_smem, r0, lane, wave, nw, tile, jp0, npw, true, acc);
     // the first part's outputs as (re, im) while the FP32 part runs: two
     // registers per output instead of three
@@ -1032,11 +1030,30 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
             }
         }
     if (TWO) {
+        // the FP32 part in the real 2 x 2 form of window_kernel (table2 from
+        // small_window_table): two accumulators per output instead of three
+        // keep the first part's outputs in registers
         WinArgs b = a;
         b.ncolv = a.ncolv2;
         b.colptr = a.colptr2;
         b.table = a.table2;
-        window3_stages<float, SPW2>(b, win3_smem, r0, lane, wave, nw, tile, jp0, npw, false, acc2);
+        b.npairs = a.npairs2;
+        b.pairs_p = 0;
+        b.bp0 = 0;
+        v4f acc2[2 * SPW2][1];
+#pragma unroll
+        for (int u = 0; u < 2 * SPW2; ++u) acc2[u][0] = v4f{0, 0, 0, 0};
+        const int js0 = 2 * jp0, nsw = min(2 * SPW2, a.nshift - js0);
+        window_stages<float, 1, 2 * SPW2>(b, win3_smem, r0, lane, wave, nw, tile, js0, nsw, false, acc2);
+        // shift 2 u + (r >> 1) of the wave, output 2 g + (r & 1): (re, im) in
+        // registers 2 (r & 1), 2 (r & 1) + 1 of its accumulator
+#pragma unroll
+        for (int u = 0; u < SPW2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ore[u][r] += (double)acc2[2 * u + (r >> 1)][0][2 * (r & 1)];
+                oim[u][r] += (double)acc2[2 * u + (r >> 1)][0][2 * (r & 1) + 1];
+            }
     }
     if (row >= n) return;
     const int g = lane >> 4;
@@ -1049,12 +1066,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
         for (int r = 0; r < 4; ++r) {
             const int js = 2 * (jp0 + u) + (r >> 1), q = 2 * g + (r & 1);
             if (js >= a.nshift) continue;
-            double re = ore[u][r], im = oim[u][r];
-            if (TWO) {
-                const double s1 = (double)acc2[u][0][r], s2 = (double)acc2[u][1][r], s3 = (double)acc2[u][2][r];
-                re += s1 - s2;
-                im += s3 - s1 - s2;
-            }
+            const double re = ore[u][r], im = oim[u][r];
             const int j = a.shifts[js];
             if (q < a.m) {
                 zd *x = a.X + (size_t)j * a.xstride + (int64_t)q * n + row;

@@ -98,8 +98,9 @@ struct WinArgs {
     // (complex128, V = nrows / 12, shift j at j * nrows * m).
     zd *Xapi;
     // Nonzero: three real products per complex product (window3_kernel);
-    // table and table2 then come from small_window_table3, and the window
-    // has no P_{j,i0} inputs (bp0 = 0) and m + bend <= 8 (nmt = 1).
+    // table then comes from small_window_table3 (table2, the FP32 part, still
+    // from small_window_table), and the window has no P_{j,i0} inputs
+    // (bp0 = 0) and m + bend <= 8 (nmt = 1).
     int gauss;
 };
 hipError_t window_apply(bool fp64, const WinArgs &a, hipStream_t st);

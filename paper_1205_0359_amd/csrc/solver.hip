@@ -1076,7 +1076,9 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
                 continue;
             }
             double *tab = (double *)h->wtable.p + tab_off;
-            if (gauss) {
+            // the FP32 part of a window across the switch keeps the real
+            // 2 x 2 table (see WinArgs.gauss)
+            if (gauss && !(seg.size() == 2 && sg == 1)) {
                 tab_off += (size_t)((wt.nshift + 1) / 2) * ((wt.ncolv + 3) / 4) * 3 * 64;
                 PROF_LAUNCH(h, kProfSmall, 0.0, st, small_window_table3(WC, wt, dshift, dpm, f64s, tab, st));
             } else {
