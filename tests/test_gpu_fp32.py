@@ -216,3 +216,35 @@ def test_fp32_from_the_first_step(L, m, s):
     Xh = host(X).reshape(s, n, m)
     for j in range(s):
         assert rel_fro(Xh[j], ref.X[j]) <= 1e-8, j
+
+
+@pytest.mark.parametrize("L,m,s", [((3, 5, 7, 9), 4, 3), ((5, 5, 5, 7), 3, 4), ((4, 4, 4, 6), 5, 3)])
+def test_first_window_across_the_switch_goes_on(L, m, s):
+    """A first window that spans the switch and ends before the solve does:
+    its FP64 part (three real products per complex product) and FP32 part
+    (real 2 x 2 form) run as one launch that also hands P_{j,end} on in
+    FP32 (window = switch step + 1).  And a first window of FP32 blocks only
+    (switch_at = 1) that hands P_{j,end} on (window = 3).  With m = 5 the
+    m + b_end = 10 outputs per shift take the real 2 x 2 form throughout.
+    Every (l, j)
+    reaches the FP64 true residual 1e-10 and the solution agrees with the
+    FP64 oracle's within cond * 1e-10."""
+    V = int(np.prod(L))
+    U = inputs.make_links(L, "haar", inputs.rng_for(885, m))
+    B = inputs.gaussian_rhs(inputs.rng_for(885, 10 + m), V, m)
+    sig = tuple(np.logspace(-4, -0.3, s))
+    n = 12 * V
+    ref = oracle.dsbcg(_op(L, U, 0.124), B.reshape(n, m), sig, 1e-13)
+    h = dsb.Handle(L)
+    announce("first window across the switch", L, f"m={m}", f"s={s}")
+    _, st0 = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=FP32)
+    sw, nit = st0["switch_iter"], st0["block_iters"]
+    assert 1 < sw and sw + 1 < nit
+    for kw in ({"window": sw + 1}, {"window": 3, "switch_at": 1.0}):
+        announce("first window across the switch", L, kw)
+        X, st = dsb.dsbcg_solve(h, dev(U), 0.124, dev(B), sig, 1e-10, precision=FP32, **kw)
+        assert st["status"] == "OK" and st["true_relres"].max() <= 1e-10
+        assert st["reliable_updates"] >= 1
+        Xh = host(X).reshape(s, n, m)
+        for j in range(s):
+            assert rel_fro(Xh[j], ref.X[j]) <= 1e-8, (kw, j)
