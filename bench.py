@@ -263,6 +263,25 @@ def copy_ceiling(reps=10):
             "kind": "device-to-device copy of 1 GiB (runtime copy kernel), read + written bytes"}
 
 
+def host_info():
+    """CPU model, logical CPUs and memory of the host (the oracle's baseline machine)."""
+    info = {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    info["mem_gib"] = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
 def source_digest(paths):
     h = hashlib.sha256()
     for pth in paths:
@@ -882,7 +901,7 @@ def main():
         "grad": grad,
         "partial_fraction": rational,
         "vector_stop": vstop,
-        "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()},
+        "host": host_info(),
     }
     print(json.dumps(line), flush=True)
 
