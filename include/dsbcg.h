@@ -310,6 +310,12 @@ int dsbcg_link_grad(dsbcg_handle h, double kappa, const void *Phi, const void *P
 int dsbcg_profile_enable(dsbcg_handle h, int32_t enable);
 int dsbcg_profile_read(dsbcg_handle h, int32_t kclass, double *ms, int64_t *launches,
                        double *bytes);
+/* Time only the classes whose bit is set in class_mask (bit k: class k;
+ * 0xffffffff, the default, times every class).  Launches of other classes
+ * run without events, so that one class can be timed inside a measured
+ * region at the cost of its own launches only.  The mask stays until the
+ * next call; dsbcg_profile_enable leaves it as it is. */
+int dsbcg_profile_select(dsbcg_handle h, uint32_t class_mask);
 /* Name of a kernel class, NULL past the last one. */
 const char *dsbcg_profile_name(int32_t kclass);
 

@@ -7,10 +7,12 @@ ctypes binding, the seeded input generators and the build script.
 """
 from ._lib import (DSBCG_FP32_RELIABLE, DSBCG_FP64, DSBCGError, Handle, NotConvergedError,
                    NotHPDError, dsbcg_apply_A, dsbcg_apply_A_noalloc, dsbcg_apply_D, dsbcg_link_grad, dsbcg_neighbors,
-                   dsbcg_profile_enable, dsbcg_profile_read, dsbcg_solve, dsbcg_solve_multi,
+                   dsbcg_profile_enable, dsbcg_profile_read, dsbcg_profile_select, dsbcg_solve,
+                   dsbcg_solve_multi,
                    dsbcg_solve_rational, dsbcg_grad, dsbcg_stage_links, dsbcg_release_workspace, default_opts, load)
 
 __all__ = ["DSBCG_FP32_RELIABLE", "DSBCG_FP64", "DSBCGError", "Handle", "NotConvergedError",
            "NotHPDError", "dsbcg_apply_A", "dsbcg_apply_A_noalloc", "dsbcg_apply_D", "dsbcg_link_grad", "dsbcg_neighbors",
-           "dsbcg_profile_enable", "dsbcg_profile_read", "dsbcg_solve", "dsbcg_solve_multi",
+           "dsbcg_profile_enable", "dsbcg_profile_read", "dsbcg_profile_select", "dsbcg_solve",
+           "dsbcg_solve_multi",
            "dsbcg_solve_rational", "dsbcg_grad", "dsbcg_stage_links", "dsbcg_release_workspace", "default_opts", "load"]

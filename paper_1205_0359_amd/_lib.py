@@ -119,6 +119,8 @@ def load():
     lib.dsbcg_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
     lib.dsbcg_profile_read.restype = ctypes.c_int
+    lib.dsbcg_profile_select.argtypes = [P, ctypes.c_uint32]
+    lib.dsbcg_profile_select.restype = ctypes.c_int
     lib.dsbcg_profile_name.argtypes = [i32]
     lib.dsbcg_profile_name.restype = ctypes.c_char_p
     lib.dsbcg_last_error.argtypes = []
@@ -429,6 +431,11 @@ def dsbcg_link_grad(h: Handle, kappa: float, Phi, Psi, dU=None, stream=None):
 def dsbcg_profile_enable(h: Handle, enable: bool = True):
     """Start (and reset) or stop per-kernel-class timing with HIP events."""
     _check(load().dsbcg_profile_enable(h.ptr, int(bool(enable))))
+
+
+def dsbcg_profile_select(h: Handle, class_mask: int = 0xFFFFFFFF):
+    """Time only the kernel classes whose bit is set (default: every class)."""
+    _check(load().dsbcg_profile_select(h.ptr, int(class_mask) & 0xFFFFFFFF))
 
 
 def dsbcg_profile_read(h: Handle) -> dict:

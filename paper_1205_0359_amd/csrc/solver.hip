@@ -89,8 +89,10 @@ struct ProfRec {
 struct dsbcg_ctx {
     Geom g{};
     int device = 0;
-    // kernel timing (dsbcg_profile_enable)
+    // kernel timing (dsbcg_profile_enable); prof_mask: classes timed
+    // (dsbcg_profile_select)
     bool prof = false;
+    uint32_t prof_mask = 0xffffffffu;
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_pool;
     double prof_ms[kProfClasses] = {};
@@ -169,9 +171,12 @@ struct ProfToken {
     hipEvent_t a = nullptr;
 };
 
-ProfToken prof_begin(dsbcg_ctx *h, hipStream_t st) {
+// whether launches of class cls are timed
+inline bool prof_on(const dsbcg_ctx *h, int cls) { return h->prof && ((h->prof_mask >> cls) & 1u); }
+
+ProfToken prof_begin(dsbcg_ctx *h, hipStream_t st, int cls) {
     ProfToken t;
-    if (!h->prof) return t;
+    if (!prof_on(h, cls)) return t;
     if (prof_event(h, &t.a) != hipSuccess) return t;
     if (hipEventRecord(t.a, st) != hipSuccess) return t;
     t.on = true;
@@ -209,7 +214,7 @@ hipError_t prof_flush(dsbcg_ctx *h) {
 
 #define PROF_LAUNCH(h, cls, bytes, st, expr)                  \
     do {                                                      \
-        ProfToken tok_ = prof_begin((h), (st));               \
+        ProfToken tok_ = prof_begin((h), (st), (cls));        \
         HIPCHK(expr);                                         \
         HIPCHK(prof_end((h), tok_, (cls), (bytes), (st)));    \
     } while (0)
@@ -1305,7 +1310,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             CHK(ts.run(a, nullptr));
         }
         CHK(read_report(h, st));
-        if (h->prof && h->rep_host->skip_qr2) {
+        if (prof_on(h, prof_cls(kProfBlock, f64)) && h->rep_host->skip_qr2) {
             // the second-pass launch returned at once: it moved no data
             const int cls = prof_cls(kProfBlock, f64);
             h->prof_bytes[cls] -= 2.0 * b * col_bytes;
@@ -1315,7 +1320,7 @@ int solve_core(dsbcg_ctx *h, double kappa, const void *B, int64_t bstride, int m
             // a drop decision below the resolution of the Gram matrix: the
             // skipped basis update moved no data; form W'' and redo its QR
             // column by column
-            if (h->prof) {
+            if (prof_on(h, prof_cls(kProfBlock, f64))) {
                 const int cls = prof_cls(kProfBlock, f64);
                 h->prof_bytes[cls] -= (3.0 * b + bp) * col_bytes;
                 h->prof_launches[cls] -= 1;
@@ -1461,6 +1466,12 @@ int dsbcg_profile_enable(dsbcg_handle h, int32_t enable) {
         h->prof_launches[k] = 0;
     }
     h->prof = enable != 0;
+    return DSBCG_OK;
+}
+
+int dsbcg_profile_select(dsbcg_handle h, uint32_t class_mask) {
+    if (!h) return fail(DSBCG_ERR_ARG, "NULL handle");
+    h->prof_mask = class_mask;
     return DSBCG_OK;
 }
 

@@ -191,6 +191,37 @@ def test_solve_repeatable_bitwise():
     assert np.array_equal(host(X1), host(X2)) and s1["block_iters"] == s2["block_iters"]
 
 
+def test_profile_class_mask():
+    """dsbcg_profile_select: with the mask of one class only that class's
+    launches are timed (the others count none); with every class the totals
+    match the selected class's, and the solution is the same bit for bit."""
+    L = (4, 4, 6, 8)
+    announce("profile mask", L)
+    U, B = _problem(L, 5, 861, "smooth")
+    h = dsb.Handle(L)
+    dU, dB = dev(U), dev(B)
+    names = [dsb.load().dsbcg_profile_name(k).decode() for k in range(32)
+             if dsb.load().dsbcg_profile_name(k)]
+    k = names.index("wilson_stencil.f64")
+    dsb.dsbcg_profile_enable(h, True)
+    X1, s1 = dsb.dsbcg_solve(h, dU, 0.125, dB, (1e-3, 1e-1), 1e-10)
+    every = dsb.dsbcg_profile_read(h)
+    dsb.dsbcg_profile_select(h, 1 << k)
+    dsb.dsbcg_profile_enable(h, True)
+    X2, s2 = dsb.dsbcg_solve(h, dU, 0.125, dB, (1e-3, 1e-1), 1e-10)
+    one = dsb.dsbcg_profile_read(h)
+    dsb.dsbcg_profile_enable(h, False)
+    dsb.dsbcg_profile_select(h)
+    assert np.array_equal(host(X1), host(X2))
+    assert sum(v["launches"] > 0 for v in every.values()) >= 4
+    for name, v in one.items():
+        if name == "wilson_stencil.f64":
+            assert v["launches"] == every[name]["launches"] > 0
+            assert v["bytes"] == every[name]["bytes"] and v["ms"] > 0
+        else:
+            assert v["launches"] == 0 and v["ms"] == 0 and v["bytes"] == 0, name
+
+
 @pytest.mark.parametrize("m,s", [(1, 1), (16, 16)])
 def test_extreme_widths(m, s):
     L = (2, 2, 4, 4)
