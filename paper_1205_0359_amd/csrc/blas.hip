@@ -263,30 +263,42 @@ __global__ __launch_bounds__(256) void ts_reg_kernel(TsArgs a) {
     }
 }
 
-// Wider blocks (B = 16): a tile of rows (one per thread) is staged in LDS
-// (column-major) and the Gram is accumulated by 2 x 2 blocks of pairs; with
-// 128 threads two halves of the tile are summed separately.
+// Wider blocks (B = 16): a workgroup of 4 waves takes tiles of 64 rows.
+// Each row's outputs are formed by 4 threads (output columns q = c, c + 4,
+// c + 8, c + 12 for thread group c) and staged in LDS, column-major with
+// rows padded to 65 entries so that the Gram reads of different columns
+// fall in different banks.  The Gram is accumulated by 2 x 2 blocks of
+// pairs, each block by 4 threads over a quarter of the tile's rows, and the
+// quarters are added in a fixed order at the end.
 template <typename R>
 struct TileRows {
-    static constexpr int value = sizeof(R) == 8 ? 64 : 128;
+    static constexpr int value = 64;
 };
+constexpr int kLdsThreads = 256;
 
 template <typename R>
-__global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
+__global__ __launch_bounds__(kLdsThreads) void ts_lds_kernel(TsArgs a) {
     if (a.skip && *a.skip) return;  // uniform: before any barrier
     constexpr int B = kMaxW;
     constexpr int kTileRows = TileRows<R>::value;
+    constexpr int kLd = kTileRows + 1;      // padded column length in LDS
+    constexpr int kQuarter = kTileRows / 4;
+    constexpr size_t kTileBytes = 2 * (size_t)B * kLd * sizeof(cx<R>);
+    constexpr size_t kRedBytes = 4 * 8 * 64 * sizeof(zd);
     __shared__ cx<R> coef[3 * B * B];
-    __shared__ cx<R> so[B * kTileRows];
-    __shared__ cx<R> sl[B * kTileRows];
-    __shared__ zd red[8][64];
+    // so and sl (the tile's outputs and L columns) while the tiles run, the
+    // quarters' partial Gram blocks afterwards
+    __shared__ __align__(16) char lds[kTileBytes > kRedBytes ? kTileBytes : kRedBytes];
+    cx<R> *so = reinterpret_cast<cx<R> *>(lds);
+    cx<R> *sl = so + B * kLd;
     load_coefs<R, B>(a, coef);
     const int t = threadIdx.x;
     const bool withL = a.gram == 2 || a.gram == 4;  // gram 4: a.bl == a.bout (checked by ts_run)
     const int bl = withL ? a.bl : a.bout;           // gram 3 (diagonal) runs as gram 1
     const int nbq = (a.bout + 1) / 2, nbp = (bl + 1) / 2;
     const int nblk = nbp * nbq;
-    const int blk = t & 63, half = t >> 6;
+    const int lane = t & 63, grp = t >> 6;         // combination: row lane, column group
+    const int blk = lane, quarter = grp;           // Gram: 2 x 2 block, quarter of the rows
     const int bp = (blk < nblk) ? blk / nbq : 0, bq = (blk < nblk) ? blk - (blk / nbq) * nbq : 0;
     zd G[2][2], G2[2][2];  // G2: out^H out of gram 4
     for (int u = 0; u < 2; ++u)
@@ -297,45 +309,59 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
     __syncthreads();
     for (int64_t t0 = r0; t0 < r1; t0 += kTileRows) {
         __asm__ volatile("" ::: "memory");
-        const int64_t row = t0 + t;
+        const int64_t row = t0 + lane;
         const bool ok = row < r1;
-        if (ok) {
-            cx<R> o[B];
-            combine_row<R, B, 3>(a, coef, row, o);
+        // outputs q = grp + 4 j of this row: out = sum_k X_k C_k, every input
+        // of a block in flight at once (past bx[k] the coefficients are
+        // zero), in the order of combine_row
+        cx<R> o[B / 4];
 #pragma unroll
-            for (int q = 0; q < B; ++q) {
-                if (out && q < a.bout) out[q * a.cso + row] = o[q];
-                so[q * kTileRows + t] = o[q];
-            }
-            if (withL) {
-                const cx<R> *Lp = (const cx<R> *)a.L + row;
+        for (int j = 0; j < B / 4; ++j) o[j] = mk<R>(0, 0);
+        if (ok) {
+#pragma unroll 1
+            for (int k = 0; k < a.K; ++k) {
+                const cx<R> *X = (const cx<R> *)a.X[k] + row;
+                const int last = max(a.bx[k] - 1, 0);
+                cx<R> x[B];
+#pragma unroll
+                for (int p = 0; p < B; ++p) x[p] = X[(int64_t)min(p, last) * a.cs[k]];
 #pragma unroll
                 for (int p = 0; p < B; ++p) {
-                    const cx<R> v = Lp[(int64_t)min(p, a.bl - 1) * a.csl];
-                    sl[p * kTileRows + t] = p < a.bl ? v : mk<R>(0, 0);
+                    // one coefficient row at a time
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int j = 0; j < B / 4; ++j) cmac(o[j], x[p], coef[(k * B + p) * B + grp + 4 * j]);
                 }
             }
-        } else {
-            for (int q = 0; q < B; ++q) so[q * kTileRows + t] = mk<R>(0, 0);
-            if (withL)
-                for (int p = 0; p < B; ++p) sl[p * kTileRows + t] = mk<R>(0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < B / 4; ++j) {
+            const int q = grp + 4 * j;
+            if (ok && out && q < a.bout) out[q * a.cso + row] = o[j];
+            so[q * kLd + lane] = (ok && q < a.bout) ? o[j] : mk<R>(0, 0);
+            if (withL) {
+                cx<R> v = mk<R>(0, 0);
+                if (ok && q < a.bl) v = ((const cx<R> *)a.L)[(int64_t)q * a.csl + row];
+                sl[q * kLd + lane] = v;
+            }
         }
         __syncthreads();
         if (a.gram && blk < nblk) {
             const cx<R> *L = withL ? sl : so;
             const int p0 = 2 * bp, q0 = 2 * bq;
-            for (int r = half * 64; r < half * 64 + 64 && r < kTileRows; ++r) {
-                const zd l0 = cvt<double>(L[p0 * kTileRows + r]);
-                const zd l1 = cvt<double>(L[(p0 + 1) * kTileRows + r]);
-                const zd y0 = cvt<double>(so[q0 * kTileRows + r]);
-                const zd y1 = cvt<double>(so[(q0 + 1) * kTileRows + r]);
+#pragma unroll 2
+            for (int r = quarter * kQuarter; r < (quarter + 1) * kQuarter; ++r) {
+                const zd l0 = cvt<double>(L[p0 * kLd + r]);
+                const zd l1 = cvt<double>(L[(p0 + 1) * kLd + r]);
+                const zd y0 = cvt<double>(so[q0 * kLd + r]);
+                const zd y1 = cvt<double>(so[(q0 + 1) * kLd + r]);
                 cmac_conj(G[0][0], l0, y0);
                 cmac_conj(G[0][1], l0, y1);
                 cmac_conj(G[1][0], l1, y0);
                 cmac_conj(G[1][1], l1, y1);
                 if (a.gram == 4) {
-                    const zd o0 = cvt<double>(so[p0 * kTileRows + r]);
-                    const zd o1 = cvt<double>(so[(p0 + 1) * kTileRows + r]);
+                    const zd o0 = cvt<double>(so[p0 * kLd + r]);
+                    const zd o1 = cvt<double>(so[(p0 + 1) * kLd + r]);
                     cmac_conj(G2[0][0], o0, y0);
                     cmac_conj(G2[0][1], o0, y1);
                     cmac_conj(G2[1][0], o1, y0);
@@ -346,25 +372,28 @@ __global__ __launch_bounds__(128) void ts_lds_kernel(TsArgs a) {
         __syncthreads();
     }
     if (!a.gram) return;
-    // combine the two row halves, then write the blocks
-    if (half == 1 && blk < nblk)
+    // add the four quarters in a fixed order, then write the blocks
+    zd *red = reinterpret_cast<zd *>(lds);  // [quarter][8][64]
+    if (blk < nblk)
         for (int u = 0; u < 2; ++u)
             for (int v = 0; v < 2; ++v) {
-                red[u * 2 + v][blk] = G[u][v];
-                red[4 + u * 2 + v][blk] = G2[u][v];
+                red[(quarter * 8 + u * 2 + v) * 64 + blk] = G[u][v];
+                red[(quarter * 8 + 4 + u * 2 + v) * 64 + blk] = G2[u][v];
             }
     __syncthreads();
-    if (half == 0 && blk < nblk) {
+    if (quarter == 0 && blk < nblk) {
         const int p0 = 2 * bp, q0 = 2 * bq;
         for (int u = 0; u < 2; ++u)
             for (int v = 0; v < 2; ++v) {
                 const int p = p0 + u, q = q0 + v;
                 if (p < bl && q < a.bout) {
-                    a.partials[(int64_t)blockIdx.x * kPartialStride + p * 16 + q] =
-                        (blockDim.x > 64) ? G[u][v] + red[u * 2 + v][blk] : G[u][v];
-                    if (a.gram == 4)
-                        a.partials[(int64_t)blockIdx.x * kPartialStride + 256 + p * 16 + q] =
-                            (blockDim.x > 64) ? G2[u][v] + red[4 + u * 2 + v][blk] : G2[u][v];
+                    zd g = red[(u * 2 + v) * 64 + blk], g2 = red[(4 + u * 2 + v) * 64 + blk];
+                    for (int h = 1; h < 4; ++h) {
+                        g = g + red[(h * 8 + u * 2 + v) * 64 + blk];
+                        g2 = g2 + red[(h * 8 + 4 + u * 2 + v) * 64 + blk];
+                    }
+                    a.partials[(int64_t)blockIdx.x * kPartialStride + p * 16 + q] = g;
+                    if (a.gram == 4) a.partials[(int64_t)blockIdx.x * kPartialStride + 256 + p * 16 + q] = g2;
                 }
             }
     }
@@ -414,7 +443,7 @@ void ts_launch(const TsArgs &a, int w, int nwg, hipStream_t st) {
         case 7: ts_launch_k<R, 7>(a, nwg, st); break;
         case 8: ts_launch_k<R, 8>(a, nwg, st); break;
         default:
-            hipLaunchKernelGGL(ts_lds_kernel<R>, dim3(nwg), dim3(TileRows<R>::value), 0, st, a);
+            hipLaunchKernelGGL(ts_lds_kernel<R>, dim3(nwg), dim3(kLdsThreads), 0, st, a);
             break;
     }
 }
