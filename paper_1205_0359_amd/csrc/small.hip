@@ -534,11 +534,15 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepRe
                                                           const zd *__restrict__ alpha_raw,
                                                           const zd *__restrict__ G, double tau_W,
                                                           const zd *__restrict__ Gref) {
-    // the inputs go to LDS with every lane, the sequential factorisation
-    // then runs on LDS only (thread 0), and the results leave in parallel
+    // The inputs go to LDS with every lane.  The factorisation runs column by
+    // column: thread 0 forms the remainder d of column k and decides, and
+    // when k is kept the other lanes form its row of R for the columns after
+    // k at once (each entry by the same formula, in the same order, as a
+    // column-by-column solve); the inverse columns and the conditioning terms
+    // then run one per lane.
     __shared__ zd Gs[256], R[256], C1s[256];
-    __shared__ double nrm[2], gref[16];
-    __shared__ int piv[16], nks, skip;
+    __shared__ double nrm[2], gref[16], dterm[16], thr_s;
+    __shared__ int piv[16], nks, skip, keepk, unresolved;
     const int t = threadIdx.x;
     const int b = st->b, bp = st->bp;
     (void)alpha_raw;
@@ -567,55 +571,70 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepRe
         test = fmax(test, sqrt(nrm[0]));
         test = fmax(test, sqrt(nrm[1]));
         st->test = test;
-        const double thr = tau_W * test;
-        int nk = 0, unresolved = 0;
-        for (int k = 0; k < b; ++k) {
+        thr_s = tau_W * test;
+        nks = 0;
+        unresolved = 0;
+    }
+    __syncthreads();
+    const double thr = thr_s;
+    for (int k = 0; k < b; ++k) {
+        if (t == 0) {
+            const int nk = nks;
             const double gkk = fmax(Gs[k * 16 + k].x, gref[k]);  // scale of the rounding of d
             double d = Gs[k * 16 + k].x;
-            for (int r = 0; r < nk; ++r) {
-                zd v = Gs[piv[r] * 16 + k];
-                for (int q = 0; q < r; ++q) v = v - conj(R[q * 16 + piv[r]]) * R[q * 16 + k];
-                v = zdivr(v, R[r * 16 + piv[r]].x);
-                R[r * 16 + k] = v;
-                d -= norm2(v);
-            }
+            for (int r = 0; r < nk; ++r) d -= norm2(R[r * 16 + k]);
             // a remainder at the rounding level of G_kk decides nothing when
             // the threshold lies below that level
             if (d <= kResolve * gkk && kResolve * gkk > thr * thr) unresolved = 1;
+            keepk = 0;
             if (d > thr * thr) {
                 // a kept column: new row nk of R (dropped columns keep the
-                // entries computed for the rows above)
-                for (int c = 0; c < b; ++c) R[nk * 16 + c] = mk<double>(0, 0);
+                // entries of the rows above)
                 R[nk * 16 + k] = mk<double>(sqrt(d), 0.0);
                 piv[nk] = k;
-                ++nk;
+                nks = nk + 1;
+                keepk = 1;
             }
         }
-        // R has nk rows; zero the entries left of each pivot
-        for (int r = 0; r < nk; ++r)
-            for (int c = 0; c < piv[r]; ++c) R[r * 16 + c] = mk<double>(0, 0);
-        // C1 = E_K R_KK^{-1}: R_KK (nk x nk) is R restricted to the pivot columns
-        for (int q = 0; q < nk; ++q) {
-            // column q of R_KK^{-1}: solve R_KK x = e_q (upper triangular)
-            zd x[16];
-            for (int r = nk - 1; r >= 0; --r) {
-                zd v = (r == q) ? mk<double>(1, 0) : mk<double>(0, 0);
-                for (int c = r + 1; c < nk; ++c) v = v - R[r * 16 + piv[c]] * x[c];
-                x[r] = zdivr(v, R[r * 16 + piv[r]].x);
+        __syncthreads();
+        if (keepk) {
+            const int r = nks - 1, c = k + 1 + t;
+            if (c < b) {
+                zd v = Gs[k * 16 + c];
+                for (int q = 0; q < r; ++q) v = v - conj(R[q * 16 + k]) * R[q * 16 + c];
+                R[r * 16 + c] = zdivr(v, R[r * 16 + k].x);
             }
-            for (int r = 0; r < nk; ++r) C1s[piv[r] * 16 + q] = x[r];
         }
-        // condition of the kept columns scaled to unit norm, Rs = R_KK D^{-1}:
-        // ||Rs||_F^2 = nk and Rs^{-1} = D R_KK^{-1} (rows scaled by the norms)
+        __syncthreads();
+    }
+    const int nk = nks;
+    // C1 = E_K R_KK^{-1}: R_KK (nk x nk) is R restricted to the pivot
+    // columns; column q of R_KK^{-1} solves R_KK x = e_q (upper triangular)
+    if (t < nk) {
+        const int q = t;
+        zd x[16];
+        for (int r = nk - 1; r >= 0; --r) {
+            zd v = (r == q) ? mk<double>(1, 0) : mk<double>(0, 0);
+            for (int c = r + 1; c < nk; ++c) v = v - R[r * 16 + piv[c]] * x[c];
+            x[r] = zdivr(v, R[r * 16 + piv[r]].x);
+        }
+        for (int r = 0; r < nk; ++r) C1s[piv[r] * 16 + q] = x[r];
+    }
+    __syncthreads();
+    // condition of the kept columns scaled to unit norm, Rs = R_KK D^{-1}:
+    // ||Rs||_F^2 = nk and Rs^{-1} = D R_KK^{-1} (rows scaled by the norms)
+    if (t < nk) {
+        const int c = t;
+        double d2 = 0.0;
+        for (int r = 0; r <= c; ++r) d2 += norm2(R[r * 16 + piv[c]]);
+        double row2 = 0.0;
+        for (int q = 0; q < nk; ++q) row2 += norm2(C1s[piv[c] * 16 + q]);
+        dterm[c] = d2 * row2;
+    }
+    __syncthreads();
+    if (t == 0) {
         double inv2 = 0.0;
-        for (int c = 0; c < nk; ++c) {
-            double d2 = 0.0;
-            for (int r = 0; r <= c; ++r) d2 += norm2(R[r * 16 + piv[c]]);
-            double row2 = 0.0;
-            for (int q = 0; q < nk; ++q) row2 += norm2(C1s[piv[c] * 16 + q]);
-            inv2 += d2 * row2;
-        }
-        nks = nk;
+        for (int c = 0; c < nk; ++c) inv2 += dterm[c];
         skip = (nk > 0 && nk * inv2 <= 16.0 * 16.0) ? 1 : 0;
         st->redo = unresolved;
         if (unresolved) {
@@ -624,7 +643,6 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(SmallState *st, StepRe
         }
     }
     __syncthreads();
-    const int nk = nks;
     for (int e = t; e < 256; e += 64) {
         const int r = e / 16;
         if (r < nk) st->R1[e] = R[e];
@@ -784,24 +802,22 @@ __global__ __launch_bounds__(256) void finish_kernel(SmallState *st, StepReport 
         BN[r * 16 + c] = v;
     }
     __syncthreads();
-    // per shift: C_j = -beta_{i+1} M_j = Z_{j,i+1}; estimates; freezing
-    for (int js = t; js < nact; js += 256) {
+    // per shift and column l: column l of C_j = -beta_{i+1} M_j = Z_{j,i+1};
+    // its estimate; freezing (each thread clears only its own bit)
+    for (int w = t; w < nact * m; w += 256) {
+        const int js = w / m, l = w - js * m;
         const int j = list[js];
-        uint32_t mask = rep->colmask[j];
-        for (int l = 0; l < m; ++l) {
-            double nrm = 0.0;
-            for (int r = 0; r < nk; ++r) {
-                zd v = mk<double>(0, 0);
-                for (int q = 0; q < b; ++q) v = v - BN[r * 16 + q] * st->M[j][q * 16 + l];
-                st->Z[j][r * 16 + l] = v;
-                nrm += norm2(v);
-            }
-            const double bn = st->bnorm[st->colmap[j][l]];
-            const double e = (bn > 0.0) ? sqrt(nrm) / bn : 0.0;
-            rep->est[j][l] = e;
-            if (freeze && ((mask >> l) & 1u) && e <= tol) mask &= ~(1u << l);
+        double nrm = 0.0;
+        for (int r = 0; r < nk; ++r) {
+            zd v = mk<double>(0, 0);
+            for (int q = 0; q < b; ++q) v = v - BN[r * 16 + q] * st->M[j][q * 16 + l];
+            st->Z[j][r * 16 + l] = v;
+            nrm += norm2(v);
         }
-        rep->colmask[j] = mask;
+        const double bn = st->bnorm[st->colmap[j][l]];
+        const double e = (bn > 0.0) ? sqrt(nrm) / bn : 0.0;
+        rep->est[j][l] = e;
+        if (freeze && ((rep->colmask[j] >> l) & 1u) && e <= tol) atomicAnd(&rep->colmask[j], ~(1u << l));
     }
     __syncthreads();
     for (int e = t; e < 256; e += 256) {
